@@ -1,0 +1,239 @@
+"""Throughput of the batched IFNSO path on one MI355X.
+
+Workload (the metric's configuration): the weight-gradient set of a synthetic 32-layer
+transformer, hidden size 4096 with GQA and SwiGLU -- per layer Wq, Wo 4096x4096, Wk, Wv
+1024x4096, gate, up 14336x4096, down 4096x14336 (224 matrices); bfloat16 entries
+N(0, 0.02^2) plus a rank-16 component of Frobenius norm 0.5, generated on the device from
+the seeded counter generator. Exponents {0,1,2,4,8,16}, fixed coefficients "gform_v1".
+One step = one batched call over all 224 matrices (Gram, 4 squarings, product).
+
+Prints one JSON line. `value` is matrices/s over the timed region, with the inputs
+already resident in HBM. The roofline entry is for the kernel with the largest time per
+step, timed with HIP events recorded around each stage inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
+PEAK_F32_TFLOPS = 157.3    # MI355X dense fp32 MFMA
+
+
+def _hip():
+    lib = ctypes.CDLL("libamdhip64.so")
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def make_d3(torch, dev, layers=32):
+    from workloads import configs, gen
+    Ms = []
+    for l in range(layers):
+        for idx, (_, r, c) in enumerate(configs.LAYER_SHAPES):
+            m = gen.lowrank_plus_noise_torch(r, c, configs.d3_seed(l, idx), device=dev)
+            Ms.append(gen.round_to_bf16_torch(m))
+            del m
+    torch.cuda.synchronize()
+    return Ms
+
+
+def stage_flops(shapes, J):
+    """Algorithmic flops per launch: Gram h^2 w (symmetric), squaring h^3 (symmetric),
+    product 2 h^2 w, summed over the problems of the launch."""
+    g = sum(min(r, c) ** 2 * max(r, c) for r, c in shapes)
+    s = sum(min(r, c) ** 3 for r, c in shapes)
+    p = sum(2 * min(r, c) ** 2 * max(r, c) for r, c in shapes)
+    return {"gram": float(g), "square": float(s), "product": float(p), "step": float(g + J * s + p)}
+
+
+def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
+    """The FP64 oracle on a bounded sample (layer 0: its 7 matrices), on the host cores."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    outs = [oracle.ifnso(M, exps, coeffs) for M in Ms_host]
+    dt = time.perf_counter() - t0
+    rel = []
+    for Yo, Yd in zip(outs, Ys_dev):
+        rel.append(float(np.linalg.norm(Yd - Yo) / np.linalg.norm(Yo)))
+    orth = [oracle.orth_error(Yo) / math.sqrt(min(Yo.shape)) for Yo in outs]
+    return {"value": len(Ms_host) / dt, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"layer 0 of the set ({len(Ms_host)} matrices: 2x 4096x4096, 2x 1024x4096, "
+                      f"2x 14336x4096, 1x 4096x14336), float64 numpy, {dt:.1f} s"}, rel, orth
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layers", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
+    ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the 224 matrices are independent and would be sharded by matrix across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hip = _hip()
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    exps, coeffs = configs.load_coeffs("gform_v1")
+    t0 = time.perf_counter()
+    Ms = make_d3(torch, dev, args.layers)
+    shapes = [tuple(m.shape) for m in Ms]
+    n = len(Ms)
+    log(f"generated {n} matrices in {time.perf_counter() - t0:.1f} s")
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+    stream = torch.cuda.current_stream()
+    J = plan.num_stages - 2
+    fl = stage_flops(shapes, J)
+
+    for _ in range(args.warmup):
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # graph replay (no stage events)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(args.warmup):
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg0) / max(args.warmup, 1) * 1e3
+
+    # the timed region: K steps, HIP events before every stage
+    ns = plan.num_stages
+    evs = []
+    for _ in range(args.steps):
+        row = []
+        for _ in range(ns + 1):
+            e = ctypes.c_void_p()
+            assert hip.hipEventCreate(ctypes.byref(e)) == 0
+            row.append(e.value)
+        evs.append(row)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.stage_events(evs[k])
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {elapsed:.3f} s")
+    stage_ms = np.zeros((args.steps, ns))
+    f = ctypes.c_float()
+    for k in range(args.steps):
+        for i in range(ns):
+            assert hip.hipEventElapsedTime(ctypes.byref(f), evs[k][i], evs[k][i + 1]) == 0
+            stage_ms[k, i] = f.value
+    for row in evs:
+        for e in row:
+            hip.hipEventDestroy(e)
+    per = stage_ms.mean(axis=0)
+    kern = {"gram": (per[0], 1, fl["gram"]), "square": (per[1:1 + J].sum(), J, fl["square"]),
+            "product": (per[-1], 1, fl["product"])}
+    dom = max(kern, key=lambda k: kern[k][0])
+    dur_ms = kern[dom][0] / kern[dom][1]
+    achieved = kern[dom][2] / (dur_ms * 1e-3) / 1e12
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n * args.steps / elapsed
+    step_tflops = fl["step"] / (ms_per_step * 1e-3) / 1e12
+
+    extra = {"graph_ms_per_step": round(graph_ms, 3),
+             "stage_ms": {"gram": round(per[0], 3), "square_per_level": [round(x, 3) for x in per[1:1 + J]],
+                          "product": round(per[-1], 3)},
+             "algorithmic_tflop_per_step": round(fl["step"] / 1e12, 2),
+             "mfma_util": round(step_tflops / PEAK_BF16_TFLOPS, 4)}
+
+    # orthogonality (float64 on the device), not timed
+    if not args.no_check:
+        out = torch.empty(n, dtype=torch.float64, device=dev)
+        ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        ifn.orth_error(Ys, out, ows)
+        oe = out.cpu().numpy() / np.sqrt([min(s) for s in shapes])
+        extra["orth_err_over_sqrt_h"] = {"mean": float(oe.mean()), "max": float(oe.max())}
+
+    # plain float32 path on the same matrices (two steps), for the speed-up and error targets
+    if not args.no_f32:
+        M32 = [m.float() for m in Ms]
+        Y32 = [torch.empty_like(m) for m in M32]
+        del ws
+        plan32 = ifn.Plan(exps, coeffs, shapes, compute="f32")
+        ws32 = torch.empty(plan32.workspace_bytes, dtype=torch.uint8, device=dev)
+        plan32.orthogonalize_batched(M32, Y32, ws32)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter()
+        plan32.orthogonalize_batched(M32, Y32, ws32)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t32
+        extra["f32_path"] = {"matrices_per_s": n / t32, "speedup_bf16_over_f32": value / (n / t32)}
+        if not args.no_check:
+            out = torch.empty(n, dtype=torch.float64, device=dev)
+            ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+            ifn.orth_error(Y32, out, ows)
+            oe32 = out.cpu().numpy() / np.sqrt([min(s) for s in shapes])
+            extra["f32_path"]["orth_err_over_sqrt_h_mean"] = float(oe32.mean())
+            rel = []
+            for a, b in zip(Ys, Y32):
+                rel.append(float(torch.linalg.norm(a.float() - b) / torch.linalg.norm(b)))
+            extra["f32_path"]["bf16_vs_f32_rel_max"] = max(rel)
+        del M32, Y32, ws32, plan32
+
+    cpu = None
+    if not args.no_cpu:
+        idx = list(range(7))
+        Mh = [Ms[i].float().cpu().numpy().astype(np.float64) for i in idx]
+        Yd = [Ys[i].float().cpu().numpy().astype(np.float64) for i in idx]
+        log("running the CPU oracle on layer 0 ...")
+        cpu, rel, orth = cpu_baseline(Mh, exps, coeffs, Yd)
+        extra["parity_layer0_rel_max"] = max(rel)
+        extra["oracle_orth_err_over_sqrt_h_layer0_mean"] = float(np.mean(orth))
+
+    line = {
+        "metric": "matrices/s + MFMA util on 32-layer grad set; ||XX^T-I|| vs FP64 oracle",
+        "value": round(value, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices, hidden 4096 GQA SwiGLU, "
+                               "bf16 N(0,0.02^2) + rank-16 (norm 0.5)",
+                   "matrices": n, "exponents": list(exps), "coeffs": "gform_v1", "compute": "bf16",
+                   "parallelism": "single GPU, one grouped launch per stage"},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "avg_launch_ms": round(dur_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

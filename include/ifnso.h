@@ -1,0 +1,172 @@
+/*
+ * ifnso.h -- C ABI of libifnso, an MI355X (gfx950) implementation of IFNSO,
+ * the iteration-free Newton-Schulz orthogonalisation of Hu et al.
+ * ("IFNSO: Iteration-Free Newton-Schulz Orthogonalization", arXiv 2602.02500).
+ *
+ * What it computes (for every problem of a plan):
+ *   A = M if rows <= cols else M^T                 transposition rule, Sec. 1 and Algorithm 1
+ *   X = A / s                                      s = ||A||_F (Eq. (constraint)),
+ *                                                  s = ||A A^T||_F^(1/2) (Eq. (new_scale_formula)),
+ *                                                  or s = 1
+ *   B = X X^T            (IFNSO_BASIS_GRAM,        Eq. (new_unified_formula_0))
+ *   B = I - X X^T        (IFNSO_BASIS_COMPLEMENT,  Eq. (after_matrix_formula); with the
+ *                                                  Gram-Frobenius scale B is T_1 of Sec. 2.4)
+ *   B^(2^j) = (B^(2^(j-1)))^2                      repeated squaring, Sec. 2.4
+ *   Y = (sum_k c_k B^(e_k)) X, e_k in {0} u {2^j}  Eq. (generalized_matrix_formula), Algorithm 1
+ * and returns Y in M's orientation (Y^T when M was transposed) and layout.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are row-major with a leading dimension (elements between the starts of
+ *    consecutive rows), ld >= cols.
+ *  - M, Y and the workspace are device pointers owned by the caller. The library never
+ *    allocates inside a compute call and never synchronises the host; work is enqueued
+ *    on the caller's HIP stream (passed as void *, a hipStream_t; NULL = default
+ *    stream). Kernel-side faults surface at the caller's next synchronisation.
+ *  - Errors are returned as ifnso_status; ifnso_last_error() gives a thread-local
+ *    message. Argument checks happen before any HIP call, so an error return means
+ *    that nothing was enqueued.
+ *  - A zero input matrix gives Y = 0 (no epsilon is added to any normalisation).
+ *  - Concurrent calls that share a workspace race; give each in-flight call its own.
+ */
+#ifndef IFNSO_H
+#define IFNSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IFNSO_OK = 0,
+  IFNSO_ERR_INVALID_ARGUMENT = 1,   /* bad pointer, size, descriptor, or plan mismatch */
+  IFNSO_ERR_UNSUPPORTED = 2,        /* a valid combination this build does not implement */
+  IFNSO_ERR_WORKSPACE_TOO_SMALL = 3,
+  IFNSO_ERR_HIP = 4,                /* a HIP runtime call failed; see ifnso_last_error() */
+  IFNSO_ERR_INTERNAL = 5
+} ifnso_status;
+
+/* element type of M and Y in memory */
+typedef enum { IFNSO_F32 = 0, IFNSO_BF16 = 1 } ifnso_dtype;
+
+/* operand type of the matrix products (accumulation is always float32):
+ *  F32   float32 operands on the FP32 matrix cores (the plain path; M must be F32)
+ *  BF16  bfloat16 operands (M must be BF16)
+ *  FP8_E4M3  OCP e4m3 operands for the Gram and the squarings, with one power-of-two
+ *        scale per matrix from its absolute maximum; the final product uses bfloat16
+ *        (M must be BF16) */
+typedef enum { IFNSO_COMPUTE_F32 = 0, IFNSO_COMPUTE_BF16 = 1, IFNSO_COMPUTE_FP8_E4M3 = 2 } ifnso_compute;
+
+typedef enum { IFNSO_BASIS_GRAM = 0, IFNSO_BASIS_COMPLEMENT = 1 } ifnso_basis;
+
+typedef enum {
+  IFNSO_NORM_FROBENIUS = 0,       /* s = ||A||_F                 Eq. (constraint)          */
+  IFNSO_NORM_GRAM_FROBENIUS = 1,  /* s = ||A A^T||_F^(1/2)        Eq. (new_scale_formula)   */
+  IFNSO_NORM_NONE = 2             /* s = 1                                                  */
+} ifnso_norm;
+
+/* FIXED: the descriptor's coefficients for every problem.
+ * LEARNED: reserved for per-problem coefficients predicted on the device; plans that
+ *   request it fail with IFNSO_ERR_UNSUPPORTED in this build. */
+typedef enum { IFNSO_COEFF_FIXED = 0, IFNSO_COEFF_LEARNED = 1 } ifnso_coeff_mode;
+
+enum {
+  IFNSO_FLAG_ENFORCE_SUM_ONE = 1  /* reject coefficients with |sum c - 1| > 1e-12 */
+};
+
+/* Polynomial descriptor. Arrays are read during ifnso_plan() only (copied). */
+typedef struct {
+  int32_t num_terms;          /* K, 1..16 */
+  const int32_t *exponents;   /* [K] strictly increasing; each 0 or 2^j with j <= 15 */
+  const double *coeffs;       /* [K] finite */
+  int32_t basis;              /* ifnso_basis */
+  int32_t norm;               /* ifnso_norm */
+  int32_t compute;            /* ifnso_compute */
+  int32_t coeff_mode;         /* ifnso_coeff_mode */
+  const float *mlp_params;    /* LEARNED only (reserved) */
+  size_t mlp_params_len;
+  uint32_t flags;             /* IFNSO_FLAG_* */
+} ifnso_poly_desc;
+
+typedef struct ifnso_plan_s *ifnso_plan_t;
+
+/* Creates a plan for num_problems matrices of shapes rows[i] x cols[i] (host arrays).
+ * The plan validates the descriptor, fixes the orientation of each problem, builds the
+ * tile schedules, uploads them and the coefficients to `device`, and sizes the
+ * workspace. It owns those device buffers until ifnso_plan_destroy().
+ * Errors: INVALID_ARGUMENT (null pointers, num_problems < 1, a dimension < 1,
+ * bad exponents/coefficients/enums, LEARNED without a parameter blob of the right
+ * length), UNSUPPORTED (dtype/compute combination not built), HIP. */
+ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_problems, const int64_t *rows,
+                        const int64_t *cols, int32_t in_dtype, int32_t out_dtype, int32_t device,
+                        ifnso_plan_t *out_plan);
+
+/* Bytes of device workspace one call of this plan needs (256-byte aligned base). */
+ifnso_status ifnso_plan_workspace_bytes(ifnso_plan_t plan, size_t *bytes);
+
+/* Frees the plan and its device buffers. The caller must make sure no enqueued call of
+ * the plan is still running. NULL is accepted. */
+ifnso_status ifnso_plan_destroy(ifnso_plan_t plan);
+
+/* Orthogonalises the single problem of a plan made with num_problems == 1.
+ * M: device, rows x cols, leading dimension ldm; Y: device, same shape, ldy.
+ * Y must not overlap M. Errors: INVALID_ARGUMENT (plan has more than one problem, null
+ * or overlapping pointers, ld < cols), WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_orthogonalize(ifnso_plan_t plan, const void *M, int64_t ldm, void *Y, int64_t ldy,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Orthogonalises every problem of the plan in one grouped schedule: one persistent
+ * launch per stage (Gram, each squaring level, product) over the tiles of all
+ * problems, replayed as a HIP graph. M, ldm, Y, ldy are host arrays of length
+ * num_problems holding device pointers and leading dimensions. */
+ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M, const int64_t *ldm,
+                                         void *const *Y, const int64_t *ldy, void *workspace,
+                                         size_t workspace_bytes, void *stream);
+
+/* Number of kernel launches (stages) of one call of this plan: the Gram, one per
+ * squaring level, and the product (J + 2 where 2^J is the largest exponent), or a
+ * negative status for a NULL plan. */
+int32_t ifnso_plan_num_stages(ifnso_plan_t plan);
+
+/* Measurement hook: the next ifnso_orthogonalize / ifnso_orthogonalize_batched call of
+ * this plan records events[i] (hipEvent_t handles created by the caller with timing
+ * enabled) on its stream just before stage i, and events[num_stages] after the last
+ * stage; that call enqueues its stages directly instead of replaying the graph. count must
+ * equal ifnso_plan_num_stages(plan) + 1; count 0 cancels a pending request.
+ * Errors: INVALID_ARGUMENT. */
+ifnso_status ifnso_plan_stage_events(ifnso_plan_t plan, void *const *events, int32_t count);
+
+/* Classical Newton-Schulz with one odd quintic per step, Eq. (iteration_jordan):
+ *   X_0 = A / ||A||_F,  X_{k+1} = a X_k + (b G_k + c G_k^2) X_k,  G_k = X_k X_k^T,
+ * for `steps` steps (abc = {a, b, c}; {1.5, -0.5, 0} is the cubic of
+ * Eq. (one_iteration_matrix)). M: device rows x cols (ldm), dtype `dtype` (F32 with
+ * compute F32, BF16 with compute BF16); Y: device, same shape and dtype, ldy.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
+                                void *Y, int64_t ldy, int32_t steps, const double abc[3], int32_t compute,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for ifnso_classical_ns with these dimensions (0 on bad arguments). */
+size_t ifnso_classical_ns_workspace_bytes(int64_t rows, int64_t cols, int32_t compute);
+
+/* Orthogonality error of the Experiment section, e = ||Z Z^T - I||_F with Z = Y in the
+ * h <= w orientation, computed on the device in float64 for `count` matrices (host arrays
+ * of device pointers, shapes and leading dimensions; one dtype for all). Writes `count`
+ * doubles to the device array `out`. The device workspace must hold
+ * ifnso_orth_error_workspace_bytes(count) bytes (256-byte aligned). Evaluation helper,
+ * not part of the timed path: it synchronises `stream` before returning.
+ * Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_orth_error(int32_t count, const void *const *Y, const int64_t *rows, const int64_t *cols,
+                              const int64_t *ldy, int32_t dtype, double *out, void *workspace,
+                              size_t workspace_bytes, void *stream);
+size_t ifnso_orth_error_workspace_bytes(int32_t count);
+
+/* Thread-local message describing the last error returned on this thread. */
+const char *ifnso_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFNSO_H */

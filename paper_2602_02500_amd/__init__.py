@@ -1,0 +1,225 @@
+"""Python binding of libifnso (IFNSO on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the library's HIP
+kernels. The functions take torch tensors for device memory and use torch's current
+HIP stream; the C ABI itself (include/ifnso.h) takes raw device pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+__all__ = [
+    "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes",
+    "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
+    "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
+    "header_functions", "STATUS", "orth_error_workspace_bytes",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libifnso.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "ifnso.h")
+
+F32, BF16 = 0, 1
+COMPUTE_F32, COMPUTE_BF16, COMPUTE_FP8 = 0, 1, 2
+BASIS_GRAM, BASIS_COMPLEMENT = 0, 1
+NORM_FROBENIUS, NORM_GRAM_FROBENIUS, NORM_NONE = 0, 1, 2
+COEFF_FIXED, COEFF_LEARNED = 0, 1
+FLAG_ENFORCE_SUM_ONE = 1
+STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "WORKSPACE_TOO_SMALL", 4: "HIP", 5: "INTERNAL"}
+
+_BASIS = {"gram": BASIS_GRAM, "complement": BASIS_COMPLEMENT}
+_NORM = {"frobenius": NORM_FROBENIUS, "gram_frobenius": NORM_GRAM_FROBENIUS, "none": NORM_NONE}
+_COMPUTE = {"f32": COMPUTE_F32, "bf16": COMPUTE_BF16, "fp8": COMPUTE_FP8}
+
+
+class IfnsoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PolyDesc(ctypes.Structure):
+    _fields_ = [
+        ("num_terms", ctypes.c_int32),
+        ("exponents", ctypes.POINTER(ctypes.c_int32)),
+        ("coeffs", ctypes.POINTER(ctypes.c_double)),
+        ("basis", ctypes.c_int32),
+        ("norm", ctypes.c_int32),
+        ("compute", ctypes.c_int32),
+        ("coeff_mode", ctypes.c_int32),
+        ("mlp_params", ctypes.POINTER(ctypes.c_float)),
+        ("mlp_params_len", ctypes.c_size_t),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the in-tree libifnso.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_02500_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    L.ifnso_plan.argtypes = [ctypes.POINTER(PolyDesc), i32, P64, P64, i32, i32, i32, ctypes.POINTER(vp)]
+    L.ifnso_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ifnso_plan_destroy.argtypes = [vp]
+    L.ifnso_orthogonalize.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp]
+    L.ifnso_orthogonalize_batched.argtypes = [vp, ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64, vp, sz, vp]
+    L.ifnso_classical_ns.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, ctypes.POINTER(ctypes.c_double), i32,
+                                     vp, sz, vp]
+    L.ifnso_classical_ns_workspace_bytes.argtypes = [i64, i64, i32]
+    L.ifnso_classical_ns_workspace_bytes.restype = sz
+    L.ifnso_orth_error.argtypes = [i32, ctypes.POINTER(vp), P64, P64, P64, i32, vp, vp, sz, vp]
+    L.ifnso_orth_error_workspace_bytes.argtypes = [i32]
+    L.ifnso_orth_error_workspace_bytes.restype = sz
+    L.ifnso_plan_num_stages.argtypes = [vp]
+    L.ifnso_plan_num_stages.restype = i32
+    L.ifnso_plan_stage_events.argtypes = [vp, ctypes.POINTER(vp), i32]
+    L.ifnso_plan_stage_events.restype = ctypes.c_int
+    L.ifnso_last_error.restype = ctypes.c_char_p
+    for name in ("ifnso_plan", "ifnso_plan_workspace_bytes", "ifnso_plan_destroy", "ifnso_orthogonalize",
+                 "ifnso_orthogonalize_batched", "ifnso_classical_ns", "ifnso_orth_error"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/ifnso.h."""
+    src = open(HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ifnso_[a-z0-9_]+)\s*\(", src)))
+
+
+def _check(status: int):
+    if status != 0:
+        raise IfnsoError(status, load().ifnso_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t) -> int:
+    return t if isinstance(t, int) else t.data_ptr()
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class Plan:
+    """A plan over problems of the given (rows, cols) shapes (ifnso_plan)."""
+
+    def __init__(self, exponents: Sequence[int], coeffs: Sequence[float], shapes, basis="gram",
+                 norm="frobenius", compute="bf16", in_dtype=None, out_dtype=None, device: int = 0,
+                 flags: int = 0):
+        L = load()
+        self._L = L
+        K = len(exponents)
+        self._e = (ctypes.c_int32 * K)(*[int(x) for x in exponents])
+        self._c = (ctypes.c_double * K)(*[float(x) for x in coeffs])
+        comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+        d = PolyDesc(K, self._e, self._c, _BASIS[basis] if isinstance(basis, str) else int(basis),
+                     _NORM[norm] if isinstance(norm, str) else int(norm), comp, COEFF_FIXED, None, 0, int(flags))
+        self.shapes = [(int(r), int(c)) for r, c in shapes]
+        n = len(self.shapes)
+        rows = (ctypes.c_int64 * n)(*[r for r, _ in self.shapes])
+        cols = (ctypes.c_int64 * n)(*[c for _, c in self.shapes])
+        if in_dtype is None:
+            in_dtype = F32 if comp == COMPUTE_F32 else BF16
+        if out_dtype is None:
+            out_dtype = in_dtype
+        self.in_dtype, self.out_dtype = int(in_dtype), int(out_dtype)
+        h = ctypes.c_void_p()
+        _check(L.ifnso_plan(ctypes.byref(d), n, rows, cols, self.in_dtype, self.out_dtype, int(device),
+                            ctypes.byref(h)))
+        self._h = h
+        b = ctypes.c_size_t()
+        _check(L.ifnso_plan_workspace_bytes(h, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+
+    def orthogonalize(self, M, Y, workspace, stream=None):
+        ws = _ptr(workspace)
+        nb = self.workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
+        _check(self._L.ifnso_orthogonalize(self._h, _ptr(M), int(M.stride(0)), _ptr(Y), int(Y.stride(0)), ws, nb,
+                                           _stream(stream)))
+
+    def orthogonalize_batched(self, Ms, Ys, workspace, stream=None):
+        n = len(Ms)
+        mp = (ctypes.c_void_p * n)(*[_ptr(m) for m in Ms])
+        yp = (ctypes.c_void_p * n)(*[_ptr(y) for y in Ys])
+        ldm = (ctypes.c_int64 * n)(*[int(m.stride(0)) for m in Ms])
+        ldy = (ctypes.c_int64 * n)(*[int(y.stride(0)) for y in Ys])
+        nb = self.workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
+        _check(self._L.ifnso_orthogonalize_batched(self._h, mp, ldm, yp, ldy, _ptr(workspace), nb, _stream(stream)))
+
+    @property
+    def num_stages(self) -> int:
+        return int(self._L.ifnso_plan_num_stages(self._h))
+
+    def stage_events(self, events):
+        """Events (raw hipEvent_t handles) for the next call: one before each stage and one after."""
+        n = len(events)
+        arr = (ctypes.c_void_p * max(n, 1))(*[int(e) for e in events])
+        _check(self._L.ifnso_plan_stage_events(self._h, arr, n))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            self._L.ifnso_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def classical_ns_workspace_bytes(rows: int, cols: int, compute="bf16") -> int:
+    comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    return int(load().ifnso_classical_ns_workspace_bytes(rows, cols, comp))
+
+
+def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=None):
+    L = load()
+    comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    rows, cols = M.shape
+    abc_c = (ctypes.c_double * 3)(*[float(x) for x in abc])
+    nb = workspace.numel() * workspace.element_size()
+    _check(L.ifnso_classical_ns(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
+                                int(steps), abc_c, comp, _ptr(workspace), nb, _stream(stream)))
+
+
+def orth_error(Ys, out, workspace, stream=None):
+    """float64 ||Z Z^T - I||_F of each matrix (Z in the h <= w orientation) into `out`."""
+    L = load()
+    n = len(Ys)
+    yp = (ctypes.c_void_p * n)(*[_ptr(y) for y in Ys])
+    rows = (ctypes.c_int64 * n)(*[y.shape[0] for y in Ys])
+    cols = (ctypes.c_int64 * n)(*[y.shape[1] for y in Ys])
+    ld = (ctypes.c_int64 * n)(*[int(y.stride(0)) for y in Ys])
+    nb = workspace.numel() * workspace.element_size()
+    _check(L.ifnso_orth_error(n, yp, rows, cols, ld, _dtype_code(Ys[0]), _ptr(out), _ptr(workspace), nb,
+                              _stream(stream)))
+
+
+def orth_error_workspace_bytes(count: int) -> int:
+    return int(load().ifnso_orth_error_workspace_bytes(int(count)))

@@ -1,0 +1,65 @@
+// Structures shared by the host scheduler and the device kernels of libifnso.
+#pragma once
+#include <stdint.h>
+
+namespace ifnso {
+
+constexpr int kMaxTerms = 16;
+constexpr int kSlots = 17;       // coefficient slot 0: exponent 0; slot 1 + j: exponent 2^j
+constexpr int kMaxLevels = 18;   // levels 1..17 (level l holds B^(2^(l-1)))
+constexpr int kThreads = 256;    // every GEMM workgroup: 4 waves of 64
+constexpr int kFeat = 8;         // learned mode: traces tr(G^(2^j)), j = 0..7
+
+enum Basis : int32_t { kGram = 0, kComplement = 1 };
+enum Norm : int32_t { kFrob = 0, kGramFrob = 1, kNone = 2 };
+enum OpType : int32_t { kOpF32 = 0, kOpBF16 = 1, kOpFP8 = 2 };
+
+// One problem of a call, rebuilt by the host for every call (pointers move between calls).
+struct ProbDev {
+  const void *M;       // input, rows x cols, row-major, leading dimension ldm
+  void *Y;             // output, same shape and layout as M, leading dimension ldy
+  int64_t ldm, ldy;
+  int32_t h, w;        // h = min(rows, cols), w = max(rows, cols)
+  int32_t trans;       // 1 when rows > cols (A = M^T)
+  int32_t hp;          // h padded to the tile grid; leading dimension of every h x h buffer
+  int32_t nt;          // tiles along h for the symmetric stages (hp / tile)
+  int32_t vecM;        // M and Y allow 16-byte vector access
+  void *opnd[2];       // h x h operand ping-pong (operand type), full symmetric
+  float *accf;         // h x h float32: Gram (upper tiles), then the running sum P
+  float *df[2];        // complement basis: float32 D levels (upper tiles)
+  double *norm_part;   // [nt]         sum of squares of A per row block (diagonal Gram tiles)
+  double *lvl_part;    // [levels][nt*nt] sum of squares of the stored level, upper tiles
+  double *diag_part;   // [levels][nt]    trace partials of the stored level
+  double *coef;        // [kSlots] coefficients of this problem (slot layout)
+  double *stats;       // [IFNSO_STATS_PER_PROBLEM]
+  void *xbuf[2];       // classical NS: h x w iterates (wide orientation), leading dim ldx
+  int64_t ldx;
+  float *lvls;         // learned mode: float32 copies of each stored level (upper tiles)
+  int64_t lvl_stride;  // elements between levels in lvls
+  int32_t pad_[2];
+};
+
+// One tile of work: problem index, tile row, tile column, stage-specific flags.
+struct Task {
+  int32_t p, tm, tn, flags;
+};
+
+struct StageArgs {
+  const ProbDev *probs;  // device table (batched calls); unused when tasks == nullptr
+  const Task *tasks;     // device task list; nullptr: one problem (`one`), tiles decoded on the fly
+  int32_t ntasks;
+  int32_t level;       // squaring: produces level+1 from level
+  int32_t J;           // number of squarings of the plan
+  int32_t basis;
+  int32_t norm;
+  int32_t last;        // squaring stage is the last one
+  int32_t learned;     // learned mode: keep levels, defer aggregation
+  int32_t ns_step;     // classical NS: step index (-1 for IFNSO)
+  int32_t ns_last;     // classical NS: last step
+  double ns_abc[3];
+  int32_t p_empty;     // product: no terms with exponent >= 1
+  int32_t ns_steps;    // classical NS: total steps (used by the h == 1 scalar path)
+  ProbDev one;         // the problem of a single-problem launch
+};
+
+}  // namespace ifnso

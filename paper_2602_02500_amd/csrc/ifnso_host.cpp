@@ -1,0 +1,669 @@
+// Host side of libifnso: plans, argument checks, workspace layout, tile schedules,
+// per-call problem tables, HIP-graph replay and the C ABI declared in ifnso.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ifnso.h"
+#include "ifnso_common.hpp"
+#include "ifnso_launch.hpp"
+
+using namespace ifnso;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ifnso_status fail(ifnso_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(IFNSO_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kStatsPerProblem = 32;
+constexpr int kSlotsRing = 4;  // per-call problem tables in flight per plan
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+size_t op_size(int op) { return op == kOpF32 ? 4 : (op == kOpBF16 ? 2 : 1); }
+
+// Tile size of the symmetric stages and the product; every h x h buffer is padded to a
+// multiple of kPad so that all stage kernels read it without bounds checks.
+constexpr int kTS = 128;
+constexpr int kPad = 256;
+
+struct ProbLayout {
+  int64_t rows, cols;
+  int32_t h, w, trans, hp, nt;
+  size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2];
+  int64_t ldx;
+  size_t bytes;
+};
+
+// Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
+// float32 D ping-pong; classical NS adds two h x w iterates.
+ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns) {
+  ProbLayout L{};
+  L.rows = rows;
+  L.cols = cols;
+  L.trans = rows > cols;
+  L.h = (int32_t)std::min(rows, cols);
+  L.w = (int32_t)std::max(rows, cols);
+  L.hp = (int32_t)round_up(L.h, kPad);
+  L.nt = L.hp / kTS;
+  const size_t hh = (size_t)L.hp * L.hp;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, kAlign);
+    return at;
+  };
+  L.off_opnd[0] = take(hh * op_size(op));
+  L.off_opnd[1] = take(hh * op_size(op));
+  L.off_accf = take(hh * 4);
+  if (complement) {
+    L.off_df[0] = take(hh * 4);
+    L.off_df[1] = take(hh * 4);
+  }
+  const int levels = J + 2;
+  L.off_norm = take((size_t)L.nt * 8);
+  L.off_lvl = take((size_t)levels * L.nt * L.nt * 8);
+  L.off_diag = take((size_t)levels * L.nt * 8);
+  if (ns) {
+    L.ldx = round_up(L.w, 8);
+    L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
+    L.off_xbuf[1] = take((size_t)L.h * L.ldx * op_size(op));
+  }
+  L.bytes = o;
+  return L;
+}
+
+void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t ldm, void *Y, int64_t ldy,
+              int op, double *coef, double *stats) {
+  std::memset(&d, 0, sizeof d);
+  d.M = M;
+  d.Y = Y;
+  d.ldm = ldm;
+  d.ldy = ldy;
+  d.h = L.h;
+  d.w = L.w;
+  d.trans = L.trans;
+  d.hp = L.hp;
+  d.nt = L.nt;
+  const size_t es = op_size(op);
+  d.vecM = ((uintptr_t)M % 16 == 0) && ((size_t)ldm * es % 16 == 0);
+  d.opnd[0] = ws + L.off_opnd[0];
+  d.opnd[1] = ws + L.off_opnd[1];
+  d.accf = (float *)(ws + L.off_accf);
+  d.df[0] = L.off_df[0] ? (float *)(ws + L.off_df[0]) : nullptr;
+  d.df[1] = L.off_df[1] ? (float *)(ws + L.off_df[1]) : nullptr;
+  d.norm_part = (double *)(ws + L.off_norm);
+  d.lvl_part = (double *)(ws + L.off_lvl);
+  d.diag_part = (double *)(ws + L.off_diag);
+  d.coef = coef;
+  d.stats = stats;
+  d.xbuf[0] = L.off_xbuf[0] ? ws + L.off_xbuf[0] : nullptr;
+  d.xbuf[1] = L.off_xbuf[1] ? ws + L.off_xbuf[1] : nullptr;
+  d.ldx = L.ldx;
+}
+
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+size_t matrix_bytes(int64_t rows, int64_t ld, int64_t cols, size_t es) {
+  return ((size_t)(rows - 1) * ld + cols) * es;
+}
+
+int dev_cus(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return 256;
+  return p.multiProcessorCount;
+}
+
+int grid_for(int op, int stage, int ntasks, int cus) {
+  int occ = 1;
+  if (stage_occupancy(op, kTS, stage, &occ) != hipSuccess || occ < 1) occ = 1;
+  return std::max(1, std::min(ntasks, occ * cus));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------------------------
+struct ifnso_plan_s {
+  int device = 0;
+  int num = 0;
+  int K = 0;
+  int32_t exps[kMaxTerms] = {};
+  double coeffs[kMaxTerms] = {};
+  double slots[kSlots] = {};
+  int basis = 0, norm = 0, op = 0, coeff_mode = 0;
+  uint32_t flags = 0;
+  int in_dtype = 0, out_dtype = 0;
+  int J = 0;
+  bool p_empty = false;
+  std::vector<ProbLayout> lay;
+  std::vector<size_t> ws_off;  // per-problem offset into the workspace
+  size_t ws_bytes = 0;
+  // device schedule
+  Task *d_tasks = nullptr;
+  int n_gram = 0, n_square = 0, n_prod = 0;
+  size_t off_gram = 0, off_square = 0, off_prod = 0;
+  double *d_coef = nullptr;   // [num][kSlots]
+  double *d_stats = nullptr;  // [num][kStatsPerProblem]
+  int grid[3] = {1, 1, 1};
+  int cus = 256;
+  // per-call tables
+  ProbDev *d_table[kSlotsRing] = {};
+  ProbDev *h_table[kSlotsRing] = {};
+  hipEvent_t ev[kSlotsRing] = {};
+  bool ev_used[kSlotsRing] = {};
+  int next_slot = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[kSlotsRing] = {};
+  std::vector<hipEvent_t> stage_events;  // pending measurement request (one call)
+  std::mutex mu;
+};
+
+static ifnso_status validate_desc(const ifnso_poly_desc *d) {
+  if (!d) return fail(IFNSO_ERR_INVALID_ARGUMENT, "descriptor is NULL");
+  if (d->num_terms < 1 || d->num_terms > kMaxTerms)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "num_terms %d outside 1..%d", d->num_terms, kMaxTerms);
+  if (!d->exponents || !d->coeffs) return fail(IFNSO_ERR_INVALID_ARGUMENT, "exponents/coeffs is NULL");
+  for (int k = 0; k < d->num_terms; k++) {
+    const int32_t e = d->exponents[k];
+    if (e < 0 || e > (1 << 15) || (e != 0 && (e & (e - 1)) != 0))
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "exponent %d is not 0 or 2^j with j <= 15", e);
+    if (k && e <= d->exponents[k - 1])
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "exponents must be strictly increasing");
+    if (!std::isfinite(d->coeffs[k])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficient %d is not finite", k);
+  }
+  if (d->basis != IFNSO_BASIS_GRAM && d->basis != IFNSO_BASIS_COMPLEMENT)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad basis %d", d->basis);
+  if (d->norm < IFNSO_NORM_FROBENIUS || d->norm > IFNSO_NORM_NONE)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad norm %d", d->norm);
+  if (d->compute < IFNSO_COMPUTE_F32 || d->compute > IFNSO_COMPUTE_FP8_E4M3)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad compute %d", d->compute);
+  if (d->coeff_mode != IFNSO_COEFF_FIXED && d->coeff_mode != IFNSO_COEFF_LEARNED)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad coeff_mode %d", d->coeff_mode);
+  if (d->flags & ~(uint32_t)IFNSO_FLAG_ENFORCE_SUM_ONE) return fail(IFNSO_ERR_INVALID_ARGUMENT, "unknown flags");
+  if (d->flags & IFNSO_FLAG_ENFORCE_SUM_ONE) {
+    double s = 0;
+    for (int k = 0; k < d->num_terms; k++) s += d->coeffs[k];
+    if (std::fabs(s - 1.0) > 1e-12) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficients sum to %.17g, not 1", s);
+  }
+  if (d->coeff_mode == IFNSO_COEFF_LEARNED) {
+    return fail(IFNSO_ERR_UNSUPPORTED, "learned coefficients are not built in this library");
+  }
+  if (d->compute == IFNSO_COMPUTE_FP8_E4M3) return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute is not built");
+  return IFNSO_OK;
+}
+
+static int slot_of_exponent(int e) {
+  if (e == 0) return 0;
+  int j = 0;
+  while ((1 << j) < e) j++;
+  return 1 + j;
+}
+
+extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_problems, const int64_t *rows,
+                                   const int64_t *cols, int32_t in_dtype, int32_t out_dtype, int32_t device,
+                                   ifnso_plan_t *out_plan) {
+  if (!out_plan) return fail(IFNSO_ERR_INVALID_ARGUMENT, "out_plan is NULL");
+  *out_plan = nullptr;
+  ifnso_status st = validate_desc(desc);
+  if (st != IFNSO_OK) return st;
+  if (num_problems < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "num_problems %d < 1", num_problems);
+  if (!rows || !cols) return fail(IFNSO_ERR_INVALID_ARGUMENT, "rows/cols is NULL");
+  if ((in_dtype != IFNSO_F32 && in_dtype != IFNSO_BF16) || (out_dtype != IFNSO_F32 && out_dtype != IFNSO_BF16))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad dtype");
+  for (int i = 0; i < num_problems; i++) {
+    if (rows[i] < 1 || cols[i] < 1)
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d has shape %lld x %lld", i, (long long)rows[i],
+                  (long long)cols[i]);
+    if (std::min(rows[i], cols[i]) > 65536 || std::max(rows[i], cols[i]) > (1LL << 30))
+      return fail(IFNSO_ERR_UNSUPPORTED, "problem %d is larger than this build supports", i);
+  }
+  const int op = desc->compute == IFNSO_COMPUTE_F32 ? kOpF32 : kOpBF16;
+  if ((op == kOpF32 && in_dtype != IFNSO_F32) || (op == kOpBF16 && in_dtype != IFNSO_BF16))
+    return fail(IFNSO_ERR_UNSUPPORTED, "compute type must match the input dtype (F32 with F32, BF16 with BF16)");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(IFNSO_ERR_INVALID_ARGUMENT, "device %d not present", device);
+
+  ifnso_plan_s *p = new (std::nothrow) ifnso_plan_s;
+  if (!p) return fail(IFNSO_ERR_INTERNAL, "out of host memory");
+  p->device = device;
+  p->num = num_problems;
+  p->K = desc->num_terms;
+  for (int k = 0; k < p->K; k++) {
+    p->exps[k] = desc->exponents[k];
+    p->coeffs[k] = desc->coeffs[k];
+    p->slots[slot_of_exponent(p->exps[k])] = p->coeffs[k];
+  }
+  p->basis = desc->basis;
+  p->norm = desc->norm;
+  p->op = op;
+  p->coeff_mode = desc->coeff_mode;
+  p->flags = desc->flags;
+  p->in_dtype = in_dtype;
+  p->out_dtype = out_dtype;
+  const int emax = p->exps[p->K - 1];
+  p->J = emax <= 1 ? 0 : slot_of_exponent(emax) - 1;
+  p->p_empty = emax == 0;
+  size_t off = 0;
+  for (int i = 0; i < num_problems; i++) {
+    p->lay.push_back(layout_problem(rows[i], cols[i], op, p->J, p->basis == IFNSO_BASIS_COMPLEMENT, false));
+    p->ws_off.push_back(off);
+    off = align_up(off + p->lay.back().bytes, kAlign);
+  }
+  p->ws_bytes = off;
+
+  // tile schedules: largest problems first (longest-processing-time order)
+  std::vector<int> order(num_problems);
+  for (int i = 0; i < num_problems; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double fa = (double)p->lay[a].h * p->lay[a].h * p->lay[a].w;
+    const double fb = (double)p->lay[b].h * p->lay[b].h * p->lay[b].w;
+    return fa > fb;
+  });
+  std::vector<Task> gram, square, prod;
+  for (int i : order) {
+    const ProbLayout &L = p->lay[i];
+    const int nt = (L.h + kTS - 1) / kTS;  // tiles that hold data; the padding tiles are zero
+    for (int tm = 0; tm < L.nt; tm++)
+      for (int tn = tm; tn < L.nt; tn++) {
+        gram.push_back(Task{i, tm, tn, 0});
+        square.push_back(Task{i, tm, tn, 0});
+      }
+    (void)nt;
+    const int rt = ((L.trans ? L.w : L.h) + kTS - 1) / kTS, ct = ((L.trans ? L.h : L.w) + kTS - 1) / kTS;
+    for (int tm = 0; tm < rt; tm++)
+      for (int tn = 0; tn < ct; tn++) prod.push_back(Task{i, tm, tn, 0});
+  }
+  p->n_gram = (int)gram.size();
+  p->n_square = (int)square.size();
+  p->n_prod = (int)prod.size();
+  std::vector<Task> all;
+  p->off_gram = 0;
+  all.insert(all.end(), gram.begin(), gram.end());
+  p->off_square = all.size();
+  all.insert(all.end(), square.begin(), square.end());
+  p->off_prod = all.size();
+  all.insert(all.end(), prod.begin(), prod.end());
+
+  auto cleanup = [&](ifnso_status s) {
+    ifnso_plan_destroy(p);
+    return s;
+  };
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = 0;
+  if (hipSetDevice(device) != hipSuccess) return cleanup(fail(IFNSO_ERR_HIP, "hipSetDevice(%d) failed", device));
+  hipError_t e = hipSuccess;
+  std::vector<double> coef((size_t)num_problems * kSlots);
+  for (int i = 0; i < num_problems; i++)
+    for (int k = 0; k < kSlots; k++) coef[(size_t)i * kSlots + k] = p->slots[k];
+  p->cus = dev_cus(device);
+  if (e == hipSuccess) e = hipMalloc(&p->d_tasks, all.size() * sizeof(Task));
+  if (e == hipSuccess) e = hipMemcpy(p->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_coef, coef.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(p->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_stats, (size_t)num_problems * kStatsPerProblem * sizeof(double));
+  for (int s = 0; s < kSlotsRing && e == hipSuccess; s++) {
+    e = hipMalloc(&p->d_table[s], (size_t)num_problems * sizeof(ProbDev));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_table[s], (size_t)num_problems * sizeof(ProbDev), 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev[s], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  hipSetDevice(prev);
+  if (e != hipSuccess) return cleanup(fail(IFNSO_ERR_HIP, "plan allocation: %s", hipGetErrorString(e)));
+  p->grid[kStageGram] = grid_for(op, kStageGram, p->n_gram, p->cus);
+  p->grid[kStageSquare] = grid_for(op, kStageSquare, p->n_square, p->cus);
+  p->grid[kStageProduct] = grid_for(op, kStageProduct, p->n_prod, p->cus);
+  *out_plan = p;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_workspace_bytes(ifnso_plan_t p, size_t *bytes) {
+  if (!p || !bytes) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = p->ws_bytes;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
+  if (!p) return IFNSO_OK;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = 0;
+  (void)hipSetDevice(p->device);
+  for (int s = 0; s < kSlotsRing; s++) {
+    if (p->gexec[s]) (void)hipGraphExecDestroy(p->gexec[s]);
+    if (p->ev[s]) {
+      (void)hipEventSynchronize(p->ev[s]);
+      (void)hipEventDestroy(p->ev[s]);
+    }
+    if (p->d_table[s]) (void)hipFree(p->d_table[s]);
+    if (p->h_table[s]) (void)hipHostFree(p->h_table[s]);
+  }
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_tasks) (void)hipFree(p->d_tasks);
+  if (p->d_coef) (void)hipFree(p->d_coef);
+  if (p->d_stats) (void)hipFree(p->d_stats);
+  (void)hipSetDevice(prev);
+  delete p;
+  return IFNSO_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// enqueueing the stages
+// ---------------------------------------------------------------------------------------------
+static StageArgs base_args(const ifnso_plan_s *p) {
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.J = p->J;
+  a.basis = p->basis;
+  a.norm = p->norm;
+  a.ns_step = -1;
+  a.p_empty = p->p_empty;
+  a.learned = 0;
+  return a;
+}
+
+// Enqueues every stage of a plan on `s`, reading problems from `table` (batched) or `one`.
+// With `ev`, records ev[i] before stage i and ev[J + 2] after the last stage.
+static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, const ProbDev *one, hipStream_t s,
+                               const hipEvent_t *ev = nullptr) {
+  StageArgs a = base_args(p);
+  const int outbf = p->out_dtype == IFNSO_BF16;
+  int ng, nsq, npr;
+  if (one) {
+    a.tasks = nullptr;
+    a.one = *one;
+    const ProbLayout &L = p->lay[0];
+    ng = nsq = L.nt * (L.nt + 1) / 2;
+    const int rt = ((L.trans ? L.w : L.h) + kTS - 1) / kTS, ct = ((L.trans ? L.h : L.w) + kTS - 1) / kTS;
+    npr = rt * ct;
+  } else {
+    a.probs = table;
+    ng = p->n_gram;
+    nsq = p->n_square;
+    npr = p->n_prod;
+  }
+  const int cus = p->cus;
+  hipError_t e;
+  int stage = 0;
+  auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[stage++], s) : hipSuccess; };
+  a.ntasks = ng;
+  if (!one) a.tasks = p->d_tasks + p->off_gram;
+  if ((e = mark()) != hipSuccess) return e;
+  e = launch_stage(p->op, kTS, kStageGram, a, grid_for(p->op, kStageGram, ng, cus), outbf, s);
+  if (e != hipSuccess) return e;
+  for (int lvl = 1; lvl <= p->J; lvl++) {
+    if ((e = mark()) != hipSuccess) return e;
+    a.ntasks = nsq;
+    if (!one) a.tasks = p->d_tasks + p->off_square;
+    a.level = lvl;
+    a.last = lvl == p->J;
+    e = launch_stage(p->op, kTS, kStageSquare, a, grid_for(p->op, kStageSquare, nsq, cus), outbf, s);
+    if (e != hipSuccess) return e;
+  }
+  a.ntasks = npr;
+  if (!one) a.tasks = p->d_tasks + p->off_prod;
+  a.level = 0;
+  a.last = 0;
+  if ((e = mark()) != hipSuccess) return e;
+  e = launch_stage(p->op, kTS, kStageProduct, a, grid_for(p->op, kStageProduct, npr, cus), outbf, s);
+  if (e != hipSuccess) return e;
+  return mark();
+}
+
+static ifnso_status check_matrix_args(const ifnso_plan_s *p, int i, const void *M, int64_t ldm, const void *Y,
+                                      int64_t ldy) {
+  const ProbLayout &L = p->lay[i];
+  if (!M || !Y) return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: NULL matrix pointer", i);
+  if (ldm < L.cols || ldy < L.cols)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: leading dimension smaller than cols (%lld)", i,
+                (long long)L.cols);
+  const size_t ies = p->in_dtype == IFNSO_F32 ? 4 : 2, oes = p->out_dtype == IFNSO_F32 ? 4 : 2;
+  if (ranges_overlap(M, matrix_bytes(L.rows, ldm, L.cols, ies), Y, matrix_bytes(L.rows, ldy, L.cols, oes)))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: Y overlaps M", i);
+  return IFNSO_OK;
+}
+
+static bool use_graphs() {
+  const char *v = getenv("IFNSO_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int64_t *ldm, void *const *Y,
+                                const int64_t *ldy, void *ws, size_t ws_bytes, hipStream_t s, bool single) {
+  if (!ws && p->ws_bytes) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (ws_bytes < p->ws_bytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, plan needs %zu", ws_bytes, p->ws_bytes);
+  if ((uintptr_t)ws % kAlign) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace must be %zu-byte aligned", kAlign);
+  for (int i = 0; i < p->num; i++) {
+    ifnso_status st = check_matrix_args(p, i, M[i], ldm[i], Y[i], ldy[i]);
+    if (st != IFNSO_OK) return st;
+  }
+  std::lock_guard<std::mutex> lock(p->mu);
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != p->device) HIP_TRY(hipSetDevice(p->device));
+  struct Restore {
+    int d, cur;
+    ~Restore() {
+      if (d != cur) (void)hipSetDevice(d);
+    }
+  } restore{prev, p->device};
+  char *base = (char *)ws;
+  std::vector<hipEvent_t> ev;
+  ev.swap(p->stage_events);
+  const hipEvent_t *evp = ev.empty() ? nullptr : ev.data();
+  if (single) {
+    ProbDev one;
+    fill_dev(one, p->lay[0], base + p->ws_off[0], M[0], ldm[0], Y[0], ldy[0], p->op, p->d_coef, p->d_stats);
+    HIP_TRY(enqueue_plan(p, nullptr, &one, s, evp));
+    return IFNSO_OK;
+  }
+  const int slot = p->next_slot;
+  p->next_slot = (slot + 1) % kSlotsRing;
+  if (p->ev_used[slot]) HIP_TRY(hipEventSynchronize(p->ev[slot]));  // table slot free again
+  ProbDev *ht = p->h_table[slot];
+  for (int i = 0; i < p->num; i++)
+    fill_dev(ht[i], p->lay[i], base + p->ws_off[i], M[i], ldm[i], Y[i], ldy[i], p->op,
+             p->d_coef + (size_t)i * kSlots, p->d_stats + (size_t)i * kStatsPerProblem);
+  HIP_TRY(hipMemcpyAsync(p->d_table[slot], ht, (size_t)p->num * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+  if (use_graphs() && !evp) {
+    if (!p->gexec[slot]) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue_plan(p, p->d_table[slot], nullptr, p->cap_stream);
+      hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(IFNSO_ERR_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      hipError_t e3 = hipGraphInstantiate(&p->gexec[slot], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) return fail(IFNSO_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e3));
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec[slot], s));
+  } else {
+    HIP_TRY(enqueue_plan(p, p->d_table[slot], nullptr, s, evp));
+  }
+  HIP_TRY(hipEventRecord(p->ev[slot], s));
+  p->ev_used[slot] = true;
+  return IFNSO_OK;
+}
+
+extern "C" int32_t ifnso_plan_num_stages(ifnso_plan_t p) {
+  if (!p) return -IFNSO_ERR_INVALID_ARGUMENT;
+  return p->J + 2;
+}
+
+extern "C" ifnso_status ifnso_plan_stage_events(ifnso_plan_t p, void *const *events, int32_t count) {
+  if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
+  std::lock_guard<std::mutex> lock(p->mu);
+  if (count == 0) {
+    p->stage_events.clear();
+    return IFNSO_OK;
+  }
+  if (!events || count != p->J + 3)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "need %d events (stages + 1), got %d", p->J + 3, count);
+  for (int i = 0; i < count; i++)
+    if (!events[i]) return fail(IFNSO_ERR_INVALID_ARGUMENT, "event %d is NULL", i);
+  p->stage_events.assign((hipEvent_t *)events, (hipEvent_t *)events + count);
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_orthogonalize(ifnso_plan_t p, const void *M, int64_t ldm, void *Y, int64_t ldy,
+                                            void *workspace, size_t workspace_bytes, void *stream) {
+  if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (p->num != 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan has %d problems; use the batched call", p->num);
+  const void *Ms[1] = {M};
+  void *Ys[1] = {Y};
+  return run_batched(p, Ms, &ldm, Ys, &ldy, workspace, workspace_bytes, (hipStream_t)stream, true);
+}
+
+extern "C" ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t p, const void *const *M, const int64_t *ldm,
+                                                    void *const *Y, const int64_t *ldy, void *workspace,
+                                                    size_t workspace_bytes, void *stream) {
+  if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!M || !ldm || !Y || !ldy) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL pointer array");
+  return run_batched(p, M, ldm, Y, ldy, workspace, workspace_bytes, (hipStream_t)stream, false);
+}
+
+// ---------------------------------------------------------------------------------------------
+// classical Newton-Schulz
+// ---------------------------------------------------------------------------------------------
+static int ns_op(int32_t compute, int32_t dtype) {
+  if (compute == IFNSO_COMPUTE_F32 && dtype == IFNSO_F32) return kOpF32;
+  if (compute == IFNSO_COMPUTE_BF16 && dtype == IFNSO_BF16) return kOpBF16;
+  return -1;
+}
+
+extern "C" size_t ifnso_classical_ns_workspace_bytes(int64_t rows, int64_t cols, int32_t compute) {
+  if (rows < 1 || cols < 1) return 0;
+  const int op = compute == IFNSO_COMPUTE_F32 ? kOpF32 : compute == IFNSO_COMPUTE_BF16 ? kOpBF16 : -1;
+  if (op < 0) return 0;
+  return layout_problem(rows, cols, op, 1, false, true).bytes;
+}
+
+extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
+                                           void *Y, int64_t ldy, int32_t steps, const double abc[3],
+                                           int32_t compute, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!M || !Y || !abc) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (rows < 1 || cols < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad shape");
+  if (ldm < cols || ldy < cols) return fail(IFNSO_ERR_INVALID_ARGUMENT, "leading dimension smaller than cols");
+  if (steps < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "steps must be >= 1");
+  if (dtype != IFNSO_F32 && dtype != IFNSO_BF16) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad dtype");
+  if (compute < IFNSO_COMPUTE_F32 || compute > IFNSO_COMPUTE_FP8_E4M3)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad compute");
+  for (int i = 0; i < 3; i++)
+    if (!std::isfinite(abc[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficient not finite");
+  const int op = ns_op(compute, dtype);
+  if (op < 0) return fail(IFNSO_ERR_UNSUPPORTED, "classical NS supports F32/F32 and BF16/BF16 (dtype/compute)");
+  if (std::min(rows, cols) > 65536) return fail(IFNSO_ERR_UNSUPPORTED, "matrix too large");
+  const ProbLayout L = layout_problem(rows, cols, op, 1, false, true);
+  if (!workspace) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < L.bytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", workspace_bytes, L.bytes);
+  if ((uintptr_t)workspace % kAlign) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  const size_t es = op_size(op);
+  if (ranges_overlap(M, matrix_bytes(rows, ldm, cols, es), Y, matrix_bytes(rows, ldy, cols, es)))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "Y overlaps M");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const int cus = dev_cus(dev);
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_dev(a.one, L, (char *)workspace, M, ldm, Y, ldy, op, nullptr, nullptr);
+  a.J = 1;
+  a.basis = kGram;
+  a.norm = kFrob;
+  for (int i = 0; i < 3; i++) a.ns_abc[i] = abc[i];
+  const int nsym = L.nt * (L.nt + 1) / 2;
+  hipStream_t s = (hipStream_t)stream;
+  a.ns_steps = steps;
+  // h == 1: the product kernel runs the scalar recursion from the float64 norm in one pass
+  const int passes = L.h == 1 ? 1 : steps;
+  for (int k = 0; k < passes; k++) {
+    a.ns_step = k;
+    a.ns_last = k == passes - 1;
+    a.ntasks = nsym;
+    a.level = 1;
+    a.last = 1;
+    HIP_TRY(launch_stage(op, kTS, kStageGram, a, grid_for(op, kStageGram, nsym, cus), 0, s));
+    if (L.h > 1) HIP_TRY(launch_stage(op, kTS, kStageSquare, a, grid_for(op, kStageSquare, nsym, cus), 0, s));
+    const bool tall_map = k == 0 && L.trans;
+    const int rt = ((tall_map ? L.w : L.h) + kTS - 1) / kTS, ct = ((tall_map ? L.h : L.w) + kTS - 1) / kTS;
+    a.ntasks = rt * ct;
+    a.level = 0;
+    a.last = 0;
+    HIP_TRY(launch_stage(op, kTS, kStageProduct, a, grid_for(op, kStageProduct, rt * ct, cus),
+                         dtype == IFNSO_BF16, s));
+  }
+  return IFNSO_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// evaluation helpers
+// ---------------------------------------------------------------------------------------------
+static constexpr int kOrthSplit = 32;
+
+extern "C" size_t ifnso_orth_error_workspace_bytes(int32_t count) {
+  if (count < 1) return 0;
+  return align_up((size_t)count * sizeof(OrthEntry), kAlign) + (size_t)count * kOrthSplit * sizeof(double);
+}
+
+extern "C" ifnso_status ifnso_orth_error(int32_t count, const void *const *Y, const int64_t *rows,
+                                         const int64_t *cols, const int64_t *ldy, int32_t dtype, double *out,
+                                         void *workspace, size_t workspace_bytes, void *stream) {
+  if (count < 1 || !Y || !rows || !cols || !ldy || !out) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad arguments");
+  if (dtype != IFNSO_F32 && dtype != IFNSO_BF16) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad dtype");
+  if (!workspace || workspace_bytes < ifnso_orth_error_workspace_bytes(count))
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  std::vector<OrthEntry> e(count);
+  for (int i = 0; i < count; i++) {
+    if (!Y[i] || rows[i] < 1 || cols[i] < 1 || ldy[i] < cols[i])
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "matrix %d: bad pointer or shape", i);
+    e[i] = OrthEntry{Y[i], rows[i], cols[i], ldy[i]};
+  }
+  hipStream_t s = (hipStream_t)stream;
+  OrthArgs a;
+  a.e = (const OrthEntry *)workspace;
+  a.part = (double *)((char *)workspace + align_up((size_t)count * sizeof(OrthEntry), kAlign));
+  a.out = out;
+  a.nsplit = kOrthSplit;
+  a.count = count;
+  HIP_TRY(hipMemcpyAsync((void *)a.e, e.data(), (size_t)count * sizeof(OrthEntry), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_orth_error(a, dtype == IFNSO_BF16, s));
+  // the host array `e` must outlive the copy
+  HIP_TRY(hipStreamSynchronize(s));
+  return IFNSO_OK;
+}
+
+extern "C" const char *ifnso_last_error(void) { return g_last_error.c_str(); }

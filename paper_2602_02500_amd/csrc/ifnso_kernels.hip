@@ -1,0 +1,478 @@
+// Stage kernels of libifnso for gfx950.
+//
+// A plan runs, for every problem, the stages of the polynomial (Algorithm 1 of the
+// paper, in the Gram or the complement basis):
+//   Gram      G_raw = A A^T on upper tiles; fused float64 partials of ||A||_F^2 (diagonal
+//             tiles, from the staged operand registers), of ||G_raw||_F^2 and of tr(G_raw).
+//   square j  level j+1 = (level j)^2 on upper tiles, written back as a full symmetric
+//             operand; the running sum P accumulates c * level in float32.
+//   product   Y = s (c0 A + P A), written in M's orientation and dtype.
+// Each stage is one persistent launch over a task list that holds the tiles of every
+// problem; scalars (norms, level scales, coefficients) are recomputed by each workgroup
+// from the float64 partials of earlier stages, in a fixed order, so results do not depend
+// on scheduling.
+//
+// Level scaling (Gram basis): the stored operand of level l is B_l with true value
+// S_l * B_l. Level 1 stores G_raw, S_1 = s_g (1/||A||_F^2, 1/||G_raw||_F or 1 by norm).
+// Squaring stores B_{l+1} = F_{l+1} * B_l^2 with F_{l+1} = 2^-round(log2 ||B_l||_F^2), so
+// every stored level keeps unit-order entries even when the true power underflows float32;
+// S_{l+1} = S_l^2 / F_{l+1}. Complement basis: levels hold D_l = T_1^(2^(l-1)) - I with
+// D_1 = -s_g G_raw and D_{l+1} = 2 D_l + D_l^2 (the shifted form keeps small 1 - T
+// entries exact), and the identity parts are folded into the coefficient of X.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ifnso_common.hpp"
+#include "ifnso_launch.hpp"
+#include "ifnso_tile.hpp"
+
+namespace ifnso {
+
+// ---------------------------------------------------------------------------------------------
+// per-problem scalars from the float64 partials
+// ---------------------------------------------------------------------------------------------
+struct Scalars {
+  double nA2;   // ||A||_F^2
+  double g2;    // ||G_raw||_F^2
+  double sg;    // scale of the level-1 operand (G = sg * G_raw)
+  double sout;  // output scale s
+  bool zero;
+};
+
+__device__ __forceinline__ Scalars problem_scalars(const ProbDev &P, int norm) {
+  Scalars s;
+  s.nA2 = wave_sum(P.norm_part, P.nt);
+  s.g2 = wave_sum_upper(P.lvl_part + (int64_t)1 * P.nt * P.nt, P.nt);
+  s.zero = !(s.nA2 > 0.0);
+  if (norm == kFrob) {
+    s.sg = s.zero ? 0.0 : 1.0 / s.nA2;
+    s.sout = s.zero ? 0.0 : 1.0 / sqrt(s.nA2);
+  } else if (norm == kGramFrob) {
+    const double o = sqrt(s.g2);
+    s.sg = s.zero ? 0.0 : 1.0 / o;
+    s.sout = s.zero ? 0.0 : 1.0 / sqrt(o);
+  } else {
+    s.sg = 1.0;
+    s.sout = 1.0;
+  }
+  return s;
+}
+
+__device__ __forceinline__ double pow2_inv_round(double nb) {
+  if (!(nb > 0.0) || !isfinite(nb)) return 1.0;
+  return exp2(-rint(log2(nb)));
+}
+
+// Gram basis: scale S_level of the stored operand of `level` (level >= 1).
+__device__ __forceinline__ double level_scale(const ProbDev &P, double sg, int level) {
+  double S = sg;
+  const int64_t nt2 = (int64_t)P.nt * P.nt;
+  for (int l = 1; l < level; l++) {
+    const double F = pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+    S = S * S / F;
+  }
+  return S;
+}
+
+// ---------------------------------------------------------------------------------------------
+// task fetch: a device task list (grouped launches) or tiles decoded from the index
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ Task decode_upper(int t, int nt) {
+  int tm = 0;
+  while (t >= nt - tm) {
+    t -= nt - tm;
+    tm++;
+  }
+  return Task{0, tm, tm + t, 0};
+}
+
+template <int TS>
+__device__ __forceinline__ Task fetch_task(const StageArgs &a, int t, int stage) {
+  if (a.tasks) return a.tasks[t];
+  const ProbDev &P = a.one;
+  if (stage != kStageProduct) return decode_upper(t, P.nt);
+  const bool tall_map = (a.ns_step <= 0) && P.trans;
+  const int ncols = ((tall_map ? P.h : P.w) + TS - 1) / TS;
+  return Task{0, t / ncols, t % ncols, 0};
+}
+
+__device__ __forceinline__ const ProbDev &prob_of(const StageArgs &a, const Task &task) {
+  return a.tasks ? a.probs[task.p] : a.one;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Gram
+// ---------------------------------------------------------------------------------------------
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
+  using TL = Tile<T, TS, TS>;
+  __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    const Task task = fetch_task<TS>(a, t, kStageGram);
+    const ProbDev &P = prob_of(a, task);
+    const int m0 = task.tm * TS, n0 = task.tn * TS;
+    const bool diag = task.tm == task.tn;
+    const bool first_step = a.ns_step <= 0;
+    TL tile;
+    double nrm;
+    if (!first_step) {  // classical NS, later steps: X_k (wide, K-major) from the workspace
+      const T *X = (const T *)P.xbuf[(a.ns_step - 1) & 1];
+      nrm = tile.template run<false, false>(smem, X, P.ldx, m0, P.h, true, X, P.ldx, n0, P.h, true, P.w, false);
+    } else if (P.trans) {
+      const T *M = (const T *)P.M;
+      nrm = tile.template run<true, true>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, P.w, diag);
+    } else {
+      const T *M = (const T *)P.M;
+      nrm = tile.template run<false, false>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, P.w, diag);
+    }
+    T *op = (T *)P.opnd[0];
+    const int64_t hp = P.hp;
+    const bool keep_f32 = a.J >= 1 || a.ns_step >= 0 || a.learned;
+    double lv = 0.0, dg = 0.0;
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; fm++)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; fn++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+          const int i = m0 + TL::row_of(fm, r), j = n0 + TL::col_of(fn);
+          const float v = tile.acc[fm][fn][r];
+          const T tv = Elem<T>::from_f(v);
+          op[i * hp + j] = tv;
+          if (!diag) op[j * hp + i] = tv;
+          if (keep_f32) P.accf[i * hp + j] = v;
+          const double dv = (double)v;
+          lv = fma(dv, diag ? dv : 2.0 * dv, lv);
+          if (i == j) dg += dv;
+        }
+    if (!diag || !first_step) nrm = 0.0;
+    block_sum3(lv, dg, nrm, (double *)smem);
+    if (threadIdx.x == 0) {
+      const int nt = P.nt;
+      P.lvl_part[(int64_t)1 * nt * nt + task.tm * nt + task.tn] = lv;
+      if (diag) {
+        P.diag_part[1 * nt + task.tm] = dg;
+        if (first_step) P.norm_part[task.tm] = nrm;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// squaring: level -> level + 1
+// ---------------------------------------------------------------------------------------------
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
+  using TL = Tile<T, TS, TS>;
+  __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
+  const int level = a.level;
+  int cur_p = -1;
+  // per-problem factors (recomputed when the problem changes)
+  float f_out = 1.f;    // stored next level = f_out * acc
+  float c_acc = 0.f;    // P += c_acc * acc                 (Gram basis)
+  float c_first = 0.f;  // level 1: P = c_first * G_raw + ...
+  float alpha = 1.f;    // complement: D_next = 2 D + alpha * acc
+  float c_next = 0.f;   // complement: P += c_next * D_next
+  float dscale = 1.f;   // complement, level 1: D_1 = dscale * G_raw
+  float ns_b = 0.f, ns_c = 0.f;
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    const Task task = fetch_task<TS>(a, t, kStageSquare);
+    const ProbDev &P = prob_of(a, task);
+    if (task.p != cur_p) {
+      cur_p = task.p;
+      const Scalars sc = problem_scalars(P, a.norm);
+      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      if (a.ns_step >= 0) {
+        const double s = (a.ns_step == 0) ? sc.sg : 1.0;
+        ns_b = (float)(a.ns_abc[1] * s);
+        ns_c = (float)(a.ns_abc[2] * s * s);
+      } else if (a.basis == kGram) {
+        const double S = level_scale(P, sc.sg, level);
+        f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt));
+        c_acc = (float)(P.coef[level + 1] * S * S);
+        c_first = (float)(P.coef[1] * sc.sg);
+      } else {
+        alpha = (float)(level == 1 ? sc.sg * sc.sg : 1.0);
+        dscale = (float)(-sc.sg);
+        c_next = (float)P.coef[level + 1];
+        c_first = (float)P.coef[1];
+      }
+    }
+    const int m0 = task.tm * TS, n0 = task.tn * TS;
+    const bool diag = task.tm == task.tn;
+    const int64_t hp = P.hp;
+    const T *src = (const T *)P.opnd[(level - 1) & 1];
+    TL tile;
+    tile.template run<false, false>(smem, src, hp, m0, P.hp, true, src, hp, n0, P.hp, true, P.h, false);
+    T *dst = (T *)P.opnd[level & 1];
+    const bool last = a.last;
+    double lv = 0.0, dg = 0.0, unused = 0.0;
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; fm++)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; fn++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+          const int i = m0 + TL::row_of(fm, r), j = n0 + TL::col_of(fn);
+          const int64_t ij = i * hp + j;
+          const float acc = tile.acc[fm][fn][r];
+          float out, pv;
+          if (a.ns_step >= 0) {
+            // classical NS: B = b G + c G^2 (G = s G_raw at the first step)
+            out = ns_b * P.accf[ij] + ns_c * acc;
+            pv = out;
+          } else if (a.basis == kGram) {
+            out = f_out * acc;
+            pv = (level == 1 ? c_first * P.accf[ij] : P.accf[ij]) + c_acc * acc;
+          } else {
+            const float dprev = (level == 1) ? dscale * P.accf[ij] : P.df[level & 1][ij];
+            out = 2.f * dprev + alpha * acc;
+            pv = (level == 1 ? c_first * dprev : P.accf[ij]) + c_next * out;
+            if (!last) P.df[(level + 1) & 1][ij] = out;
+          }
+          const T tv = Elem<T>::from_f(last ? pv : out);
+          dst[ij] = tv;
+          if (!diag) dst[j * hp + i] = tv;
+          if (!last) P.accf[ij] = pv;
+          const double dv = (double)out;
+          lv = fma(dv, diag ? dv : 2.0 * dv, lv);
+          if (i == j) dg += dv;
+        }
+    block_sum3(lv, dg, unused, (double *)smem);
+    if (threadIdx.x == 0 && a.ns_step < 0) {
+      const int nt = P.nt;
+      P.lvl_part[(int64_t)(level + 1) * nt * nt + task.tm * nt + task.tn] = lv;
+      if (diag) P.diag_part[(level + 1) * nt + task.tm] = dg;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// product: Y = s (c0 X + P X), in M's orientation
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float load_el(const void *p, int64_t idx) {
+  return Elem<T>::to_f(((const T *)p)[idx]);
+}
+
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const int out_bf16) {
+  using TL = Tile<T, TS, TS>;
+  __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
+  int cur_p = -1;
+  float sc0 = 0.f, sps = 0.f;
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    const Task task = fetch_task<TS>(a, t, kStageProduct);
+    const ProbDev &P = prob_of(a, task);
+    if (task.p != cur_p) {
+      cur_p = task.p;
+      const Scalars sc = problem_scalars(P, a.norm);
+      double c0, ps, sout;
+      if (P.h == 1) {
+        // A single row or column: G = x x^T / s^2 is a scalar known exactly from the float64
+        // norm, so the polynomial (or the NS recursion) is evaluated in float64 here.
+        const double g = (a.norm == kNone && a.ns_step < 0) ? sc.nA2 : 1.0;
+        sout = sc.zero ? 0.0 : (a.norm == kNone && a.ns_step < 0 ? 1.0 : 1.0 / sqrt(sc.nA2));
+        double v = 0.0;
+        if (a.ns_step >= 0) {
+          double x = 1.0;
+          for (int k = 0; k < a.ns_steps; k++) x = x * (a.ns_abc[0] + x * x * (a.ns_abc[1] + a.ns_abc[2] * x * x));
+          v = x;
+        } else {
+          const double b = (a.basis == kGram) ? g : 1.0 - g;
+          for (int k = 0; k < kSlots; k++) {
+            const double e = k == 0 ? 0.0 : exp2((double)(k - 1));
+            if (P.coef[k] != 0.0) v += P.coef[k] * pow(b, e);
+          }
+        }
+        c0 = v;
+        ps = 0.0;
+      } else if (a.ns_step >= 0) {
+        c0 = a.ns_abc[0];
+        ps = 1.0;
+        sout = (a.ns_step == 0) ? sc.sout : 1.0;
+        if (a.ns_step == 0 && sc.zero) sout = 0.0;
+      } else {
+        sout = sc.sout;
+        if (a.basis == kGram) {
+          c0 = P.coef[0];
+          ps = (a.J == 0) ? P.coef[1] * sc.sg : 1.0;
+        } else {
+          c0 = 0.0;
+          for (int k = 0; k < kSlots; k++) c0 += P.coef[k];
+          ps = (a.J == 0) ? -P.coef[1] * sc.sg : 1.0;
+        }
+        if (sc.zero && a.norm != kNone) sout = 0.0;
+      }
+      sc0 = (float)(sout * c0);
+      sps = (float)(sout * ps);
+    }
+    const T *Pb = (const T *)P.opnd[a.J & 1];
+    const int64_t hp = P.hp;
+    // geometry: source X_k, destination, orientation of the computed tile
+    const bool ns = a.ns_step >= 0;
+    const bool from_m = !ns || a.ns_step == 0;
+    const T *X = from_m ? (const T *)P.M : (const T *)P.xbuf[(a.ns_step - 1) & 1];
+    const int64_t ldx = from_m ? P.ldm : P.ldx;
+    const bool xvec = from_m ? (P.vecM != 0) : true;
+    const bool tall_map = from_m && P.trans;  // tile rows index w, cols index h
+    const bool to_y = !ns || a.ns_last;
+    void *dst = to_y ? P.Y : P.xbuf[a.ns_step & 1];
+    const bool dst_bf16 = to_y ? (out_bf16 != 0) : (sizeof(T) == 2);
+    // dst element for logical wide-orientation (i, n):
+    //   to Y: trans ? Y[n][i] : Y[i][n];  to xbuf: xbuf[i][n]
+    const int m0 = task.tm * TS, n0 = task.tn * TS;
+    TL tile;
+    if (a.p_empty || P.h == 1) {
+      tile.zero();
+    } else if (tall_map) {
+      tile.template run<false, false>(smem, X, ldx, m0, P.w, xvec, Pb, hp, n0, P.hp, true, P.h, false);
+    } else {
+      tile.template run<false, true>(smem, Pb, hp, m0, P.hp, true, X, ldx, n0, P.w, xvec, P.h, false);
+    }
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; fm++)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; fn++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+          const int tr = m0 + TL::row_of(fm, r), tc = n0 + TL::col_of(fn);
+          // logical (i, n) in the wide orientation
+          const int i = tall_map ? tc : tr, n = tall_map ? tr : tc;
+          if (i >= P.h || n >= P.w) continue;
+          const int64_t xidx = tall_map ? (int64_t)n * ldx + i : (int64_t)i * ldx + n;
+          const float x = load_el<T>(X, xidx);
+          const float y = sc0 * x + sps * tile.acc[fm][fn][r];
+          int64_t didx;
+          if (to_y) didx = P.trans ? (int64_t)n * P.ldy + i : (int64_t)i * P.ldy + n;
+          else didx = (int64_t)i * P.ldx + n;
+          if (dst_bf16) ((uint16_t *)dst)[didx] = f32_to_bf16(y);
+          else ((float *)dst)[didx] = y;
+        }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// float64 orthogonality error ||Z Z^T - I||_F (evaluation only)
+// ---------------------------------------------------------------------------------------------
+template <typename TY>
+__global__ __launch_bounds__(256) void k_orth_error(const OrthArgs a) {
+  constexpr int T64 = 64, KS = 16;
+  __shared__ double Zi[KS][T64 + 1];
+  __shared__ double Zj[KS][T64 + 1];
+  __shared__ double red[4];
+  const int p = blockIdx.x / a.nsplit, split = blockIdx.x % a.nsplit;
+  const OrthEntry E = a.e[p];
+  const TY *Y = (const TY *)E.ptr;
+  const bool trans = E.rows > E.cols;
+  const int64_t h = trans ? E.cols : E.rows, w = trans ? E.rows : E.cols, ld = E.ld;
+  const int tr = threadIdx.x >> 4, tcol = threadIdx.x & 15;
+  const int nt = (int)((h + T64 - 1) / T64);
+  double total = 0.0;
+  auto zel = [&](int64_t i, int64_t k) -> double {
+    if (i >= h || k >= w) return 0.0;
+    const int64_t idx = trans ? k * ld + i : i * ld + k;
+    if constexpr (sizeof(TY) == 2) return (double)bf16_to_f32(((const uint16_t *)Y)[idx]);
+    else return (double)((const float *)Y)[idx];
+  };
+  for (int ti = split; ti < nt; ti += a.nsplit) {
+    for (int tj = ti; tj < nt; tj++) {
+      double acc[4][4] = {};
+      for (int64_t k0 = 0; k0 < w; k0 += KS) {
+        for (int e = threadIdx.x; e < KS * T64; e += 256) {
+          const int r = trans ? (e % T64) : (e / KS), kk = trans ? (e / T64) : (e % KS);
+          Zi[kk][r] = zel((int64_t)ti * T64 + r, k0 + kk);
+          Zj[kk][r] = zel((int64_t)tj * T64 + r, k0 + kk);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KS; kk++) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            av[u] = Zi[kk][tr * 4 + u];
+            bv[u] = Zj[kk][tcol * 4 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+      }
+      const double wgt = (ti == tj) ? 1.0 : 2.0;
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int64_t gi = (int64_t)ti * T64 + tr * 4 + u, gj = (int64_t)tj * T64 + tcol * 4 + v;
+          if (gi < h && gj < h) {
+            const double e = acc[u][v] - (gi == gj ? 1.0 : 0.0);
+            total = fma(wgt * e, e, total);
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) a.part[(int64_t)p * a.nsplit + split] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void k_orth_finish(const OrthArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.count) return;
+  double s = 0.0;
+  for (int i = 0; i < a.nsplit; i++) s += a.part[(int64_t)p * a.nsplit + i];
+  a.out[p] = sqrt(s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+template <typename T, int TS>
+static hipError_t launch_stage_t(int stage, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  if (stage == kStageGram) hipLaunchKernelGGL((k_gram<T, TS>), dim3(grid), dim3(kThreads), 0, s, a);
+  else if (stage == kStageSquare) hipLaunchKernelGGL((k_square<T, TS>), dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_product<T, TS>), dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(int op, int ts, int stage, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
+  if (op == kOpBF16) {
+    if (ts == 128) return launch_stage_t<uint16_t, 128>(stage, a, grid, out_bf16, s);
+  } else if (op == kOpF32) {
+    if (ts == 128) return launch_stage_t<float, 128>(stage, a, grid, out_bf16, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu) {
+  const void *fn = nullptr;
+  if (op == kOpBF16 && ts == 128) {
+    fn = stage == kStageGram ? (const void *)k_gram<uint16_t, 128>
+       : stage == kStageSquare ? (const void *)k_square<uint16_t, 128> : (const void *)k_product<uint16_t, 128>;
+  } else if (op == kOpF32 && ts == 128) {
+    fn = stage == kStageGram ? (const void *)k_gram<float, 128>
+       : stage == kStageSquare ? (const void *)k_square<float, 128> : (const void *)k_product<float, 128>;
+  }
+  if (!fn) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
+}
+
+hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s) {
+  const dim3 grid(a.count * a.nsplit);
+  if (bf16) hipLaunchKernelGGL(k_orth_error<uint16_t>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_orth_error<float>, grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_orth_finish, dim3((a.count + 63) / 64), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ifnso

@@ -1,0 +1,29 @@
+// Internal interface between the host scheduler and the kernel translation unit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ifnso_common.hpp"
+
+namespace ifnso {
+
+enum Stage : int { kStageGram = 0, kStageSquare = 1, kStageProduct = 2 };
+
+struct OrthEntry {
+  const void *ptr;
+  int64_t rows, cols, ld;
+};
+
+struct OrthArgs {
+  const OrthEntry *e;  // [count], device
+  double *part;        // [count][nsplit], device
+  double *out;         // [count], device
+  int32_t nsplit;
+  int32_t count;
+};
+
+hipError_t launch_stage(int op, int ts, int stage, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
+hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu);
+hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
+
+}  // namespace ifnso

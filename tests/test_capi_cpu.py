@@ -1,0 +1,97 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, and
+rejects bad arguments before touching the HIP runtime."""
+import ctypes
+
+import pytest
+
+import paper_2602_02500_amd as ifn
+
+
+@pytest.fixture(scope="module")
+def L():
+    return ifn.load()
+
+
+def test_exports_every_header_symbol(L):
+    names = ifn.header_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _plan(L, exps, coeffs, basis=0, norm=0, compute=1, mode=0, flags=0, rows=(64,), cols=(96,), ind=1, outd=1):
+    K = len(exps)
+    e = (ctypes.c_int32 * max(K, 1))(*exps)
+    c = (ctypes.c_double * max(K, 1))(*coeffs)
+    d = ifn.PolyDesc(K, e, c, basis, norm, compute, mode, None, 0, flags)
+    n = len(rows)
+    r = (ctypes.c_int64 * n)(*rows)
+    cc = (ctypes.c_int64 * n)(*cols)
+    h = ctypes.c_void_p()
+    st = L.ifnso_plan(ctypes.byref(d), n, r, cc, ind, outd, 0, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("exps,coeffs", [
+    ([3], [1.0]),               # not a power of two
+    ([0, 2, 1], [1, 1, 1]),     # not increasing
+    ([0, 0], [1, 1]),           # repeated
+    ([1 << 16], [1.0]),         # above 2^15
+    ([-1], [1.0]),
+    ([], []),                   # no terms
+    ([0, 1], [1.0, float("nan")]),
+])
+def test_plan_rejects_bad_polynomials(L, exps, coeffs):
+    st, _ = _plan(L, exps, coeffs)
+    assert st == 1, L.ifnso_last_error()
+
+
+def test_plan_rejects_bad_enums_and_shapes(L):
+    assert _plan(L, [0, 1], [1, 1], basis=7)[0] == 1
+    assert _plan(L, [0, 1], [1, 1], norm=9)[0] == 1
+    assert _plan(L, [0, 1], [1, 1], compute=5)[0] == 1
+    assert _plan(L, [0, 1], [1, 1], rows=(0,))[0] == 1
+    assert _plan(L, [0, 1], [1, 1], cols=(-3,))[0] == 1
+    assert _plan(L, [0, 1], [1, 1], ind=4)[0] == 1
+
+
+def test_sum_one_flag(L):
+    st, _ = _plan(L, [0, 1], [0.5, 0.6], flags=ifn.FLAG_ENFORCE_SUM_ONE)
+    assert st == 1 and b"sum" in L.ifnso_last_error()
+
+
+def test_unsupported_combinations(L):
+    assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_F32, ind=ifn.BF16)[0] == 2
+    assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_BF16, ind=ifn.F32)[0] == 2
+    assert _plan(L, [0, 1], [1, 1], mode=1)[0] == 2
+
+
+def test_null_arguments(L):
+    h = ctypes.c_void_p()
+    assert L.ifnso_plan(None, 1, None, None, 1, 1, 0, ctypes.byref(h)) == 1
+    assert L.ifnso_plan_destroy(None) == 0
+    assert L.ifnso_orthogonalize(None, None, 0, None, 0, None, 0, None) == 1
+    sz = ctypes.c_size_t()
+    assert L.ifnso_plan_workspace_bytes(None, ctypes.byref(sz)) == 1
+
+
+def test_classical_ns_argument_checks(L):
+    abc = (ctypes.c_double * 3)(3.4445, -4.775, 2.0315)
+    assert L.ifnso_classical_ns(None, 4, 4, 4, 0, 16, 4, 5, abc, 0, 256, 1 << 20, None) == 1
+    assert L.ifnso_classical_ns(1024, 4, 8, 4, 0, 4096, 8, 5, abc, 0, 256, 1 << 20, None) == 1  # ldm < cols
+    assert L.ifnso_classical_ns(1024, 4, 8, 8, 0, 4096, 8, 0, abc, 0, 256, 1 << 20, None) == 1  # steps
+    assert L.ifnso_classical_ns(1024, 4, 8, 8, 0, 4096, 8, 2, abc, 1, 256, 1 << 20, None) == 2  # f32 data, bf16 compute
+    need = L.ifnso_classical_ns_workspace_bytes(4, 8, 0)
+    assert need > 0
+    assert L.ifnso_classical_ns(1024, 4, 8, 8, 0, 1 << 30, 8, 2, abc, 0, 256, need - 1, None) == 3
+    assert L.ifnso_classical_ns(1024, 4, 8, 8, 0, 1028, 8, 2, abc, 0, 256, need, None) == 1  # overlap
+    assert L.ifnso_classical_ns_workspace_bytes(0, 8, 0) == 0
+
+
+def test_workspace_sizes_grow_with_shape(L):
+    a = L.ifnso_classical_ns_workspace_bytes(256, 512, 1)
+    b = L.ifnso_classical_ns_workspace_bytes(1024, 4096, 1)
+    c = L.ifnso_classical_ns_workspace_bytes(4096, 1024, 1)
+    assert 0 < a < b and b == c
+    assert L.ifnso_orth_error_workspace_bytes(0) == 0
+    assert L.ifnso_orth_error_workspace_bytes(224) > 224 * 32
