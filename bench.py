@@ -113,16 +113,19 @@ def main():
     plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
-    stream = torch.cuda.current_stream()
-    J = plan.num_stages - 2
+    nl = plan.num_launches
+    J = nl - 4
     fl = stage_flops(shapes, J)
+    info = [plan.launch_info(i) for i in range(nl)]
+    # kernel of each launch slot (squaring levels share one kernel)
+    names = ["gram_wide", "gram_tall"] + ["square"] * J + ["product_wide", "product_tall"]
 
     for _ in range(args.warmup):
         plan.orthogonalize_batched(Ms, Ys, ws)
     torch.cuda.synchronize()
     log("warmup done")
 
-    # graph replay (no stage events)
+    # graph replay (no events)
     torch.cuda.synchronize()
     tg0 = time.perf_counter()
     for _ in range(args.warmup):
@@ -130,12 +133,11 @@ def main():
     torch.cuda.synchronize()
     graph_ms = (time.perf_counter() - tg0) / max(args.warmup, 1) * 1e3
 
-    # the timed region: K steps, HIP events before every stage
-    ns = plan.num_stages
+    # the timed region: K steps, a HIP event before every launch slot and one after the last
     evs = []
     for _ in range(args.steps):
         row = []
-        for _ in range(ns + 1):
+        for _ in range(nl + 1):
             e = ctypes.c_void_p()
             assert hip.hipEventCreate(ctypes.byref(e)) == 0
             row.append(e.value)
@@ -143,33 +145,38 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        plan.stage_events(evs[k])
+        plan.launch_events(evs[k])
         plan.orthogonalize_batched(Ms, Ys, ws)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps: {elapsed:.3f} s")
-    stage_ms = np.zeros((args.steps, ns))
+    slot_ms = np.zeros((args.steps, nl))
     f = ctypes.c_float()
     for k in range(args.steps):
-        for i in range(ns):
+        for i in range(nl):
             assert hip.hipEventElapsedTime(ctypes.byref(f), evs[k][i], evs[k][i + 1]) == 0
-            stage_ms[k, i] = f.value
+            slot_ms[k, i] = f.value
     for row in evs:
         for e in row:
             hip.hipEventDestroy(e)
-    per = stage_ms.mean(axis=0)
-    kern = {"gram": (per[0], 1, fl["gram"]), "square": (per[1:1 + J].sum(), J, fl["square"]),
-            "product": (per[-1], 1, fl["product"])}
+    per = slot_ms.mean(axis=0)
+    kern = {}
+    for i, nm in enumerate(names):
+        t, n_l, flop = kern.get(nm, (0.0, 0, 0.0))
+        if info[i][1] > 0:
+            kern[nm] = (t + per[i], n_l + 1, flop + info[i][1])
     dom = max(kern, key=lambda k: kern[k][0])
     dur_ms = kern[dom][0] / kern[dom][1]
-    achieved = kern[dom][2] / (dur_ms * 1e-3) / 1e12
+    flop_per_launch = kern[dom][2] / kern[dom][1]
+    achieved = flop_per_launch / (dur_ms * 1e-3) / 1e12
     ms_per_step = elapsed / args.steps * 1e3
     value = n * args.steps / elapsed
     step_tflops = fl["step"] / (ms_per_step * 1e-3) / 1e12
 
     extra = {"graph_ms_per_step": round(graph_ms, 3),
-             "stage_ms": {"gram": round(per[0], 3), "square_per_level": [round(x, 3) for x in per[1:1 + J]],
-                          "product": round(per[-1], 3)},
+             "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
+                             "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 else None}
+                         for k, v in kern.items()},
              "algorithmic_tflop_per_step": round(fl["step"] / 1e12, 2),
              "mfma_util": round(step_tflops / PEAK_BF16_TFLOPS, 4)}
 

@@ -124,18 +124,24 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
                                          void *const *Y, const int64_t *ldy, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
-/* Number of kernel launches (stages) of one call of this plan: the Gram, one per
- * squaring level, and the product (J + 2 where 2^J is the largest exponent), or a
- * negative status for a NULL plan. */
-int32_t ifnso_plan_num_stages(ifnso_plan_t plan);
+/* Launch slots of one call of this plan, in order: Gram for the problems with rows <= cols,
+ * Gram for the transposed (rows > cols) problems, one squaring per level, then the product for
+ * the two groups in the same order: J + 4 slots where 2^J is the largest exponent. A slot with
+ * no work in a call launches nothing. Returns the count, or a negative status for NULL. */
+int32_t ifnso_plan_num_launches(ifnso_plan_t plan);
 
-/* Measurement hook: the next ifnso_orthogonalize / ifnso_orthogonalize_batched call of
- * this plan records events[i] (hipEvent_t handles created by the caller with timing
- * enabled) on its stream just before stage i, and events[num_stages] after the last
- * stage; that call enqueues its stages directly instead of replaying the graph. count must
- * equal ifnso_plan_num_stages(plan) + 1; count 0 cancels a pending request.
+/* Stage of launch slot i (0 Gram, 1 squaring, 2 product) and its algorithmic flop count:
+ * h^2 w per problem for the Gram (symmetric), h^3 per problem for a squaring (symmetric),
+ * 2 h^2 w per problem for the product. Errors: INVALID_ARGUMENT. */
+ifnso_status ifnso_plan_launch_info(ifnso_plan_t plan, int32_t i, int32_t *stage, double *flops);
+
+/* Measurement hook: the next ifnso_orthogonalize / ifnso_orthogonalize_batched call of this
+ * plan records events[i] (hipEvent_t handles created by the caller with timing enabled) on its
+ * stream just before launch slot i, and events[num_launches] after the last slot; that call
+ * enqueues its kernels directly instead of replaying the graph. count must equal
+ * ifnso_plan_num_launches(plan) + 1; count 0 cancels a pending request.
  * Errors: INVALID_ARGUMENT. */
-ifnso_status ifnso_plan_stage_events(ifnso_plan_t plan, void *const *events, int32_t count);
+ifnso_status ifnso_plan_launch_events(ifnso_plan_t plan, void *const *events, int32_t count);
 
 /* Classical Newton-Schulz with one odd quintic per step, Eq. (iteration_jordan):
  *   X_0 = A / ||A||_F,  X_{k+1} = a X_k + (b G_k + c G_k^2) X_k,  G_k = X_k X_k^T,

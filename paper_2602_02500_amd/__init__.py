@@ -81,10 +81,12 @@ def load() -> ctypes.CDLL:
     L.ifnso_orth_error.argtypes = [i32, ctypes.POINTER(vp), P64, P64, P64, i32, vp, vp, sz, vp]
     L.ifnso_orth_error_workspace_bytes.argtypes = [i32]
     L.ifnso_orth_error_workspace_bytes.restype = sz
-    L.ifnso_plan_num_stages.argtypes = [vp]
-    L.ifnso_plan_num_stages.restype = i32
-    L.ifnso_plan_stage_events.argtypes = [vp, ctypes.POINTER(vp), i32]
-    L.ifnso_plan_stage_events.restype = ctypes.c_int
+    L.ifnso_plan_num_launches.argtypes = [vp]
+    L.ifnso_plan_num_launches.restype = i32
+    L.ifnso_plan_launch_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.ifnso_plan_launch_info.restype = ctypes.c_int
+    L.ifnso_plan_launch_events.argtypes = [vp, ctypes.POINTER(vp), i32]
+    L.ifnso_plan_launch_events.restype = ctypes.c_int
     L.ifnso_last_error.restype = ctypes.c_char_p
     for name in ("ifnso_plan", "ifnso_plan_workspace_bytes", "ifnso_plan_destroy", "ifnso_orthogonalize",
                  "ifnso_orthogonalize_batched", "ifnso_classical_ns", "ifnso_orth_error"):
@@ -172,14 +174,20 @@ class Plan:
         _check(self._L.ifnso_orthogonalize_batched(self._h, mp, ldm, yp, ldy, _ptr(workspace), nb, _stream(stream)))
 
     @property
-    def num_stages(self) -> int:
-        return int(self._L.ifnso_plan_num_stages(self._h))
+    def num_launches(self) -> int:
+        return int(self._L.ifnso_plan_num_launches(self._h))
 
-    def stage_events(self, events):
-        """Events (raw hipEvent_t handles) for the next call: one before each stage and one after."""
+    def launch_info(self, i: int):
+        """(stage, algorithmic flops) of launch slot i; stage 0 Gram, 1 squaring, 2 product."""
+        st, fl = ctypes.c_int32(), ctypes.c_double()
+        _check(self._L.ifnso_plan_launch_info(self._h, int(i), ctypes.byref(st), ctypes.byref(fl)))
+        return int(st.value), float(fl.value)
+
+    def launch_events(self, events):
+        """Events (raw hipEvent_t handles) for the next call: one before each slot and one after."""
         n = len(events)
         arr = (ctypes.c_void_p * max(n, 1))(*[int(e) for e in events])
-        _check(self._L.ifnso_plan_stage_events(self._h, arr, n))
+        _check(self._L.ifnso_plan_launch_events(self._h, arr, n))
 
     def destroy(self):
         if getattr(self, "_h", None):

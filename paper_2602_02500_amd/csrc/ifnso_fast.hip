@@ -1,0 +1,686 @@
+// Fast bfloat16 stage kernels for gfx950: 256 x 256 output tiles, 64-deep K steps.
+//
+// Operands are read through buffer resource descriptors: an out-of-range chunk gets an
+// offset past the descriptor's record count and reads as zero, so edge tiles need no
+// branches (the host routes a problem here only when its rows are 16-byte aligned and its
+// column count is a multiple of 8, so every 16-byte chunk is wholly in or out of range).
+// K-contiguous operands go straight from HBM into LDS (buffer_load ... lds, 16 bytes per
+// lane); the XOR swizzle of the LDS rows is applied on the global side, since a wave's
+// LDS-DMA writes land contiguously. Operands whose M/N index is contiguous are loaded
+// into registers, transposed in 8 x 8 blocks, and written to LDS. Two LDS stages: the loads
+// of step k+1 are in flight while step k runs its 64 MFMAs per wave
+// (v_mfma_f32_32x32x16_bf16; each wave owns a 128 x 128 block, 256 AGPR accumulators).
+// Epilogues stage the float32 tile through LDS (half a tile at a time) so that stores of
+// the tile, of its mirror and of the float32 running sum are 16-byte vector accesses.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ifnso_common.hpp"
+#include "ifnso_launch.hpp"
+#include "ifnso_tile.hpp"
+
+namespace ifnso {
+namespace fast {
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int BM = 256, BN = 256, BK = 64;
+constexpr int WM = 128, WN = 128, FM = 4, FN = 4;
+constexpr int STAGE_BYTES = (BM + BN) * 128;  // 64 KiB
+constexpr int LDS_BYTES = 2 * STAGE_BYTES;    // 128 KiB
+constexpr uint32_t OOB = 0x80000000u;
+constexpr int EP_LD = BN + 8;                 // float stride of the epilogue staging rows
+constexpr int EP_BYTES = 128 * EP_LD * 4;
+constexpr int SMEM_BYTES = LDS_BYTES > EP_BYTES ? LDS_BYTES : EP_BYTES;  // 132 KiB
+
+// Values that are the same in every lane (per-task problem fields loaded from memory) are
+// moved to scalar registers, so buffer descriptors and loop bounds stay in SGPRs.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ const void *uni(const void *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (const void *)(((uint64_t)hi << 32) | lo);
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(uni(p)), (short)0, (int)uni(bytes), 0x00020000);
+}
+
+// The same descriptor as four scalar words (base, stride 0, record count, gfx9 format word).
+__device__ __forceinline__ i32x4 rsrc_words(const void *p, uint32_t bytes) {
+  const uint64_t a = (uint64_t)uni(p);
+  i32x4 r;
+  r[0] = (int)(uint32_t)a;
+  r[1] = (int)((uint32_t)(a >> 32) & 0xffffu);
+  r[2] = (int)uni(bytes);
+  r[3] = 0x00020000;
+  return r;
+}
+
+// One 16-byte-per-lane load from a buffer straight into LDS at byte offset `lds` (wave-uniform;
+// lane i lands at lds + 16 i). Written as a two-instruction sequence so that the compiler's
+// wait-count pass does not order every later LDS read behind it: the K loop waits for these
+// loads itself (wait_vmcnt + barrier) before it reads the stage they fill. The s_nop is the
+// one wait state required between an SALU write of M0 and an LDS-DMA load; the load has no
+// register results.
+__device__ __forceinline__ void dma16(const i32x4 &r, uint32_t voff, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+               :
+               : "s"(lds), "v"(voff), "s"(r)
+               : "memory", "m0");
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void *)p; }
+
+__device__ __forceinline__ int swz(int row) { return (row ^ (row >> 3)) & 7; }
+
+// ---------------------------------------------------------------------------------------------
+// operand loaders
+// ---------------------------------------------------------------------------------------------
+// K-major operand of ROWS rows straight into LDS: wave-instruction g covers rows 8g..8g+7.
+template <int ROWS>
+__device__ __forceinline__ void issue_kmaj(uint32_t lt, const i32x4 &r, uint32_t ld_bytes, int m0, int mlim, int k0,
+                                           int klim) {
+  const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < ROWS / 32; i++) {
+    const int g = i * 4 + wave;
+    const int row = g * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ swz(row);
+    const int m = m0 + row, k = k0 + c * 8;
+    const uint32_t off = (m < mlim && k < klim) ? (uint32_t)m * ld_bytes + (uint32_t)k * 2u : OOB;
+    dma16(r, off, lt + g * 1024);
+  }
+}
+
+// MN-major operand (element (m, k) at k*ld + m): one 8(k) x 8(m) block per thread.
+template <int ROWS>
+__device__ __forceinline__ void load_mnmaj(uint4 (&v)[8], __amdgpu_buffer_rsrc_t r, uint32_t ld_bytes, int m0,
+                                           int mlim, int k0, int klim) {
+  constexpr int MB = ROWS / 8, NB = MB * 8;
+  const int blk = threadIdx.x;
+  const int mb = blk % MB, kb = blk / MB;
+  const int m = m0 + mb * 8;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int k = k0 + kb * 8 + i;
+    const uint32_t off = (blk < NB && m < mlim && k < klim) ? (uint32_t)k * ld_bytes + (uint32_t)m * 2u : OOB;
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    v[i] = make_uint4(x[0], x[1], x[2], x[3]);
+  }
+}
+
+template <int ROWS>
+__device__ __forceinline__ void store_mnmaj(const uint4 (&v)[8], char *lt) {
+  constexpr int MB = ROWS / 8, NB = MB * 8;
+  const int blk = threadIdx.x;
+  if (blk >= NB) return;
+  const int mb = blk % MB, kb = blk / MB;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const uint32_t a = w32(v[2 * e], j >> 1), c = w32(v[2 * e + 1], j >> 1);
+      o[e] = (j & 1) ? ((a >> 16) | (c & 0xffff0000u)) : ((a & 0xffffu) | (c << 16));
+    }
+    *(uint4 *)(lt + lds_off(mb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// float64 sum of squares of the A tile held in LDS (diagonal Gram tiles with K-major A).
+__device__ __forceinline__ double lds_sumsq(const char *At) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < BM * 8 / kThreads; i++) {
+    const uint4 q = *(const uint4 *)(At + (threadIdx.x + kThreads * i) * 16);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const double lo = (double)__uint_as_float(w[e] << 16), hi = (double)__uint_as_float(w[e] & 0xffff0000u);
+      s = fma(lo, lo, s);
+      s = fma(hi, hi, s);
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ double regs_sumsq(const uint4 (&v)[8]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const double lo = (double)__uint_as_float(w[e] << 16), hi = (double)__uint_as_float(w[e] & 0xffff0000u);
+      s = fma(lo, lo, s);
+      s = fma(hi, hi, s);
+    }
+  }
+  return s;
+}
+
+// vmcnt-only wait (expcnt and lgkmcnt left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// ---------------------------------------------------------------------------------------------
+// the 256 x 256 mainloop: acc = Aop[am0.., :K] * Bop[bn0.., :K]^T
+// ---------------------------------------------------------------------------------------------
+struct Operand {
+  __amdgpu_buffer_rsrc_t r;
+  i32x4 w;           // the same descriptor as words, for the LDS-DMA loads
+  uint32_t ld_bytes;
+  int lim;           // rows (M/N index) in range
+};
+
+__device__ __forceinline__ Operand make_operand(const void *p, uint32_t bytes, uint32_t ld_bytes, int lim) {
+  Operand o;
+  o.r = rsrc(p, bytes);
+  o.w = rsrc_words(p, bytes);
+  o.ld_bytes = uni(ld_bytes);
+  o.lim = uni(lim);
+  return o;
+}
+
+template <bool AMN, bool BMN>
+__device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
+                                           const Operand &B, int bn0, int K, bool want_norm) {
+  const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lg = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+  const int nk = (K + BK - 1) / BK;
+  double nrm = 0.0;
+  uint4 va[8], vb[8];
+  // loads issued per stage by one thread (K-major: ROWS/32 per operand)
+  constexpr int NDIRECT = (AMN ? 0 : BM / 32) + (BMN ? 0 : BN / 32);
+  const uint32_t lbase = uni(lds_addr(smem));
+  auto issue = [&](int kt, int buf) {
+    const uint32_t As = lbase + buf * STAGE_BYTES, Bs = As + BM * 128;
+    const int k0 = kt * BK;
+    if constexpr (!AMN) issue_kmaj<BM>(As, A.w, A.ld_bytes, am0, A.lim, k0, K);
+    if constexpr (!BMN) issue_kmaj<BN>(Bs, B.w, B.ld_bytes, bn0, B.lim, k0, K);
+    if constexpr (AMN) load_mnmaj<BM>(va, A.r, A.ld_bytes, am0, A.lim, k0, K);
+    if constexpr (BMN) load_mnmaj<BN>(vb, B.r, B.ld_bytes, bn0, B.lim, k0, K);
+  };
+  auto commit_regs = [&](int buf) {
+    char *As = smem + buf * STAGE_BYTES, *Bs = As + BM * 128;
+    if constexpr (AMN) {
+      if (want_norm) nrm += regs_sumsq(va);
+      store_mnmaj<BM>(va, As);
+    }
+    if constexpr (BMN) store_mnmaj<BN>(vb, Bs);
+  };
+  if (nk <= 0) return 0.0;
+  issue(0, 0);
+  commit_regs(0);
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) issue(kt + 1, cur ^ 1);
+    // this step's direct loads were issued one iteration earlier; the next step's are the
+    // newest NDIRECT (+ register loads) in flight
+    if constexpr (AMN || BMN) {
+      if (more) wait_vmcnt<NDIRECT + (AMN ? 8 : 0) + (BMN ? 8 : 0)>();
+      else wait_vmcnt<0>();
+    } else {
+      if (more) wait_vmcnt<NDIRECT>();
+      else wait_vmcnt<0>();
+    }
+    __syncthreads();
+    const char *As = smem + cur * STAGE_BYTES, *Bs = As + BM * 128;
+    if constexpr (!AMN) {
+      if (want_norm) nrm += lds_sumsq(As);
+    }
+    {
+      // fragments of K slice kk+1 are read from LDS while slice kk's 16 MFMAs run
+      // (one LDS read per two MFMAs)
+      bf16x8 fa[2][FM], fb[2][FN];
+      auto rd = [&](int kk, int sl) {
+#pragma unroll
+        for (int i = 0; i < FM; i++) fa[sl][i] = *(const bf16x8 *)(As + lds_off(wm * WM + i * 32 + lr, 2 * kk + lg));
+#pragma unroll
+        for (int j = 0; j < FN; j++) fb[sl][j] = *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
+      };
+      rd(0, 0);
+#pragma unroll
+      for (int kk = 0; kk < BK / 16; kk++) {
+        const int sl = kk & 1;
+        if (kk + 1 < BK / 16) rd(kk + 1, sl ^ 1);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int j = 0; j < FN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][i], fb[sl][j], acc[i][j], 0, 0, 0);
+        if (kk + 1 < BK / 16) {
+#pragma unroll
+          for (int q = 0; q < FM + FN; q++) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
+          }
+        }
+      }
+    }
+    if (more) commit_regs(cur ^ 1);
+    __syncthreads();
+  }
+  return nrm;
+}
+
+// ---------------------------------------------------------------------------------------------
+// epilogue staging: half a tile (rows half*128 .. +127) of float32 in LDS
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void stage_half(const f32x16 (&acc)[FM][FN], float *ep, int half) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  if (wm != half) return;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wn * WN + j * 32 + (lane & 31);
+        ep[row * EP_LD + col] = acc[i][j][r];
+      }
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  return (uint32_t)f32_to_bf16(a) | ((uint32_t)f32_to_bf16(b) << 16);
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-problem scalars (same definitions as the generic kernels)
+// ---------------------------------------------------------------------------------------------
+struct FScalars {
+  double nA2, g2, sg, sout;
+  bool zero;
+};
+
+__device__ __forceinline__ FScalars scalars(const ProbDev &P, int norm) {
+  FScalars s;
+  s.nA2 = wave_sum(P.norm_part, P.nt);
+  s.g2 = wave_sum_upper(P.lvl_part + (int64_t)1 * P.nt * P.nt, P.nt);
+  s.zero = !(s.nA2 > 0.0);
+  if (norm == kFrob) {
+    s.sg = s.zero ? 0.0 : 1.0 / s.nA2;
+    s.sout = s.zero ? 0.0 : 1.0 / sqrt(s.nA2);
+  } else if (norm == kGramFrob) {
+    const double o = sqrt(s.g2);
+    s.sg = s.zero ? 0.0 : 1.0 / o;
+    s.sout = s.zero ? 0.0 : 1.0 / sqrt(o);
+  } else {
+    s.sg = 1.0;
+    s.sout = 1.0;
+  }
+  return s;
+}
+
+__device__ __forceinline__ double pow2_inv_round(double nb) {
+  if (!(nb > 0.0) || !isfinite(nb)) return 1.0;
+  return exp2(-rint(log2(nb)));
+}
+
+__device__ __forceinline__ double level_scale(const ProbDev &P, double sg, int level) {
+  double S = sg;
+  const int64_t nt2 = (int64_t)P.nt * P.nt;
+  for (int l = 1; l < level; l++) {
+    const double F = pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+    S = S * S / F;
+  }
+  return S;
+}
+
+__device__ __forceinline__ Task decode_upper(int t, int nt) {
+  int tm = 0;
+  while (t >= nt - tm) {
+    t -= nt - tm;
+    tm++;
+  }
+  return Task{0, tm, tm + t, 0};
+}
+
+__device__ __forceinline__ Task fetch(const StageArgs &a, int t, int stage) {
+  if (a.tasks) return a.tasks[t];
+  const ProbDev &P = a.one;
+  if (stage != kStageProduct) return decode_upper(t, P.hp / BM);
+  const int ncols = ((P.trans ? P.h : P.w) + BN - 1) / BN;
+  return Task{0, t / ncols, t % ncols, 0};
+}
+
+__device__ __forceinline__ const ProbDev &prob(const StageArgs &a, const Task &t) {
+  return a.tasks ? a.probs[t.p] : a.one;
+}
+
+// Partials of a 256 tile land in the 128-granular arrays: slot (2tm, 2tn) gets the value,
+// the other covered upper slots get 0, so consumers sum the same grid as for 128 tiles.
+__device__ __forceinline__ void write_level_partials(const ProbDev &P, int level, const Task &t, double lv, double dg) {
+  const int nt = P.nt;
+  double *lp = P.lvl_part + (int64_t)level * nt * nt;
+  const int r0 = 2 * t.tm, c0 = 2 * t.tn;
+  lp[r0 * nt + c0] = lv;
+  lp[r0 * nt + c0 + 1] = 0.0;
+  lp[(r0 + 1) * nt + c0 + 1] = 0.0;
+  if (t.tm != t.tn) lp[(r0 + 1) * nt + c0] = 0.0;
+  if (t.tm == t.tn) {
+    P.diag_part[level * nt + r0] = dg;
+    P.diag_part[level * nt + r0 + 1] = 0.0;
+  }
+}
+
+// Writes the staged half tile (rows half*128..) as bfloat16 into dst (ld hp) at the tile and,
+// off the diagonal, at its mirror. `f` maps the staged float to the stored value.
+template <typename F>
+__device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, int64_t hp, int m0, int n0, int half,
+                                              bool diag, F f) {
+  // direct: 128 rows x 32 chunks of 8
+  for (int q = threadIdx.x; q < 128 * 32; q += kThreads) {
+    const int row = q >> 5, c8 = (q & 31) * 8;
+    const float *src = ep + row * EP_LD + c8;
+    uint4 o;
+    o.x = pack_bf16x2(f(src[0], row, c8 + 0), f(src[1], row, c8 + 1));
+    o.y = pack_bf16x2(f(src[2], row, c8 + 2), f(src[3], row, c8 + 3));
+    o.z = pack_bf16x2(f(src[4], row, c8 + 4), f(src[5], row, c8 + 5));
+    o.w = pack_bf16x2(f(src[6], row, c8 + 6), f(src[7], row, c8 + 7));
+    *(uint4 *)(dst + (int64_t)(m0 + half * 128 + row) * hp + n0 + c8) = o;
+  }
+  if (diag) return;
+  // mirror: element (row, col) of the tile goes to (n0 + col, m0 + row); 256 mirror rows x
+  // 16 chunks of 8 consecutive tile rows
+  for (int q = threadIdx.x; q < 256 * 16; q += kThreads) {
+    const int col = q >> 4, r8 = (q & 15) * 8;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[e] = f(ep[(r8 + e) * EP_LD + col], r8 + e, col);
+    uint4 o;
+    o.x = pack_bf16x2(v[0], v[1]);
+    o.y = pack_bf16x2(v[2], v[3]);
+    o.z = pack_bf16x2(v[4], v[5]);
+    o.w = pack_bf16x2(v[6], v[7]);
+    *(uint4 *)(dst + (int64_t)(n0 + col) * hp + m0 + half * 128 + r8) = o;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Gram
+// ---------------------------------------------------------------------------------------------
+template <bool TRANS>
+__global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  float *ep = (float *)smem;
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    Task task = fetch(a, t, kStageGram);
+    task.p = uni(task.p);
+    task.tm = uni(task.tm);
+    task.tn = uni(task.tn);
+    const ProbDev &P = prob(a, task);
+    const int m0 = task.tm * BM, n0 = task.tn * BN;
+    const bool diag = task.tm == task.tn;
+    const uint32_t mbytes = (uint32_t)(((int64_t)(P.trans ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(P.trans ? P.h : P.w) * 2);
+    const Operand op = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.h);
+    const int K = uni(P.w);
+    f32x16 acc[FM][FN];
+    double nrm;
+    const double nrm_t = mainloop<TRANS, TRANS>(acc, smem, op, m0, op, n0, K, diag);
+    nrm = nrm_t;
+    uint16_t *dst = (uint16_t *)P.opnd[0];
+    const int64_t hp = P.hp;
+    const bool keep_f32 = a.J >= 1 || a.learned;
+    double lv = 0.0, dg = 0.0;
+    for (int half = 0; half < 2; half++) {
+      stage_half(acc, ep, half);
+      __syncthreads();
+      emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+      // float32 upper tile, partial sums
+      for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
+        const int row = q >> 6, c4 = (q & 63) * 4;
+        const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
+        if (keep_f32) *(float4 *)(P.accf + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4) = v;
+        const double w = diag ? 1.0 : 2.0;
+        lv += w * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w);
+        if (diag) {
+          const int d = half * 128 + row - c4;
+          if (d >= 0 && d < 4) dg += (double)(d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w);
+        }
+      }
+      __syncthreads();
+    }
+    if (!diag) nrm = 0.0;
+    block_sum3(lv, dg, nrm, (double *)smem);
+    if (threadIdx.x == 0) {
+      write_level_partials(P, 1, task, lv, dg);
+      if (diag) {
+        P.norm_part[2 * task.tm] = nrm;
+        P.norm_part[2 * task.tm + 1] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// squaring (Gram basis and complement basis): level -> level + 1
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  float *ep = (float *)smem;
+  const int level = a.level;
+  int cur_p = -1;
+  float f_out = 1.f, c_acc = 0.f, c_first = 0.f, alpha = 1.f, c_next = 0.f, dscale = 1.f;
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    Task task = fetch(a, t, kStageSquare);
+    task.p = uni(task.p);
+    task.tm = uni(task.tm);
+    task.tn = uni(task.tn);
+    const ProbDev &P = prob(a, task);
+    if (task.p != cur_p) {
+      cur_p = task.p;
+      const FScalars sc = scalars(P, a.norm);
+      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      if (a.basis == kGram) {
+        const double S = level_scale(P, sc.sg, level);
+        f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt));
+        c_acc = (float)(P.coef[level + 1] * S * S);
+        c_first = (float)(P.coef[1] * sc.sg);
+      } else {
+        alpha = (float)(level == 1 ? sc.sg * sc.sg : 1.0);
+        dscale = (float)(-sc.sg);
+        c_next = (float)P.coef[level + 1];
+        c_first = (float)P.coef[1];
+      }
+    }
+    const int m0 = task.tm * BM, n0 = task.tn * BN;
+    const bool diag = task.tm == task.tn;
+    const int64_t hp = P.hp;
+    const uint32_t bytes = (uint32_t)(hp * hp * 2);
+    const Operand op = make_operand(P.opnd[(level - 1) & 1], bytes, (uint32_t)(hp * 2), P.hp);
+    f32x16 acc[FM][FN];
+    mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
+    uint16_t *dst = (uint16_t *)P.opnd[level & 1];
+    const bool last = a.last;
+    double lv = 0.0, dg = 0.0, unused = 0.0;
+    for (int half = 0; half < 2; half++) {
+      stage_half(acc, ep, half);
+      __syncthreads();
+      // pass 1 (row-wise, upper tile): new level value `out`, running sum P; the staged value
+      // is replaced by what is stored (out, or P on the last level) for the bf16 emit.
+      for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
+        const int row = q >> 6, c4 = (q & 63) * 4;
+        float *sp = ep + row * EP_LD + c4;
+        const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
+        const float4 accv = *(const float4 *)sp;
+        float4 outv, pv;
+        if (a.basis == kGram) {
+          const float4 pin = *(const float4 *)(P.accf + gi);
+          outv = make_float4(f_out * accv.x, f_out * accv.y, f_out * accv.z, f_out * accv.w);
+          const float sp0 = level == 1 ? c_first : 1.f;
+          pv = make_float4(sp0 * pin.x + c_acc * accv.x, sp0 * pin.y + c_acc * accv.y, sp0 * pin.z + c_acc * accv.z,
+                           sp0 * pin.w + c_acc * accv.w);
+        } else {
+          float4 dprev;
+          if (level == 1) {
+            const float4 g = *(const float4 *)(P.accf + gi);
+            dprev = make_float4(dscale * g.x, dscale * g.y, dscale * g.z, dscale * g.w);
+          } else {
+            dprev = *(const float4 *)(P.df[level & 1] + gi);
+          }
+          outv = make_float4(2.f * dprev.x + alpha * accv.x, 2.f * dprev.y + alpha * accv.y,
+                             2.f * dprev.z + alpha * accv.z, 2.f * dprev.w + alpha * accv.w);
+          float4 pin = level == 1 ? make_float4(c_first * dprev.x, c_first * dprev.y, c_first * dprev.z, c_first * dprev.w)
+                                  : *(const float4 *)(P.accf + gi);
+          pv = make_float4(pin.x + c_next * outv.x, pin.y + c_next * outv.y, pin.z + c_next * outv.z,
+                           pin.w + c_next * outv.w);
+          if (!last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
+        }
+        if (!last) *(float4 *)(P.accf + gi) = pv;
+        const double w = diag ? 1.0 : 2.0;
+        lv += w * ((double)outv.x * outv.x + (double)outv.y * outv.y + (double)outv.z * outv.z +
+                   (double)outv.w * outv.w);
+        if (diag) {
+          const int d = half * 128 + row - c4;
+          if (d >= 0 && d < 4) dg += (double)(d == 0 ? outv.x : d == 1 ? outv.y : d == 2 ? outv.z : outv.w);
+        }
+        *(float4 *)sp = last ? pv : outv;
+      }
+      __syncthreads();
+      emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+      __syncthreads();
+    }
+    block_sum3(lv, dg, unused, (double *)smem);
+    if (threadIdx.x == 0) write_level_partials(P, level + 1, task, lv, dg);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// product: Y = s (c0 A + P A) in M's orientation (IFNSO only)
+// ---------------------------------------------------------------------------------------------
+template <bool TRANS>
+__global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, const int out_bf16) {
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  float *ep = (float *)smem;
+  int cur_p = -1;
+  float sc0 = 0.f, sps = 0.f;
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    Task task = fetch(a, t, kStageProduct);
+    task.p = uni(task.p);
+    task.tm = uni(task.tm);
+    task.tn = uni(task.tn);
+    const ProbDev &P = prob(a, task);
+    if (task.p != cur_p) {
+      cur_p = task.p;
+      const FScalars sc = scalars(P, a.norm);
+      double c0, ps, sout = sc.sout;
+      if (P.h == 1) {
+        // a single row or column: the polynomial of the scalar Gram, in float64
+        const double g = (a.norm == kNone) ? sc.nA2 : 1.0;
+        sout = sc.zero ? 0.0 : (a.norm == kNone ? 1.0 : 1.0 / sqrt(sc.nA2));
+        const double b = (a.basis == kGram) ? g : 1.0 - g;
+        double v = 0.0;
+        for (int k = 0; k < kSlots; k++)
+          if (P.coef[k] != 0.0) v += P.coef[k] * pow(b, k == 0 ? 0.0 : exp2((double)(k - 1)));
+        c0 = v;
+        ps = 0.0;
+      } else if (a.basis == kGram) {
+        c0 = P.coef[0];
+        ps = (a.J == 0) ? P.coef[1] * sc.sg : 1.0;
+      } else {
+        c0 = 0.0;
+        for (int k = 0; k < kSlots; k++) c0 += P.coef[k];
+        ps = (a.J == 0) ? -P.coef[1] * sc.sg : 1.0;
+      }
+      if (sc.zero && a.norm != kNone) sout = 0.0;
+      sc0 = (float)(sout * c0);
+      sps = (float)(sout * ps);
+    }
+    const int64_t hp = P.hp;
+    const int m0 = task.tm * BM, n0 = task.tn * BN;
+    const uint32_t mbytes = (uint32_t)(((int64_t)(P.trans ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(P.trans ? P.h : P.w) * 2);
+    const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
+    const Operand Po = make_operand(P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
+    const int Kp = uni(P.h);
+    f32x16 acc[FM][FN];
+    const int rows_out = P.trans ? P.w : P.h, cols_out = P.trans ? P.h : P.w;
+    if (a.p_empty || P.h == 1) {
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+#pragma unroll
+          for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+    } else if constexpr (TRANS) {
+      // Y_out[n][i] = sum_k M[n][k] P[i][k]
+      mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
+    } else {
+      // Y[i][n] = sum_k P[i][k] M[k][n]
+      mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
+    }
+    const uint16_t *M = (const uint16_t *)P.M;
+    for (int half = 0; half < 2; half++) {
+      stage_half(acc, ep, half);
+      __syncthreads();
+      for (int q = threadIdx.x; q < 128 * 32; q += kThreads) {
+        const int row = q >> 5, c8 = (q & 31) * 8;
+        const int r = m0 + half * 128 + row, c = n0 + c8;
+        if (r >= rows_out || c >= cols_out) continue;
+        const float *src = ep + row * EP_LD + c8;
+        const uint4 xm = *(const uint4 *)(M + (int64_t)r * P.ldm + c);
+        const uint32_t xw[4] = {xm.x, xm.y, xm.z, xm.w};
+        float y[8];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          y[2 * e] = sc0 * __uint_as_float(xw[e] << 16) + sps * src[2 * e];
+          y[2 * e + 1] = sc0 * __uint_as_float(xw[e] & 0xffff0000u) + sps * src[2 * e + 1];
+        }
+        if (out_bf16) {
+          uint4 o = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]), pack_bf16x2(y[4], y[5]),
+                               pack_bf16x2(y[6], y[7]));
+          *(uint4 *)((uint16_t *)P.Y + (int64_t)r * P.ldy + c) = o;
+        } else {
+          float *yp = (float *)P.Y + (int64_t)r * P.ldy + c;
+          *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
+          *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace fast
+
+hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  if (stage == kStageGram) {
+    if (trans) hipLaunchKernelGGL(fast::kf_gram<true>, dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL(fast::kf_gram<false>, dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (stage == kStageSquare) {
+    hipLaunchKernelGGL(fast::kf_square, dim3(grid), dim3(kThreads), 0, s, a);
+  } else {
+    if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
+    else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
+  }
+  return hipGetLastError();
+}
+
+hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
+  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false>
+                 : stage == kStageSquare ? (const void *)fast::kf_square : (const void *)fast::kf_product<false>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
+}
+
+}  // namespace ifnso

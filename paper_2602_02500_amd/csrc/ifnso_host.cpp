@@ -169,10 +169,14 @@ struct ifnso_plan_s {
   std::vector<ProbLayout> lay;
   std::vector<size_t> ws_off;  // per-problem offset into the workspace
   size_t ws_bytes = 0;
-  // device schedule
+  // device schedule: generic (128 tiles) and fast (256 tiles, bfloat16) task lists
   Task *d_tasks = nullptr;
   int n_gram = 0, n_square = 0, n_prod = 0;
   size_t off_gram = 0, off_square = 0, off_prod = 0;
+  bool fast = false;  // bfloat16 plan whose squarings use the fast kernels
+  int nf_gram[2] = {0, 0}, nf_square = 0, nf_prod[2] = {0, 0};  // [0] wide, [1] tall
+  size_t offf_gram[2] = {0, 0}, offf_square = 0, offf_prod[2] = {0, 0};
+  double fl_gram[2] = {0, 0}, fl_square = 0, fl_prod[2] = {0, 0};  // algorithmic flops per launch
   double *d_coef = nullptr;   // [num][kSlots]
   double *d_stats = nullptr;  // [num][kStatsPerProblem]
   int grid[3] = {1, 1, 1};
@@ -184,7 +188,7 @@ struct ifnso_plan_s {
   bool ev_used[kSlotsRing] = {};
   int next_slot = 0;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[kSlotsRing] = {};
+  hipGraphExec_t gexec[2 * kSlotsRing] = {};  // per table slot, generic / fast I/O
   std::vector<hipEvent_t> stage_events;  // pending measurement request (one call)
   std::mutex mu;
 };
@@ -222,6 +226,9 @@ static ifnso_status validate_desc(const ifnso_poly_desc *d) {
   if (d->compute == IFNSO_COMPUTE_FP8_E4M3) return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute is not built");
   return IFNSO_OK;
 }
+
+static bool fast_enabled_impl();
+static bool fast_enabled() { return fast_enabled_impl(); }
 
 static int slot_of_exponent(int e) {
   if (e == 0) return 0;
@@ -315,6 +322,50 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   all.insert(all.end(), square.begin(), square.end());
   p->off_prod = all.size();
   all.insert(all.end(), prod.begin(), prod.end());
+  // fast lists (256 tiles): Gram and product split by orientation, one kernel each
+  p->fast = op == kOpBF16 && fast_enabled();
+  if (p->fast) {
+    for (int i = 0; i < num_problems; i++)
+      if (p->lay[i].hp > 32512) p->fast = false;  // h x h bfloat16 buffers stay below 2 GiB
+  }
+  if (p->fast) {
+    std::vector<Task> fg[2], fs, fp[2];
+    for (int i : order) {
+      const ProbLayout &L = p->lay[i];
+      const int nt = L.hp / kFastTS, tr = L.trans;
+      for (int tm = 0; tm < nt; tm++)
+        for (int tn = tm; tn < nt; tn++) {
+          fg[tr].push_back(Task{i, tm, tn, 0});
+          fs.push_back(Task{i, tm, tn, 0});
+        }
+      const int rt = ((tr ? L.w : L.h) + kFastTS - 1) / kFastTS, ct = ((tr ? L.h : L.w) + kFastTS - 1) / kFastTS;
+      for (int tm = 0; tm < rt; tm++)
+        for (int tn = 0; tn < ct; tn++) fp[tr].push_back(Task{i, tm, tn, 0});
+      const double h = L.h, w = L.w;
+      p->fl_gram[tr] += h * h * w;
+      p->fl_square += h * h * h;
+      p->fl_prod[tr] += 2 * h * h * w;
+    }
+    for (int t = 0; t < 2; t++) {
+      p->offf_gram[t] = all.size();
+      p->nf_gram[t] = (int)fg[t].size();
+      all.insert(all.end(), fg[t].begin(), fg[t].end());
+      p->offf_prod[t] = all.size();
+      p->nf_prod[t] = (int)fp[t].size();
+      all.insert(all.end(), fp[t].begin(), fp[t].end());
+    }
+    p->offf_square = all.size();
+    p->nf_square = (int)fs.size();
+    all.insert(all.end(), fs.begin(), fs.end());
+  } else {
+    for (int i = 0; i < num_problems; i++) {
+      const ProbLayout &L = p->lay[i];
+      const double h = L.h, w = L.w;
+      p->fl_gram[0] += h * h * w;
+      p->fl_square += h * h * h;
+      p->fl_prod[0] += 2 * h * h * w;
+    }
+  }
 
   auto cleanup = [&](ifnso_status s) {
     ifnso_plan_destroy(p);
@@ -359,8 +410,9 @@ extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
   int prev = 0;
   if (hipGetDevice(&prev) != hipSuccess) prev = 0;
   (void)hipSetDevice(p->device);
+  for (int g = 0; g < 2 * kSlotsRing; g++)
+    if (p->gexec[g]) (void)hipGraphExecDestroy(p->gexec[g]);
   for (int s = 0; s < kSlotsRing; s++) {
-    if (p->gexec[s]) (void)hipGraphExecDestroy(p->gexec[s]);
     if (p->ev[s]) {
       (void)hipEventSynchronize(p->ev[s]);
       (void)hipEventDestroy(p->ev[s]);
@@ -392,51 +444,87 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   return a;
 }
 
+// Launch slots of one call, in order: Gram (wide, tall), each squaring level, product (wide,
+// tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
+// slot i and ev[num_slots] after the last one, so empty slots read as zero time.
+static int num_slots(const ifnso_plan_s *p) { return p->J + 4; }
+
+// Problem-level check for the fast kernels: 16-byte aligned rows whose length is a multiple of
+// 8 elements, and an input small enough for 32-bit buffer offsets.
+static bool fast_io_ok(const ifnso_plan_s *p, const ProbDev &d, const ProbLayout &L) {
+  const int64_t cols = L.cols;
+  const size_t in_bytes = ((size_t)(L.rows - 1) * d.ldm + cols) * 2;
+  const int oes = p->out_dtype == IFNSO_F32 ? 4 : 2;
+  return cols % 8 == 0 && d.ldm % 8 == 0 && ((uintptr_t)d.M % 16) == 0 && in_bytes < (1ull << 31) &&
+         ((size_t)d.ldy * oes) % 16 == 0 && ((uintptr_t)d.Y % 16) == 0;
+}
+
 // Enqueues every stage of a plan on `s`, reading problems from `table` (batched) or `one`.
-// With `ev`, records ev[i] before stage i and ev[J + 2] after the last stage.
-static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, const ProbDev *one, hipStream_t s,
-                               const hipEvent_t *ev = nullptr) {
+static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, const ProbDev *one, bool fast_io,
+                               hipStream_t s, const hipEvent_t *ev = nullptr) {
   StageArgs a = base_args(p);
   const int outbf = p->out_dtype == IFNSO_BF16;
-  int ng, nsq, npr;
+  const int cus = p->cus;
+  const bool fast = p->fast;
+  hipError_t e;
+  int slot = 0;
+  auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[slot++], s) : hipSuccess; };
   if (one) {
     a.tasks = nullptr;
     a.one = *one;
-    const ProbLayout &L = p->lay[0];
-    ng = nsq = L.nt * (L.nt + 1) / 2;
-    const int rt = ((L.trans ? L.w : L.h) + kTS - 1) / kTS, ct = ((L.trans ? L.h : L.w) + kTS - 1) / kTS;
-    npr = rt * ct;
   } else {
     a.probs = table;
-    ng = p->n_gram;
-    nsq = p->n_square;
-    npr = p->n_prod;
   }
-  const int cus = p->cus;
-  hipError_t e;
-  int stage = 0;
-  auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[stage++], s) : hipSuccess; };
-  a.ntasks = ng;
-  if (!one) a.tasks = p->d_tasks + p->off_gram;
-  if ((e = mark()) != hipSuccess) return e;
-  e = launch_stage(p->op, kTS, kStageGram, a, grid_for(p->op, kStageGram, ng, cus), outbf, s);
-  if (e != hipSuccess) return e;
-  for (int lvl = 1; lvl <= p->J; lvl++) {
+  const ProbLayout *L0 = one ? &p->lay[0] : nullptr;
+  const int tr0 = L0 ? L0->trans : 0;
+  auto ntiles_sym = [&](int ts) { return (L0->hp / ts) * (L0->hp / ts + 1) / 2; };
+  auto ntiles_prod = [&](int ts) {
+    return (((L0->trans ? L0->w : L0->h) + ts - 1) / ts) * (((L0->trans ? L0->h : L0->w) + ts - 1) / ts);
+  };
+  // Gram
+  for (int t = 0; t < 2; t++) {
     if ((e = mark()) != hipSuccess) return e;
-    a.ntasks = nsq;
-    if (!one) a.tasks = p->d_tasks + p->off_square;
-    a.level = lvl;
-    a.last = lvl == p->J;
-    e = launch_stage(p->op, kTS, kStageSquare, a, grid_for(p->op, kStageSquare, nsq, cus), outbf, s);
+    if (fast && fast_io) {
+      a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
+      if (!one) a.tasks = p->d_tasks + p->offf_gram[t];
+      e = launch_fast_stage(kStageGram, t, a, std::min(a.ntasks, cus), outbf, s);
+    } else if (t == 0) {
+      a.ntasks = one ? ntiles_sym(kTS) : p->n_gram;
+      if (!one) a.tasks = p->d_tasks + p->off_gram;
+      e = launch_stage(p->op, kTS, kStageGram, a, grid_for(p->op, kStageGram, a.ntasks, cus), outbf, s);
+    }
     if (e != hipSuccess) return e;
   }
-  a.ntasks = npr;
-  if (!one) a.tasks = p->d_tasks + p->off_prod;
+  for (int lvl = 1; lvl <= p->J; lvl++) {
+    if ((e = mark()) != hipSuccess) return e;
+    a.level = lvl;
+    a.last = lvl == p->J;
+    if (fast) {
+      a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
+      if (!one) a.tasks = p->d_tasks + p->offf_square;
+      e = launch_fast_stage(kStageSquare, 0, a, std::min(a.ntasks, cus), outbf, s);
+    } else {
+      a.ntasks = one ? ntiles_sym(kTS) : p->n_square;
+      if (!one) a.tasks = p->d_tasks + p->off_square;
+      e = launch_stage(p->op, kTS, kStageSquare, a, grid_for(p->op, kStageSquare, a.ntasks, cus), outbf, s);
+    }
+    if (e != hipSuccess) return e;
+  }
   a.level = 0;
   a.last = 0;
-  if ((e = mark()) != hipSuccess) return e;
-  e = launch_stage(p->op, kTS, kStageProduct, a, grid_for(p->op, kStageProduct, npr, cus), outbf, s);
-  if (e != hipSuccess) return e;
+  for (int t = 0; t < 2; t++) {
+    if ((e = mark()) != hipSuccess) return e;
+    if (fast && fast_io) {
+      a.ntasks = one ? (t == tr0 ? ntiles_prod(kFastTS) : 0) : p->nf_prod[t];
+      if (!one) a.tasks = p->d_tasks + p->offf_prod[t];
+      e = launch_fast_stage(kStageProduct, t, a, std::min(a.ntasks, cus), outbf, s);
+    } else if (t == 0) {
+      a.ntasks = one ? ntiles_prod(kTS) : p->n_prod;
+      if (!one) a.tasks = p->d_tasks + p->off_prod;
+      e = launch_stage(p->op, kTS, kStageProduct, a, grid_for(p->op, kStageProduct, a.ntasks, cus), outbf, s);
+    }
+    if (e != hipSuccess) return e;
+  }
   return mark();
 }
 
@@ -451,6 +539,11 @@ static ifnso_status check_matrix_args(const ifnso_plan_s *p, int i, const void *
   if (ranges_overlap(M, matrix_bytes(L.rows, ldm, L.cols, ies), Y, matrix_bytes(L.rows, ldy, L.cols, oes)))
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: Y overlaps M", i);
   return IFNSO_OK;
+}
+
+static bool fast_enabled_impl() {
+  const char *v = getenv("IFNSO_FAST");
+  return !(v && v[0] == '0');
 }
 
 static bool use_graphs() {
@@ -485,7 +578,7 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
   if (single) {
     ProbDev one;
     fill_dev(one, p->lay[0], base + p->ws_off[0], M[0], ldm[0], Y[0], ldy[0], p->op, p->d_coef, p->d_stats);
-    HIP_TRY(enqueue_plan(p, nullptr, &one, s, evp));
+    HIP_TRY(enqueue_plan(p, nullptr, &one, p->fast && fast_io_ok(p, one, p->lay[0]), s, evp));
     return IFNSO_OK;
   }
   const int slot = p->next_slot;
@@ -495,44 +588,64 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
   for (int i = 0; i < p->num; i++)
     fill_dev(ht[i], p->lay[i], base + p->ws_off[i], M[i], ldm[i], Y[i], ldy[i], p->op,
              p->d_coef + (size_t)i * kSlots, p->d_stats + (size_t)i * kStatsPerProblem);
+  bool fast_io = p->fast;
+  for (int i = 0; i < p->num && fast_io; i++) fast_io = fast_io_ok(p, ht[i], p->lay[i]);
   HIP_TRY(hipMemcpyAsync(p->d_table[slot], ht, (size_t)p->num * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+  const int gi = slot * 2 + (fast_io ? 1 : 0);
   if (use_graphs() && !evp) {
-    if (!p->gexec[slot]) {
+    if (!p->gexec[gi]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_plan(p, p->d_table[slot], nullptr, p->cap_stream);
+      hipError_t e = enqueue_plan(p, p->d_table[slot], nullptr, fast_io, p->cap_stream);
       hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return fail(IFNSO_ERR_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
       }
-      hipError_t e3 = hipGraphInstantiate(&p->gexec[slot], g, nullptr, nullptr, 0);
+      hipError_t e3 = hipGraphInstantiate(&p->gexec[gi], g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e3 != hipSuccess) return fail(IFNSO_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e3));
     }
-    HIP_TRY(hipGraphLaunch(p->gexec[slot], s));
+    HIP_TRY(hipGraphLaunch(p->gexec[gi], s));
   } else {
-    HIP_TRY(enqueue_plan(p, p->d_table[slot], nullptr, s, evp));
+    HIP_TRY(enqueue_plan(p, p->d_table[slot], nullptr, fast_io, s, evp));
   }
   HIP_TRY(hipEventRecord(p->ev[slot], s));
   p->ev_used[slot] = true;
   return IFNSO_OK;
 }
 
-extern "C" int32_t ifnso_plan_num_stages(ifnso_plan_t p) {
+extern "C" int32_t ifnso_plan_num_launches(ifnso_plan_t p) {
   if (!p) return -IFNSO_ERR_INVALID_ARGUMENT;
-  return p->J + 2;
+  return num_slots(p);
 }
 
-extern "C" ifnso_status ifnso_plan_stage_events(ifnso_plan_t p, void *const *events, int32_t count) {
+extern "C" ifnso_status ifnso_plan_launch_info(ifnso_plan_t p, int32_t i, int32_t *stage, double *flops) {
+  if (!p || !stage || !flops) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  const int n = num_slots(p);
+  if (i < 0 || i >= n) return fail(IFNSO_ERR_INVALID_ARGUMENT, "launch slot %d outside 0..%d", i, n - 1);
+  if (i < 2) {
+    *stage = kStageGram;
+    *flops = p->fl_gram[i];
+  } else if (i < 2 + p->J) {
+    *stage = kStageSquare;
+    *flops = p->fl_square;
+  } else {
+    *stage = kStageProduct;
+    *flops = p->fl_prod[i - 2 - p->J];
+  }
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_launch_events(ifnso_plan_t p, void *const *events, int32_t count) {
   if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
   std::lock_guard<std::mutex> lock(p->mu);
   if (count == 0) {
     p->stage_events.clear();
     return IFNSO_OK;
   }
-  if (!events || count != p->J + 3)
-    return fail(IFNSO_ERR_INVALID_ARGUMENT, "need %d events (stages + 1), got %d", p->J + 3, count);
+  const int need = num_slots(p) + 1;
+  if (!events || count != need) return fail(IFNSO_ERR_INVALID_ARGUMENT, "need %d events, got %d", need, count);
   for (int i = 0; i < count; i++)
     if (!events[i]) return fail(IFNSO_ERR_INVALID_ARGUMENT, "event %d is NULL", i);
   p->stage_events.assign((hipEvent_t *)events, (hipEvent_t *)events + count);

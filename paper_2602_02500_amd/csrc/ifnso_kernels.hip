@@ -140,7 +140,11 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
           const T tv = Elem<T>::from_f(v);
           op[i * hp + j] = tv;
           if (!diag) op[j * hp + i] = tv;
-          if (keep_f32) P.accf[i * hp + j] = v;
+          if (keep_f32) {
+            // both triangles: the 256-tile squaring kernels read whole diagonal 256 blocks
+            P.accf[i * hp + j] = v;
+            if (!diag) P.accf[j * hp + i] = v;
+          }
           const double dv = (double)v;
           lv = fma(dv, diag ? dv : 2.0 * dv, lv);
           if (i == j) dg += dv;

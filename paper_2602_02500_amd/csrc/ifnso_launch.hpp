@@ -24,6 +24,11 @@ struct OrthArgs {
 
 hipError_t launch_stage(int op, int ts, int stage, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
 hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu);
+// bfloat16 fast path, 256 x 256 tiles (see ifnso_fast.hip for the operand requirements)
+hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
+hipError_t fast_occupancy(int stage, int *blocks_per_cu);
+constexpr int kFastTS = 256;
+
 hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
 
 }  // namespace ifnso

@@ -244,3 +244,89 @@ def test_orth_error_float64(torch_dev):
     for g, m in zip(got, mats):
         ref = oracle.orth_error(m.astype(np.float32).astype(np.float64))
         assert abs(g - ref) <= 1e-10 * max(1.0, ref)
+
+
+# shapes whose rows are 16-byte aligned (cols % 8 == 0): the bfloat16 plans route the Gram and
+# the product through the 256-tile kernels; ragged 256-tile edges in both orientations
+FAST_SHAPES = [(512, 1536), (1536, 512), (264, 776), (776, 264), (8, 4096), (4096, 8), (256, 256)]
+
+
+@pytest.mark.parametrize("shape", FAST_SHAPES)
+def test_fast_path_shapes(torch_dev, shape):
+    torch, dev = torch_dev
+    M = gen.gaussian_np(*shape, seed=shape[0] + 3 * shape[1])
+    for exps, c in TERMS:
+        print(f"case fast shape={shape} exps={exps}", flush=True)
+        Y, vals = run_single(torch, dev, M, exps, c, compute="bf16")
+        r = _rel(Y, oracle.ifnso(vals, exps, c))
+        assert r <= TOL["bf16"], (exps, r)
+    for norm in ("gram_frobenius",):
+        exps, c = (0, 1, 2, 4), (1.3, -0.6, 0.4, 0.2)
+        Y, vals = run_single(torch, dev, M, exps, c, norm=norm, compute="bf16")
+        assert _rel(Y, oracle.ifnso(vals, exps, c, "gram", norm)) <= TOL["bf16"]
+    exps, c = (0, 1, 2, 4), (0.5, 0.3, 0.15, 0.05)
+    Y, vals = run_single(torch, dev, M, exps, c, basis="complement", norm="frobenius", compute="bf16")
+    assert _rel(Y, oracle.ifnso(vals, exps, c, "complement", "frobenius")) <= TOL["bf16"]
+
+
+def test_fast_path_f32_output(torch_dev):
+    torch, dev = torch_dev
+    import paper_2602_02500_amd as ifn
+    M = gen.gaussian_np(520, 1032, seed=77)
+    exps, c = configs.load_coeffs("gform_v1")
+    for shape_m in (M, M.T.copy()):
+        Y, vals = run_single(torch, dev, shape_m, exps, c, compute="bf16", out=ifn.F32)
+        assert _rel(Y, oracle.ifnso(vals, exps, c)) <= TOL["bf16"]
+
+
+def test_batched_aligned_shapes(torch_dev):
+    """A batch where every problem qualifies for the 256-tile Gram and product kernels."""
+    torch, dev = torch_dev
+    import paper_2602_02500_amd as ifn
+    shapes = [(256, 512), (512, 256), (128, 384), (512, 512), (64, 1024), (1024, 64), (264, 800), (1, 8)]
+    exps, c = configs.load_coeffs("gform_v1")
+    Ms, vals = [], []
+    for i, s in enumerate(shapes):
+        t, v = _to_dev(torch, dev, gen.gaussian_np(*s, seed=200 + i), "bf16")
+        Ms.append(t)
+        vals.append(v)
+    plan = ifn.Plan(exps, c, shapes, compute="bf16")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    for rep in range(3):
+        Ys = [torch.full_like(m, float("nan")) for m in Ms]
+        plan.orthogonalize_batched(Ms, Ys, ws)
+        torch.cuda.synchronize()
+        for Y, v in zip(Ys, vals):
+            r = _rel(Y.float().cpu().numpy().astype(np.float64), oracle.ifnso(v, exps, c))
+            assert r <= TOL["bf16"], (rep, v.shape, r)
+
+
+def test_launch_events_and_info(torch_dev):
+    """The measurement hook records one event per launch slot and the per-slot flop counts add
+    up to the algorithmic count of the call."""
+    torch, dev = torch_dev
+    import ctypes
+    import paper_2602_02500_amd as ifn
+    shapes = [(256, 512), (768, 256)]
+    exps, c = configs.load_coeffs("gform_v1")
+    plan = ifn.Plan(exps, c, shapes, compute="bf16")
+    n = plan.num_launches
+    assert n == 4 + 4
+    fl = [plan.launch_info(i) for i in range(n)]
+    total = sum(f for _, f in fl)
+    want = sum(min(s) ** 2 * max(s) * 3 + 4 * min(s) ** 3 for s in shapes)
+    assert abs(total - want) < 1e-6 * want
+    Ms = [_to_dev(torch, dev, gen.gaussian_np(*s, seed=5), "bf16")[0] for s in shapes]
+    Ys = [torch.empty_like(m) for m in Ms]
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    for e in evs:
+        e.record()  # creates the underlying HIP events
+    torch.cuda.synchronize()
+    plan.launch_events([e.cuda_event for e in evs])
+    plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    times = [evs[i].elapsed_time(evs[i + 1]) for i in range(n)]
+    assert all(t >= 0 for t in times) and sum(times) > 0
+    with pytest.raises(ifn.IfnsoError):
+        plan.launch_events([evs[0].cuda_event])
