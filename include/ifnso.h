@@ -125,14 +125,17 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
                                          size_t workspace_bytes, void *stream);
 
 /* Launch slots of one call of this plan, in order: Gram for the problems with rows <= cols,
- * Gram for the transposed (rows > cols) problems, one squaring per level, then the product for
- * the two groups in the same order: J + 4 slots where 2^J is the largest exponent. A slot with
- * no work in a call launches nothing. Returns the count, or a negative status for NULL. */
+ * Gram for the transposed (rows > cols) problems, one squaring per level, the aggregation of
+ * the weighted powers, then the product for the two groups in the same order: J + 5 slots
+ * where 2^J is the largest exponent. A slot with no work in a call launches nothing (the
+ * aggregation runs only when the levels are kept, i.e. bfloat16 Gram-basis plans with J >= 1).
+ * Returns the count, or a negative status for NULL. */
 int32_t ifnso_plan_num_launches(ifnso_plan_t plan);
 
-/* Stage of launch slot i (0 Gram, 1 squaring, 2 product) and its algorithmic flop count:
- * h^2 w per problem for the Gram (symmetric), h^3 per problem for a squaring (symmetric),
- * 2 h^2 w per problem for the product. Errors: INVALID_ARGUMENT. */
+/* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation) and its algorithmic
+ * flop count: h^2 w per problem for the Gram (symmetric), h^3 per problem for a squaring
+ * (symmetric), 2 h^2 w per problem for the product, 0 for the (memory-bound) aggregation.
+ * Errors: INVALID_ARGUMENT. */
 ifnso_status ifnso_plan_launch_info(ifnso_plan_t plan, int32_t i, int32_t *stage, double *flops);
 
 /* Measurement hook: the next ifnso_orthogonalize / ifnso_orthogonalize_batched call of this

@@ -34,8 +34,8 @@ struct ProbDev {
   double *stats;       // [IFNSO_STATS_PER_PROBLEM]
   void *xbuf[2];       // classical NS: h x w iterates (wide orientation), leading dim ldx
   int64_t ldx;
-  float *lvls;         // learned mode: float32 copies of each stored level (upper tiles)
-  int64_t lvl_stride;  // elements between levels in lvls
+  void *lv;            // level layout: level l (l = 1..J+1) stored at lv + (l-1) * lv_stride bytes,
+  int64_t lv_stride;   //   as a full symmetric h x h operand; level 1 later holds P
   int32_t pad_[2];
 };
 
@@ -59,6 +59,13 @@ struct StageArgs {
   double ns_abc[3];
   int32_t p_empty;     // product: no terms with exponent >= 1
   int32_t ns_steps;    // classical NS: total steps (used by the h == 1 scalar path)
+  // XCD-aware schedule (fast kernels): workgroup b runs on XCD b % 8 and works through that
+  // XCD's task queue tasks[xcd_off[x] .. + xcd_cnt[x]) with stride gridDim.x / 8
+  int32_t agg;         // level layout (Gram basis, fast path): levels kept, P formed by the
+                       // aggregate stage
+  int32_t xcd_sched;
+  int32_t xcd_off[8];
+  int32_t xcd_cnt[8];
   ProbDev one;         // the problem of a single-problem launch
 };
 

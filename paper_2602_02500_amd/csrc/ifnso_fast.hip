@@ -362,6 +362,21 @@ __device__ __forceinline__ Task fetch(const StageArgs &a, int t, int stage) {
   return Task{0, t / ncols, t % ncols, 0};
 }
 
+// Task iteration of a workgroup: either plain striding over the whole list, or the
+// workgroup's XCD queue (consecutive queue entries are tiles that share operand panels, so
+// the 32 workgroups of an XCD work on neighbouring tiles at the same time).
+struct TaskRange {
+  int base, start, stride, end;
+};
+
+__device__ __forceinline__ TaskRange task_range(const StageArgs &a) {
+  if (a.tasks && a.xcd_sched) {
+    const int x = blockIdx.x & 7, w = gridDim.x >> 3;
+    return TaskRange{a.xcd_off[x], (int)(blockIdx.x >> 3), w, a.xcd_cnt[x]};
+  }
+  return TaskRange{0, (int)blockIdx.x, (int)gridDim.x, a.ntasks};
+}
+
 __device__ __forceinline__ const ProbDev &prob(const StageArgs &a, const Task &t) {
   return a.tasks ? a.probs[t.p] : a.one;
 }
@@ -422,8 +437,9 @@ template <bool TRANS>
 __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
-  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
-    Task task = fetch(a, t, kStageGram);
+  const TaskRange tr = task_range(a);
+  for (int t = tr.start; t < tr.end; t += tr.stride) {
+    Task task = fetch(a, tr.base + t, kStageGram);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -439,7 +455,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
     nrm = nrm_t;
     uint16_t *dst = (uint16_t *)P.opnd[0];
     const int64_t hp = P.hp;
-    const bool keep_f32 = a.J >= 1 || a.learned;
+    const bool keep_f32 = (a.J >= 1 && !a.agg) || a.learned;
     double lv = 0.0, dg = 0.0;
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
@@ -475,14 +491,16 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
+template <bool AGG>
 __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
   const int level = a.level;
   int cur_p = -1;
   float f_out = 1.f, c_acc = 0.f, c_first = 0.f, alpha = 1.f, c_next = 0.f, dscale = 1.f;
-  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
-    Task task = fetch(a, t, kStageSquare);
+  const TaskRange tr = task_range(a);
+  for (int t = tr.start; t < tr.end; t += tr.stride) {
+    Task task = fetch(a, tr.base + t, kStageSquare);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -507,54 +525,92 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
     const bool diag = task.tm == task.tn;
     const int64_t hp = P.hp;
     const uint32_t bytes = (uint32_t)(hp * hp * 2);
-    const Operand op = make_operand(P.opnd[(level - 1) & 1], bytes, (uint32_t)(hp * 2), P.hp);
+    const void *srcp = AGG ? (const void *)((const char *)P.lv + (int64_t)(level - 1) * P.lv_stride)
+                           : (const void *)P.opnd[(level - 1) & 1];
+    const Operand op = make_operand(srcp, bytes, (uint32_t)(hp * 2), P.hp);
     f32x16 acc[FM][FN];
     mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
-    uint16_t *dst = (uint16_t *)P.opnd[level & 1];
+    uint16_t *dst = AGG ? (uint16_t *)((char *)P.lv + (int64_t)level * P.lv_stride) : (uint16_t *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
+    if constexpr (AGG) {
+      // level layout: store level+1 = f_out * acc (bf16, tile and mirror) and its partials
+      // (each thread's sum of a row segment in float32, accumulated in float64)
+      for (int half = 0; half < 2; half++) {
+        stage_half(acc, ep, half);
+        __syncthreads();
+        for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
+          const int row = q >> 6, c4 = (q & 63) * 4;
+          const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
+          const float x0 = f_out * v.x, x1 = f_out * v.y, x2 = f_out * v.z, x3 = f_out * v.w;
+          lv += (diag ? 1.0 : 2.0) * (double)(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
+          if (diag) {
+            const int d = half * 128 + row - c4;
+            if (d >= 0 && d < 4) dg += d == 0 ? x0 : d == 1 ? x1 : d == 2 ? x2 : x3;
+          }
+        }
+        const float fo = f_out;
+        emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [fo](float v, int, int) { return fo * v; });
+        __syncthreads();
+      }
+      block_sum3(lv, dg, unused, (double *)smem);
+      if (threadIdx.x == 0) write_level_partials(P, level + 1, task, lv, dg);
+      __syncthreads();
+      continue;
+    } else {
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
       // pass 1 (row-wise, upper tile): new level value `out`, running sum P; the staged value
-      // is replaced by what is stored (out, or P on the last level) for the bf16 emit.
-      for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
-        const int row = q >> 6, c4 = (q & 63) * 4;
-        float *sp = ep + row * EP_LD + c4;
-        const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
-        const float4 accv = *(const float4 *)sp;
-        float4 outv, pv;
-        if (a.basis == kGram) {
-          const float4 pin = *(const float4 *)(P.accf + gi);
-          outv = make_float4(f_out * accv.x, f_out * accv.y, f_out * accv.z, f_out * accv.w);
-          const float sp0 = level == 1 ? c_first : 1.f;
-          pv = make_float4(sp0 * pin.x + c_acc * accv.x, sp0 * pin.y + c_acc * accv.y, sp0 * pin.z + c_acc * accv.z,
-                           sp0 * pin.w + c_acc * accv.w);
-        } else {
-          float4 dprev;
-          if (level == 1) {
-            const float4 g = *(const float4 *)(P.accf + gi);
-            dprev = make_float4(dscale * g.x, dscale * g.y, dscale * g.z, dscale * g.w);
+      // is replaced by what is stored (out, or P on the last level) for the bf16 emit. The
+      // float32 reads of a batch are issued together (they do not wait on the batch's stores).
+      constexpr int PER = 128 * 64 / kThreads, BATCH = 8;
+      for (int b0 = 0; b0 < PER; b0 += BATCH) {
+        float4 pin[BATCH], dpv[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; u++) {
+          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int row = q >> 6, c4 = (q & 63) * 4;
+          const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
+          pin[u] = *(const float4 *)(P.accf + gi);
+          if (a.basis != kGram && level > 1) dpv[u] = *(const float4 *)(P.df[level & 1] + gi);
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; u++) {
+          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int row = q >> 6, c4 = (q & 63) * 4;
+          float *sp = ep + row * EP_LD + c4;
+          const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
+          const float4 accv = *(const float4 *)sp;
+          float4 outv, pv;
+          if (a.basis == kGram) {
+            outv = make_float4(f_out * accv.x, f_out * accv.y, f_out * accv.z, f_out * accv.w);
+            const float sp0 = level == 1 ? c_first : 1.f;
+            pv = make_float4(sp0 * pin[u].x + c_acc * accv.x, sp0 * pin[u].y + c_acc * accv.y,
+                             sp0 * pin[u].z + c_acc * accv.z, sp0 * pin[u].w + c_acc * accv.w);
           } else {
-            dprev = *(const float4 *)(P.df[level & 1] + gi);
+            const float4 dprev = level == 1 ? make_float4(dscale * pin[u].x, dscale * pin[u].y, dscale * pin[u].z,
+                                                          dscale * pin[u].w)
+                                            : dpv[u];
+            outv = make_float4(2.f * dprev.x + alpha * accv.x, 2.f * dprev.y + alpha * accv.y,
+                               2.f * dprev.z + alpha * accv.z, 2.f * dprev.w + alpha * accv.w);
+            const float4 p0 = level == 1 ? make_float4(c_first * dprev.x, c_first * dprev.y, c_first * dprev.z,
+                                                       c_first * dprev.w)
+                                         : pin[u];
+            pv = make_float4(p0.x + c_next * outv.x, p0.y + c_next * outv.y, p0.z + c_next * outv.z,
+                             p0.w + c_next * outv.w);
+            if (!last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
           }
-          outv = make_float4(2.f * dprev.x + alpha * accv.x, 2.f * dprev.y + alpha * accv.y,
-                             2.f * dprev.z + alpha * accv.z, 2.f * dprev.w + alpha * accv.w);
-          float4 pin = level == 1 ? make_float4(c_first * dprev.x, c_first * dprev.y, c_first * dprev.z, c_first * dprev.w)
-                                  : *(const float4 *)(P.accf + gi);
-          pv = make_float4(pin.x + c_next * outv.x, pin.y + c_next * outv.y, pin.z + c_next * outv.z,
-                           pin.w + c_next * outv.w);
-          if (!last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
+          if (!last) *(float4 *)(P.accf + gi) = pv;
+          const double w = diag ? 1.0 : 2.0;
+          lv += w * ((double)outv.x * outv.x + (double)outv.y * outv.y + (double)outv.z * outv.z +
+                     (double)outv.w * outv.w);
+          if (diag) {
+            const int d = half * 128 + row - c4;
+            if (d >= 0 && d < 4) dg += (double)(d == 0 ? outv.x : d == 1 ? outv.y : d == 2 ? outv.z : outv.w);
+          }
+          *(float4 *)sp = last ? pv : outv;
         }
-        if (!last) *(float4 *)(P.accf + gi) = pv;
-        const double w = diag ? 1.0 : 2.0;
-        lv += w * ((double)outv.x * outv.x + (double)outv.y * outv.y + (double)outv.z * outv.z +
-                   (double)outv.w * outv.w);
-        if (diag) {
-          const int d = half * 128 + row - c4;
-          if (d >= 0 && d < 4) dg += (double)(d == 0 ? outv.x : d == 1 ? outv.y : d == 2 ? outv.z : outv.w);
-        }
-        *(float4 *)sp = last ? pv : outv;
       }
       __syncthreads();
       emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
@@ -563,6 +619,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
     block_sum3(lv, dg, unused, (double *)smem);
     if (threadIdx.x == 0) write_level_partials(P, level + 1, task, lv, dg);
     __syncthreads();
+    }
   }
 }
 
@@ -575,8 +632,9 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
   float *ep = (float *)smem;
   int cur_p = -1;
   float sc0 = 0.f, sps = 0.f;
-  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
-    Task task = fetch(a, t, kStageProduct);
+  const TaskRange tr = task_range(a);
+  for (int t = tr.start; t < tr.end; t += tr.stride) {
+    Task task = fetch(a, tr.base + t, kStageProduct);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -611,7 +669,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
     const int m0 = task.tm * BM, n0 = task.tn * BN;
     const uint32_t mbytes = (uint32_t)(((int64_t)(P.trans ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(P.trans ? P.h : P.w) * 2);
     const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
-    const Operand Po = make_operand(P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
+    const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
     const int Kp = uni(P.h);
     f32x16 acc[FM][FN];
     const int rows_out = P.trans ? P.w : P.h, cols_out = P.trans ? P.h : P.w;
@@ -633,27 +691,39 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
-      for (int q = threadIdx.x; q < 128 * 32; q += kThreads) {
-        const int row = q >> 5, c8 = (q & 31) * 8;
-        const int r = m0 + half * 128 + row, c = n0 + c8;
-        if (r >= rows_out || c >= cols_out) continue;
-        const float *src = ep + row * EP_LD + c8;
-        const uint4 xm = *(const uint4 *)(M + (int64_t)r * P.ldm + c);
-        const uint32_t xw[4] = {xm.x, xm.y, xm.z, xm.w};
-        float y[8];
+      constexpr int PER = 128 * 32 / kThreads, BATCH = 8;
+      for (int b0 = 0; b0 < PER; b0 += BATCH) {
+        uint4 xm[BATCH];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-          y[2 * e] = sc0 * __uint_as_float(xw[e] << 16) + sps * src[2 * e];
-          y[2 * e + 1] = sc0 * __uint_as_float(xw[e] & 0xffff0000u) + sps * src[2 * e + 1];
+        for (int u = 0; u < BATCH; u++) {
+          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int row = q >> 5, c8 = (q & 31) * 8;
+          const int r = m0 + half * 128 + row, c = n0 + c8;
+          xm[u] = (r < rows_out && c < cols_out) ? *(const uint4 *)(M + (int64_t)r * P.ldm + c) : make_uint4(0, 0, 0, 0);
         }
-        if (out_bf16) {
-          uint4 o = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]), pack_bf16x2(y[4], y[5]),
-                               pack_bf16x2(y[6], y[7]));
-          *(uint4 *)((uint16_t *)P.Y + (int64_t)r * P.ldy + c) = o;
-        } else {
-          float *yp = (float *)P.Y + (int64_t)r * P.ldy + c;
-          *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
-          *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
+#pragma unroll
+        for (int u = 0; u < BATCH; u++) {
+          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int row = q >> 5, c8 = (q & 31) * 8;
+          const int r = m0 + half * 128 + row, c = n0 + c8;
+          if (r >= rows_out || c >= cols_out) continue;
+          const float *src = ep + row * EP_LD + c8;
+          const uint32_t xw[4] = {xm[u].x, xm[u].y, xm[u].z, xm[u].w};
+          float y[8];
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            y[2 * e] = sc0 * __uint_as_float(xw[e] << 16) + sps * src[2 * e];
+            y[2 * e + 1] = sc0 * __uint_as_float(xw[e] & 0xffff0000u) + sps * src[2 * e + 1];
+          }
+          if (out_bf16) {
+            uint4 o = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]), pack_bf16x2(y[4], y[5]),
+                                 pack_bf16x2(y[6], y[7]));
+            *(uint4 *)((uint16_t *)P.Y + (int64_t)r * P.ldy + c) = o;
+          } else {
+            float *yp = (float *)P.Y + (int64_t)r * P.ldy + c;
+            *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
+            *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
+          }
         }
       }
       __syncthreads();
@@ -661,7 +731,78 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// aggregate: P = sum_{l=1}^{J+1} c_l S_l B_l (level layout); P overwrites level 1 in place
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
+  __shared__ float wsh[kMaxLevels];
+  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    const Task task = a.tasks ? a.tasks[t] : Task{0, t, 0, 0};
+    const ProbDev &P = a.tasks ? a.probs[task.p] : a.one;
+    __syncthreads();
+    if (threadIdx.x < 64) {  // one wave: level weights c_l S_l in float64, then float32
+      const FScalars sc = scalars(P, a.norm);
+      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      double S = sc.sg;
+      for (int l = 1; l <= a.J + 1; l++) {
+        if (threadIdx.x == 0) wsh[l] = (float)(P.coef[l] * S);
+        if (l <= a.J) {
+          const double F = pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+          S = S * S / F;
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)P.hp * P.hp;
+    const int64_t e0 = (int64_t)task.tm * kAggChunk;
+    const int64_t e1 = e0 + kAggChunk < n ? e0 + kAggChunk : n;
+    const int L = a.J + 1;
+    char *base = (char *)P.lv;
+    constexpr int U = 4;  // chunks of 8 elements per thread in flight
+    for (int64_t e = e0 + (int64_t)threadIdx.x * 8; e < e1; e += (int64_t)kThreads * 8 * U) {
+      float acc[U][8];
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) acc[u][i] = 0.f;
+      for (int l = 1; l <= L; l++) {
+        const float wl = wsh[l];
+        const uint16_t *src = (const uint16_t *)(base + (int64_t)(l - 1) * P.lv_stride);
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int64_t ee = e + (int64_t)u * kThreads * 8;
+          v[u] = ee < e1 ? *(const uint4 *)(src + ee) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            acc[u][2 * q] += wl * __uint_as_float(w[q] << 16);
+            acc[u][2 * q + 1] += wl * __uint_as_float(w[q] & 0xffff0000u);
+          }
+        }
+      }
+      uint16_t *dst = (uint16_t *)base;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t ee = e + (int64_t)u * kThreads * 8;
+        if (ee < e1)
+          *(uint4 *)(dst + ee) = make_uint4(pack_bf16x2(acc[u][0], acc[u][1]), pack_bf16x2(acc[u][2], acc[u][3]),
+                                            pack_bf16x2(acc[u][4], acc[u][5]), pack_bf16x2(acc[u][6], acc[u][7]));
+      }
+    }
+  }
+}
+
 }  // namespace fast
+
+hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fast::kf_aggregate, dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
@@ -669,7 +810,8 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
     if (trans) hipLaunchKernelGGL(fast::kf_gram<true>, dim3(grid), dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(fast::kf_gram<false>, dim3(grid), dim3(kThreads), 0, s, a);
   } else if (stage == kStageSquare) {
-    hipLaunchKernelGGL(fast::kf_square, dim3(grid), dim3(kThreads), 0, s, a);
+    if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(kThreads), 0, s, a);
   } else {
     if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
     else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
@@ -679,7 +821,7 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
   const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false>
-                 : stage == kStageSquare ? (const void *)fast::kf_square : (const void *)fast::kf_product<false>;
+                 : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
 }
 

@@ -56,14 +56,14 @@ constexpr int kPad = 256;
 struct ProbLayout {
   int64_t rows, cols;
   int32_t h, w, trans, hp, nt;
-  size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2];
-  int64_t ldx;
+  size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2], off_lv;
+  int64_t ldx, lv_stride;
   size_t bytes;
 };
 
 // Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
 // float32 D ping-pong; classical NS adds two h x w iterates.
-ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns) {
+ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -79,9 +79,19 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     o = align_up(o + bytes, kAlign);
     return at;
   };
-  L.off_opnd[0] = take(hh * op_size(op));
-  L.off_opnd[1] = take(hh * op_size(op));
-  L.off_accf = take(hh * 4);
+  if (agg) {
+    // level layout: J + 1 full symmetric bf16 levels; the first one doubles as the Gram
+    // operand and, after the aggregate stage, as P
+    L.lv_stride = (int64_t)align_up(hh * op_size(op), kAlign);
+    L.off_lv = take((size_t)(J + 1) * L.lv_stride);
+    L.off_opnd[0] = L.off_lv;
+    L.off_opnd[1] = L.off_lv;
+    L.off_accf = L.off_lv;  // never written in the level layout
+  } else {
+    L.off_opnd[0] = take(hh * op_size(op));
+    L.off_opnd[1] = take(hh * op_size(op));
+    L.off_accf = take(hh * 4);
+  }
   if (complement) {
     L.off_df[0] = take(hh * 4);
     L.off_df[1] = take(hh * 4);
@@ -126,6 +136,8 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
   d.xbuf[0] = L.off_xbuf[0] ? ws + L.off_xbuf[0] : nullptr;
   d.xbuf[1] = L.off_xbuf[1] ? ws + L.off_xbuf[1] : nullptr;
   d.ldx = L.ldx;
+  d.lv = L.lv_stride ? ws + L.off_lv : nullptr;
+  d.lv_stride = L.lv_stride;
 }
 
 bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -149,11 +161,43 @@ int grid_for(int op, int stage, int ntasks, int cus) {
   return std::max(1, std::min(ntasks, occ * cus));
 }
 
+
+
+// Tiles of one problem in panel-sharing blocks of kBlkR x kBlkC tiles (row-major inside a
+// block, blocks row-major); `upper` keeps only tiles with tn >= tm.
+constexpr int kBlkR = 4, kBlkC = 8, kXcds = 8, kGroup = 32;
+
+void block_order(std::vector<Task> &out, int p, int rows, int cols, bool upper) {
+  for (int br = 0; br < rows; br += kBlkR)
+    for (int bc = upper ? (br / kBlkC) * kBlkC : 0; bc < cols; bc += kBlkC)
+      for (int tm = br; tm < std::min(rows, br + kBlkR); tm++)
+        for (int tn = bc; tn < std::min(cols, bc + kBlkC); tn++)
+          if (!upper || tn >= tm) out.push_back(Task{p, tm, tn, 0});
+}
+
+// Deals groups of kGroup consecutive tiles to the XCDs in turn; returns the tasks grouped
+// by XCD with per-XCD offsets (relative to the start of the returned list) and counts.
+std::vector<Task> xcd_queues(const std::vector<Task> &tiles, int off[kXcds], int cnt[kXcds]) {
+  std::vector<std::vector<Task>> q(kXcds);
+  for (size_t g = 0; g * kGroup < tiles.size(); g++) {
+    const size_t b = g * kGroup, e = std::min(tiles.size(), b + kGroup);
+    q[g % kXcds].insert(q[g % kXcds].end(), tiles.begin() + b, tiles.begin() + e);
+  }
+  std::vector<Task> out;
+  for (int x = 0; x < kXcds; x++) {
+    off[x] = (int)out.size();
+    cnt[x] = (int)q[x].size();
+    out.insert(out.end(), q[x].begin(), q[x].end());
+  }
+  return out;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------------------------
+
 struct ifnso_plan_s {
   int device = 0;
   int num = 0;
@@ -174,8 +218,12 @@ struct ifnso_plan_s {
   int n_gram = 0, n_square = 0, n_prod = 0;
   size_t off_gram = 0, off_square = 0, off_prod = 0;
   bool fast = false;  // bfloat16 plan whose squarings use the fast kernels
+  bool agg = false;   // level layout + aggregate stage (fast, Gram basis, J >= 1)
+  int n_agg = 0;
+  size_t off_agg = 0;
   int nf_gram[2] = {0, 0}, nf_square = 0, nf_prod[2] = {0, 0};  // [0] wide, [1] tall
   size_t offf_gram[2] = {0, 0}, offf_square = 0, offf_prod[2] = {0, 0};
+  int xq_gram[2][2][kXcds] = {}, xq_square[2][kXcds] = {}, xq_prod[2][2][kXcds] = {};  // [off/cnt]
   double fl_gram[2] = {0, 0}, fl_square = 0, fl_prod[2] = {0, 0};  // algorithmic flops per launch
   double *d_coef = nullptr;   // [num][kSlots]
   double *d_stats = nullptr;  // [num][kStatsPerProblem]
@@ -282,9 +330,14 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   const int emax = p->exps[p->K - 1];
   p->J = emax <= 1 ? 0 : slot_of_exponent(emax) - 1;
   p->p_empty = emax == 0;
+  p->fast = op == kOpBF16 && fast_enabled();
+  for (int i = 0; i < num_problems; i++)
+    if (round_up(std::min(rows[i], cols[i]), kPad) > 32512) p->fast = false;  // bf16 h x h below 2 GiB
+  p->agg = p->fast && p->basis == IFNSO_BASIS_GRAM && p->J >= 1;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
-    p->lay.push_back(layout_problem(rows[i], cols[i], op, p->J, p->basis == IFNSO_BASIS_COMPLEMENT, false));
+    p->lay.push_back(
+        layout_problem(rows[i], cols[i], op, p->J, p->basis == IFNSO_BASIS_COMPLEMENT, false, p->agg));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -323,24 +376,15 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->off_prod = all.size();
   all.insert(all.end(), prod.begin(), prod.end());
   // fast lists (256 tiles): Gram and product split by orientation, one kernel each
-  p->fast = op == kOpBF16 && fast_enabled();
-  if (p->fast) {
-    for (int i = 0; i < num_problems; i++)
-      if (p->lay[i].hp > 32512) p->fast = false;  // h x h bfloat16 buffers stay below 2 GiB
-  }
   if (p->fast) {
     std::vector<Task> fg[2], fs, fp[2];
     for (int i : order) {
       const ProbLayout &L = p->lay[i];
       const int nt = L.hp / kFastTS, tr = L.trans;
-      for (int tm = 0; tm < nt; tm++)
-        for (int tn = tm; tn < nt; tn++) {
-          fg[tr].push_back(Task{i, tm, tn, 0});
-          fs.push_back(Task{i, tm, tn, 0});
-        }
+      block_order(fg[tr], i, nt, nt, true);
+      block_order(fs, i, nt, nt, true);
       const int rt = ((tr ? L.w : L.h) + kFastTS - 1) / kFastTS, ct = ((tr ? L.h : L.w) + kFastTS - 1) / kFastTS;
-      for (int tm = 0; tm < rt; tm++)
-        for (int tn = 0; tn < ct; tn++) fp[tr].push_back(Task{i, tm, tn, 0});
+      block_order(fp[tr], i, rt, ct, false);
       const double h = L.h, w = L.w;
       p->fl_gram[tr] += h * h * w;
       p->fl_square += h * h * h;
@@ -349,14 +393,25 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
     for (int t = 0; t < 2; t++) {
       p->offf_gram[t] = all.size();
       p->nf_gram[t] = (int)fg[t].size();
-      all.insert(all.end(), fg[t].begin(), fg[t].end());
+      const std::vector<Task> qg = xcd_queues(fg[t], p->xq_gram[t][0], p->xq_gram[t][1]);
+      all.insert(all.end(), qg.begin(), qg.end());
       p->offf_prod[t] = all.size();
       p->nf_prod[t] = (int)fp[t].size();
-      all.insert(all.end(), fp[t].begin(), fp[t].end());
+      const std::vector<Task> qp = xcd_queues(fp[t], p->xq_prod[t][0], p->xq_prod[t][1]);
+      all.insert(all.end(), qp.begin(), qp.end());
     }
     p->offf_square = all.size();
     p->nf_square = (int)fs.size();
-    all.insert(all.end(), fs.begin(), fs.end());
+    const std::vector<Task> qs = xcd_queues(fs, p->xq_square[0], p->xq_square[1]);
+    all.insert(all.end(), qs.begin(), qs.end());
+    if (p->agg) {
+      p->off_agg = all.size();
+      for (int i : order) {
+        const int64_t n = (int64_t)p->lay[i].hp * p->lay[i].hp;
+        for (int64_t c = 0; c * kAggChunk < n; c++) all.push_back(Task{i, (int)c, 0, 0});
+      }
+      p->n_agg = (int)(all.size() - p->off_agg);
+    }
   } else {
     for (int i = 0; i < num_problems; i++) {
       const ProbLayout &L = p->lay[i];
@@ -441,13 +496,14 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   a.ns_step = -1;
   a.p_empty = p->p_empty;
   a.learned = 0;
+  a.agg = p->agg ? 1 : 0;
   return a;
 }
 
-// Launch slots of one call, in order: Gram (wide, tall), each squaring level, product (wide,
-// tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
+// Launch slots of one call, in order: Gram (wide, tall), each squaring level, aggregate,
+// product (wide, tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
 // slot i and ev[num_slots] after the last one, so empty slots read as zero time.
-static int num_slots(const ifnso_plan_s *p) { return p->J + 4; }
+static int num_slots(const ifnso_plan_s *p) { return p->J + 5; }
 
 // Problem-level check for the fast kernels: 16-byte aligned rows whose length is a multiple of
 // 8 elements, and an input small enough for 32-bit buffer offsets.
@@ -457,6 +513,25 @@ static bool fast_io_ok(const ifnso_plan_s *p, const ProbDev &d, const ProbLayout
   const int oes = p->out_dtype == IFNSO_F32 ? 4 : 2;
   return cols % 8 == 0 && d.ldm % 8 == 0 && ((uintptr_t)d.M % 16) == 0 && in_bytes < (1ull << 31) &&
          ((size_t)d.ldy * oes) % 16 == 0 && ((uintptr_t)d.Y % 16) == 0;
+}
+
+static bool use_xcd_sched();
+
+static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds]) {
+  a.xcd_sched = use_xcd_sched() ? 1 : 0;
+  for (int x = 0; x < kXcds; x++) {
+    a.xcd_off[x] = off[x];
+    a.xcd_cnt[x] = cnt[x];
+  }
+}
+
+// One workgroup per CU; with XCD queues, a multiple of 8 workgroups, no more than the
+// longest queue needs.
+static int fast_grid(const StageArgs &a, int cus) {
+  if (!a.xcd_sched) return std::max(1, std::min(a.ntasks, cus));
+  int mx = 1;
+  for (int x = 0; x < kXcds; x++) mx = std::max(mx, a.xcd_cnt[x]);
+  return kXcds * std::max(1, std::min(cus / kXcds, mx));
 }
 
 // Enqueues every stage of a plan on `s`, reading problems from `table` (batched) or `one`.
@@ -486,8 +561,12 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     if ((e = mark()) != hipSuccess) return e;
     if (fast && fast_io) {
       a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
-      if (!one) a.tasks = p->d_tasks + p->offf_gram[t];
-      e = launch_fast_stage(kStageGram, t, a, std::min(a.ntasks, cus), outbf, s);
+      if (!one) {
+        a.tasks = p->d_tasks + p->offf_gram[t];
+        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1]);
+      }
+      e = launch_fast_stage(kStageGram, t, a, fast_grid(a, cus), outbf, s);
+      a.xcd_sched = 0;
     } else if (t == 0) {
       a.ntasks = one ? ntiles_sym(kTS) : p->n_gram;
       if (!one) a.tasks = p->d_tasks + p->off_gram;
@@ -501,8 +580,12 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     a.last = lvl == p->J;
     if (fast) {
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
-      if (!one) a.tasks = p->d_tasks + p->offf_square;
-      e = launch_fast_stage(kStageSquare, 0, a, std::min(a.ntasks, cus), outbf, s);
+      if (!one) {
+        a.tasks = p->d_tasks + p->offf_square;
+        set_xcd(a, p->xq_square[0], p->xq_square[1]);
+      }
+      e = launch_fast_stage(kStageSquare, 0, a, fast_grid(a, cus), outbf, s);
+      a.xcd_sched = 0;
     } else {
       a.ntasks = one ? ntiles_sym(kTS) : p->n_square;
       if (!one) a.tasks = p->d_tasks + p->off_square;
@@ -512,12 +595,23 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   }
   a.level = 0;
   a.last = 0;
+  if ((e = mark()) != hipSuccess) return e;
+  if (p->agg) {
+    a.ntasks = one ? (int)(((int64_t)L0->hp * L0->hp + kAggChunk - 1) / kAggChunk) : p->n_agg;
+    if (!one) a.tasks = p->d_tasks + p->off_agg;
+    e = launch_aggregate(a, std::max(1, std::min(a.ntasks, 8 * cus)), s);
+    if (e != hipSuccess) return e;
+  }
   for (int t = 0; t < 2; t++) {
     if ((e = mark()) != hipSuccess) return e;
     if (fast && fast_io) {
       a.ntasks = one ? (t == tr0 ? ntiles_prod(kFastTS) : 0) : p->nf_prod[t];
-      if (!one) a.tasks = p->d_tasks + p->offf_prod[t];
-      e = launch_fast_stage(kStageProduct, t, a, std::min(a.ntasks, cus), outbf, s);
+      if (!one) {
+        a.tasks = p->d_tasks + p->offf_prod[t];
+        set_xcd(a, p->xq_prod[t][0], p->xq_prod[t][1]);
+      }
+      e = launch_fast_stage(kStageProduct, t, a, fast_grid(a, cus), outbf, s);
+      a.xcd_sched = 0;
     } else if (t == 0) {
       a.ntasks = one ? ntiles_prod(kTS) : p->n_prod;
       if (!one) a.tasks = p->d_tasks + p->off_prod;
@@ -539,6 +633,11 @@ static ifnso_status check_matrix_args(const ifnso_plan_s *p, int i, const void *
   if (ranges_overlap(M, matrix_bytes(L.rows, ldm, L.cols, ies), Y, matrix_bytes(L.rows, ldy, L.cols, oes)))
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: Y overlaps M", i);
   return IFNSO_OK;
+}
+
+static bool use_xcd_sched() {
+  const char *v = getenv("IFNSO_XCD_SCHED");
+  return !(v && v[0] == '0');
 }
 
 static bool fast_enabled_impl() {
@@ -630,9 +729,12 @@ extern "C" ifnso_status ifnso_plan_launch_info(ifnso_plan_t p, int32_t i, int32_
   } else if (i < 2 + p->J) {
     *stage = kStageSquare;
     *flops = p->fl_square;
+  } else if (i == 2 + p->J) {
+    *stage = kStageAggregate;
+    *flops = 0.0;
   } else {
     *stage = kStageProduct;
-    *flops = p->fl_prod[i - 2 - p->J];
+    *flops = p->fl_prod[i - 3 - p->J];
   }
   return IFNSO_OK;
 }

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
     }
     T *op = (T *)P.opnd[0];
     const int64_t hp = P.hp;
-    const bool keep_f32 = a.J >= 1 || a.ns_step >= 0 || a.learned;
+    const bool keep_f32 = (a.J >= 1 && !a.agg) || a.ns_step >= 0 || a.learned;
     double lv = 0.0, dg = 0.0;
 #pragma unroll
     for (int fm = 0; fm < TL::FM; fm++)
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
       sc0 = (float)(sout * c0);
       sps = (float)(sout * ps);
     }
-    const T *Pb = (const T *)P.opnd[a.J & 1];
+    const T *Pb = (const T *)(a.agg ? P.lv : P.opnd[a.J & 1]);
     const int64_t hp = P.hp;
     // geometry: source X_k, destination, orientation of the computed tile
     const bool ns = a.ns_step >= 0;

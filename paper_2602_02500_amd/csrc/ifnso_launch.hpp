@@ -7,7 +7,7 @@
 
 namespace ifnso {
 
-enum Stage : int { kStageGram = 0, kStageSquare = 1, kStageProduct = 2 };
+enum Stage : int { kStageGram = 0, kStageSquare = 1, kStageProduct = 2, kStageAggregate = 3 };
 
 struct OrthEntry {
   const void *ptr;
@@ -27,6 +27,9 @@ hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu);
 // bfloat16 fast path, 256 x 256 tiles (see ifnso_fast.hip for the operand requirements)
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
 hipError_t fast_occupancy(int stage, int *blocks_per_cu);
+// P = sum_l c_l S_l B_l over the stored levels (level layout); tasks are (problem, chunk)
+hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s);
+constexpr int kAggChunk = 1 << 17;  // elements per aggregate task
 constexpr int kFastTS = 256;
 
 hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
