@@ -67,8 +67,12 @@ typedef enum {
 } ifnso_norm;
 
 /* FIXED: the descriptor's coefficients for every problem.
- * LEARNED: reserved for per-problem coefficients predicted on the device; plans that
- *   request it fail with IFNSO_ERR_UNSUPPORTED in this build. */
+ * LEARNED: per-problem coefficients predicted on the device by a small network (the
+ *   "dynamic coefficients" the paper names as future work, Sec. 4) from the normalised
+ *   traces m_j = tr(G^(2^j))/h, j = 0..7, of the Gram powers the method forms (two extra
+ *   squarings supply G^32 and G^64). Requires exponents {0,1,2,4,8,16}, the Gram basis, the
+ *   Frobenius norm and bf16 compute; the descriptor's coefficients are the fallback for any
+ *   problem whose prediction is not finite. Network: see IFNSO_MLP_NUM_PARAMS below. */
 typedef enum { IFNSO_COEFF_FIXED = 0, IFNSO_COEFF_LEARNED = 1 } ifnso_coeff_mode;
 
 enum {
@@ -84,8 +88,8 @@ typedef struct {
   int32_t norm;               /* ifnso_norm */
   int32_t compute;            /* ifnso_compute */
   int32_t coeff_mode;         /* ifnso_coeff_mode */
-  const float *mlp_params;    /* LEARNED only (reserved) */
-  size_t mlp_params_len;
+  const float *mlp_params;    /* LEARNED only: host array of IFNSO_MLP_NUM_PARAMS floats (copied) */
+  size_t mlp_params_len;      /* must equal IFNSO_MLP_NUM_PARAMS when LEARNED */
   uint32_t flags;             /* IFNSO_FLAG_* */
 } ifnso_poly_desc;
 
@@ -170,6 +174,44 @@ ifnso_status ifnso_orth_error(int32_t count, const void *const *Y, const int64_t
                               const int64_t *ldy, int32_t dtype, double *out, void *workspace,
                               size_t workspace_bytes, void *stream);
 size_t ifnso_orth_error_workspace_bytes(int32_t count);
+
+/* Per-problem statistics of the most recent call of a plan, copied to the host array
+ * host_out[num_problems * IFNSO_STATS_PER_PROBLEM] after synchronising `stream`. Filled by
+ * LEARNED plans: [0] ||A||_F^2, [1..8] log2 m_j for j = 0..7, [9..24] the coefficient slots used
+ * (slot 0: exponent 0, slot 1 + j: exponent 2^j), [25] 1 if the network's coefficients were used,
+ * 0 if the fixed fallback was. Zero for FIXED plans. Errors: INVALID_ARGUMENT, HIP. */
+#define IFNSO_STATS_PER_PROBLEM 26
+ifnso_status ifnso_plan_stats(ifnso_plan_t plan, double *host_out, void *stream);
+
+/* ---- the coefficient network ---------------------------------------------------------------
+ * phi_j = log2(m_j) / (8 * 2^j) (j = 0..7) -> 64 -> gelu -> 64 -> gelu -> 6 -> projection
+ * c = z + (1 - sum z)/6 onto sum c = 1. gelu is the exact-erf form. Parameter layout (float32,
+ * row-major, output-major weights): W1[64][8], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]. */
+#define IFNSO_MLP_NUM_PARAMS 5126
+
+/* Features phi (device float[n][8]) of n spectra: sig is device float[n][smax] holding the
+ * singular values of each matrix (any scale; zero-padded), nsig device int32[n] their counts
+ * (= h). Evaluated in float64 log space. Errors: INVALID_ARGUMENT, HIP. */
+ifnso_status ifnso_mlp_features(int32_t n, const float *sig, const int32_t *nsig, int32_t smax, float *feats_out,
+                                void *stream);
+
+/* Network outputs (device double[n][6], coefficients for exponents 0,1,2,4,8,16) for n feature
+ * vectors (device float[n][8]) with parameters `params` (device). Errors: INVALID_ARGUMENT, HIP. */
+ifnso_status ifnso_mlp_forward(int32_t n, const float *feats, const float *params, double *coeffs_out,
+                               void *stream);
+
+/* One training step on the device for a batch of n samples: forward, the spectral loss
+ * (1/h) sum_i (s_i p(s_i^2) - 1)^2 over the normalised singular values s (the squared Frobenius
+ * distance to the polar factor, over h), backward, a mean gradient reduced in sample order, and
+ * one Adam update of params / adam_m / adam_v (device float[IFNSO_MLP_NUM_PARAMS], in place;
+ * t >= 1 is the step number for bias correction). grad_out (device float[IFNSO_MLP_NUM_PARAMS])
+ * and loss_out (device float[1]) are optional. Deterministic. Workspace: device,
+ * ifnso_mlp_train_workspace_bytes(n) bytes. Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_mlp_train_step(int32_t n, const float *feats, const float *sig, const int32_t *nsig, int32_t smax,
+                                  float *params, float *adam_m, float *adam_v, int32_t t, float lr, float beta1,
+                                  float beta2, float eps, float *grad_out, float *loss_out, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+size_t ifnso_mlp_train_workspace_bytes(int32_t n);
 
 /* Thread-local message describing the last error returned on this thread. */
 const char *ifnso_last_error(void);

@@ -15,7 +15,8 @@ __all__ = [
     "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes",
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
-    "header_functions", "STATUS", "orth_error_workspace_bytes",
+    "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
+    "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +29,8 @@ BASIS_GRAM, BASIS_COMPLEMENT = 0, 1
 NORM_FROBENIUS, NORM_GRAM_FROBENIUS, NORM_NONE = 0, 1, 2
 COEFF_FIXED, COEFF_LEARNED = 0, 1
 FLAG_ENFORCE_SUM_ONE = 1
+STATS_PER_PROBLEM = 26
+MLP_NUM_PARAMS = 5126
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "WORKSPACE_TOO_SMALL", 4: "HIP", 5: "INTERNAL"}
 
 _BASIS = {"gram": BASIS_GRAM, "complement": BASIS_COMPLEMENT}
@@ -87,6 +90,17 @@ def load() -> ctypes.CDLL:
     L.ifnso_plan_launch_info.restype = ctypes.c_int
     L.ifnso_plan_launch_events.argtypes = [vp, ctypes.POINTER(vp), i32]
     L.ifnso_plan_launch_events.restype = ctypes.c_int
+    L.ifnso_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.ifnso_plan_stats.restype = ctypes.c_int
+    L.ifnso_mlp_features.argtypes = [i32, vp, vp, i32, vp, vp]
+    L.ifnso_mlp_features.restype = ctypes.c_int
+    L.ifnso_mlp_forward.argtypes = [i32, vp, vp, vp, vp]
+    L.ifnso_mlp_forward.restype = ctypes.c_int
+    fl = ctypes.c_float
+    L.ifnso_mlp_train_step.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp, i32, fl, fl, fl, fl, vp, vp, vp, sz, vp]
+    L.ifnso_mlp_train_step.restype = ctypes.c_int
+    L.ifnso_mlp_train_workspace_bytes.argtypes = [i32]
+    L.ifnso_mlp_train_workspace_bytes.restype = sz
     L.ifnso_last_error.restype = ctypes.c_char_p
     for name in ("ifnso_plan", "ifnso_plan_workspace_bytes", "ifnso_plan_destroy", "ifnso_orthogonalize",
                  "ifnso_orthogonalize_batched", "ifnso_classical_ns", "ifnso_orth_error"):
@@ -132,15 +146,20 @@ class Plan:
 
     def __init__(self, exponents: Sequence[int], coeffs: Sequence[float], shapes, basis="gram",
                  norm="frobenius", compute="bf16", in_dtype=None, out_dtype=None, device: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, mlp_params=None):
+        """mlp_params: host float sequence of MLP_NUM_PARAMS values selects the learned mode."""
         L = load()
         self._L = L
         K = len(exponents)
         self._e = (ctypes.c_int32 * K)(*[int(x) for x in exponents])
         self._c = (ctypes.c_double * K)(*[float(x) for x in coeffs])
         comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+        mode, mp, mlen = COEFF_FIXED, None, 0
+        if mlp_params is not None:
+            self._mp = (ctypes.c_float * len(mlp_params))(*[float(x) for x in mlp_params])
+            mode, mp, mlen = COEFF_LEARNED, self._mp, len(mlp_params)
         d = PolyDesc(K, self._e, self._c, _BASIS[basis] if isinstance(basis, str) else int(basis),
-                     _NORM[norm] if isinstance(norm, str) else int(norm), comp, COEFF_FIXED, None, 0, int(flags))
+                     _NORM[norm] if isinstance(norm, str) else int(norm), comp, mode, mp, mlen, int(flags))
         self.shapes = [(int(r), int(c)) for r, c in shapes]
         n = len(self.shapes)
         rows = (ctypes.c_int64 * n)(*[r for r, _ in self.shapes])
@@ -189,6 +208,13 @@ class Plan:
         arr = (ctypes.c_void_p * max(n, 1))(*[int(e) for e in events])
         _check(self._L.ifnso_plan_launch_events(self._h, arr, n))
 
+    def stats(self, stream=None):
+        """Per-problem statistics of the last call (see ifnso_plan_stats), as a list of lists."""
+        n = len(self.shapes)
+        buf = (ctypes.c_double * (n * STATS_PER_PROBLEM))()
+        _check(self._L.ifnso_plan_stats(self._h, buf, _stream(stream)))
+        return [list(buf[i * STATS_PER_PROBLEM:(i + 1) * STATS_PER_PROBLEM]) for i in range(n)]
+
     def destroy(self):
         if getattr(self, "_h", None):
             self._L.ifnso_plan_destroy(self._h)
@@ -231,3 +257,28 @@ def orth_error(Ys, out, workspace, stream=None):
 
 def orth_error_workspace_bytes(count: int) -> int:
     return int(load().ifnso_orth_error_workspace_bytes(int(count)))
+
+
+def mlp_features(sig, nsig, feats_out, stream=None):
+    """Device features (n x 8) of zero-padded spectra sig (n x smax float32) with counts nsig."""
+    _check(load().ifnso_mlp_features(int(sig.shape[0]), _ptr(sig), _ptr(nsig), int(sig.shape[1]), _ptr(feats_out),
+                                     _stream(stream)))
+
+
+def mlp_forward(feats, params, coeffs_out, stream=None):
+    _check(load().ifnso_mlp_forward(int(feats.shape[0]), _ptr(feats), _ptr(params), _ptr(coeffs_out), _stream(stream)))
+
+
+def mlp_train_workspace_bytes(n: int) -> int:
+    return int(load().ifnso_mlp_train_workspace_bytes(int(n)))
+
+
+def mlp_train_step(feats, sig, nsig, params, adam_m, adam_v, t, lr, workspace, beta1=0.9, beta2=0.999, eps=1e-8,
+                   grad_out=None, loss_out=None, stream=None):
+    n = int(feats.shape[0])
+    nb = workspace.numel() * workspace.element_size()
+    _check(load().ifnso_mlp_train_step(n, _ptr(feats), _ptr(sig), _ptr(nsig), int(sig.shape[1]), _ptr(params),
+                                       _ptr(adam_m), _ptr(adam_v), int(t), float(lr), float(beta1), float(beta2),
+                                       float(eps), _ptr(grad_out) if grad_out is not None else None,
+                                       _ptr(loss_out) if loss_out is not None else None, _ptr(workspace), nb,
+                                       _stream(stream)))

@@ -219,6 +219,10 @@ struct ifnso_plan_s {
   size_t off_gram = 0, off_square = 0, off_prod = 0;
   bool fast = false;  // bfloat16 plan whose squarings use the fast kernels
   bool agg = false;   // level layout + aggregate stage (fast, Gram basis, J >= 1)
+  bool learned = false;
+  int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
+  float *d_params = nullptr;       // learned mode: network parameters
+  double *d_fixed = nullptr;       // learned mode: fixed coefficient slots (fallback)
   int n_agg = 0;
   size_t off_agg = 0;
   int nf_gram[2] = {0, 0}, nf_square = 0, nf_prod[2] = {0, 0};  // [0] wide, [1] tall
@@ -269,7 +273,16 @@ static ifnso_status validate_desc(const ifnso_poly_desc *d) {
     if (std::fabs(s - 1.0) > 1e-12) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficients sum to %.17g, not 1", s);
   }
   if (d->coeff_mode == IFNSO_COEFF_LEARNED) {
-    return fail(IFNSO_ERR_UNSUPPORTED, "learned coefficients are not built in this library");
+    if (!d->mlp_params || d->mlp_params_len != (size_t)kMlpParams)
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "learned mode needs %d network parameters", kMlpParams);
+    static const int32_t want[6] = {0, 1, 2, 4, 8, 16};
+    bool ok = d->num_terms == 6;
+    for (int k = 0; ok && k < 6; k++) ok = d->exponents[k] == want[k];
+    if (!ok) return fail(IFNSO_ERR_UNSUPPORTED, "learned mode predicts exponents {0,1,2,4,8,16} only");
+    if (d->basis != IFNSO_BASIS_GRAM || d->norm != IFNSO_NORM_FROBENIUS || d->compute != IFNSO_COMPUTE_BF16)
+      return fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the Gram basis, the Frobenius norm and bf16 compute");
+    for (size_t i = 0; i < d->mlp_params_len; i++)
+      if (!std::isfinite(d->mlp_params[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "parameter %zu is not finite", i);
   }
   if (d->compute == IFNSO_COMPUTE_FP8_E4M3) return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute is not built");
   return IFNSO_OK;
@@ -283,6 +296,11 @@ static int slot_of_exponent(int e) {
   int j = 0;
   while ((1 << j) < e) j++;
   return 1 + j;
+}
+
+static ifnso_status cleanup_early(ifnso_plan_s *p, ifnso_status st) {
+  delete p;
+  return st;
 }
 
 extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_problems, const int64_t *rows,
@@ -334,10 +352,14 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   for (int i = 0; i < num_problems; i++)
     if (round_up(std::min(rows[i], cols[i]), kPad) > 32512) p->fast = false;  // bf16 h x h below 2 GiB
   p->agg = p->fast && p->basis == IFNSO_BASIS_GRAM && p->J >= 1;
+  p->learned = desc->coeff_mode == IFNSO_COEFF_LEARNED;
+  if (p->learned && !p->agg)
+    return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
+  p->Jsq = p->learned ? p->J + 2 : p->J;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(
-        layout_problem(rows[i], cols[i], op, p->J, p->basis == IFNSO_BASIS_COMPLEMENT, false, p->agg));
+        layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false, p->agg));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -439,6 +461,13 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e == hipSuccess) e = hipMalloc(&p->d_coef, coef.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_stats, (size_t)num_problems * kStatsPerProblem * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(p->d_stats, 0, (size_t)num_problems * kStatsPerProblem * sizeof(double));
+  if (p->learned) {
+    if (e == hipSuccess) e = hipMalloc(&p->d_params, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(p->d_params, desc->mlp_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_fixed, kSlots * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(p->d_fixed, p->slots, kSlots * sizeof(double), hipMemcpyHostToDevice);
+  }
   for (int s = 0; s < kSlotsRing && e == hipSuccess; s++) {
     e = hipMalloc(&p->d_table[s], (size_t)num_problems * sizeof(ProbDev));
     if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_table[s], (size_t)num_problems * sizeof(ProbDev), 0);
@@ -479,6 +508,8 @@ extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_coef) (void)hipFree(p->d_coef);
   if (p->d_stats) (void)hipFree(p->d_stats);
+  if (p->d_params) (void)hipFree(p->d_params);
+  if (p->d_fixed) (void)hipFree(p->d_fixed);
   (void)hipSetDevice(prev);
   delete p;
   return IFNSO_OK;
@@ -503,7 +534,7 @@ static StageArgs base_args(const ifnso_plan_s *p) {
 // Launch slots of one call, in order: Gram (wide, tall), each squaring level, aggregate,
 // product (wide, tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
 // slot i and ev[num_slots] after the last one, so empty slots read as zero time.
-static int num_slots(const ifnso_plan_s *p) { return p->J + 5; }
+static int num_slots(const ifnso_plan_s *p) { return p->Jsq + 5; }
 
 // Problem-level check for the fast kernels: 16-byte aligned rows whose length is a multiple of
 // 8 elements, and an input small enough for 32-bit buffer offsets.
@@ -574,10 +605,10 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     }
     if (e != hipSuccess) return e;
   }
-  for (int lvl = 1; lvl <= p->J; lvl++) {
+  for (int lvl = 1; lvl <= p->Jsq; lvl++) {
     if ((e = mark()) != hipSuccess) return e;
     a.level = lvl;
-    a.last = lvl == p->J;
+    a.last = lvl == p->Jsq;
     if (fast) {
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
@@ -596,6 +627,12 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   a.level = 0;
   a.last = 0;
   if ((e = mark()) != hipSuccess) return e;
+  if (p->learned) {
+    StageArgs b = a;
+    if (!one) b.tasks = p->d_tasks;  // non-null: problems come from the table
+    e = launch_learned(b, p->num, p->d_params, p->d_fixed, s);
+    if (e != hipSuccess) return e;
+  }
   if (p->agg) {
     a.ntasks = one ? (int)(((int64_t)L0->hp * L0->hp + kAggChunk - 1) / kAggChunk) : p->n_agg;
     if (!one) a.tasks = p->d_tasks + p->off_agg;
@@ -726,15 +763,15 @@ extern "C" ifnso_status ifnso_plan_launch_info(ifnso_plan_t p, int32_t i, int32_
   if (i < 2) {
     *stage = kStageGram;
     *flops = p->fl_gram[i];
-  } else if (i < 2 + p->J) {
+  } else if (i < 2 + p->Jsq) {
     *stage = kStageSquare;
     *flops = p->fl_square;
-  } else if (i == 2 + p->J) {
+  } else if (i == 2 + p->Jsq) {
     *stage = kStageAggregate;
     *flops = 0.0;
   } else {
     *stage = kStageProduct;
-    *flops = p->fl_prod[i - 3 - p->J];
+    *flops = p->fl_prod[i - 3 - p->Jsq];
   }
   return IFNSO_OK;
 }
@@ -878,6 +915,54 @@ extern "C" ifnso_status ifnso_orth_error(int32_t count, const void *const *Y, co
   HIP_TRY(launch_orth_error(a, dtype == IFNSO_BF16, s));
   // the host array `e` must outlive the copy
   HIP_TRY(hipStreamSynchronize(s));
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_stats(ifnso_plan_t p, double *host_out, void *stream) {
+  if (!p || !host_out) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<double> buf((size_t)p->num * kStatsPerProblem);
+  HIP_TRY(hipMemcpy(buf.data(), p->d_stats, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < p->num; i++)
+    for (int k = 0; k < IFNSO_STATS_PER_PROBLEM; k++)
+      host_out[(size_t)i * IFNSO_STATS_PER_PROBLEM + k] = buf[(size_t)i * kStatsPerProblem + k];
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_mlp_features(int32_t n, const float *sig, const int32_t *nsig, int32_t smax,
+                                           float *feats_out, void *stream) {
+  if (n < 1 || !sig || !nsig || smax < 1 || !feats_out) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad arguments");
+  HIP_TRY(launch_mlp_features(n, sig, nsig, smax, feats_out, (hipStream_t)stream));
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_mlp_forward(int32_t n, const float *feats, const float *params, double *coeffs_out,
+                                          void *stream) {
+  if (n < 1 || !feats || !params || !coeffs_out) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad arguments");
+  HIP_TRY(launch_mlp_forward(n, feats, params, coeffs_out, (hipStream_t)stream));
+  return IFNSO_OK;
+}
+
+extern "C" size_t ifnso_mlp_train_workspace_bytes(int32_t n) {
+  if (n < 1) return 0;
+  return align_up((size_t)n * kMlpParams * sizeof(float), kAlign) + align_up((size_t)n * sizeof(float), kAlign);
+}
+
+extern "C" ifnso_status ifnso_mlp_train_step(int32_t n, const float *feats, const float *sig, const int32_t *nsig,
+                                             int32_t smax, float *params, float *adam_m, float *adam_v, int32_t t,
+                                             float lr, float beta1, float beta2, float eps, float *grad_out,
+                                             float *loss_out, void *workspace, size_t workspace_bytes,
+                                             void *stream) {
+  if (n < 1 || !feats || !sig || !nsig || smax < 1 || !params || !adam_m || !adam_v || t < 1)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad arguments");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad optimiser hyper-parameters");
+  if (!workspace || workspace_bytes < ifnso_mlp_train_workspace_bytes(n))
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  float *grads = (float *)workspace;
+  float *losses = (float *)((char *)workspace + align_up((size_t)n * kMlpParams * sizeof(float), kAlign));
+  HIP_TRY(launch_mlp_train(n, feats, sig, nsig, smax, params, adam_m, adam_v, t, lr, beta1, beta2, eps, grad_out,
+                           loss_out, grads, losses, (hipStream_t)stream));
   return IFNSO_OK;
 }
 

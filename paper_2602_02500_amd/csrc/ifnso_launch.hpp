@@ -32,6 +32,16 @@ hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s);
 constexpr int kAggChunk = 1 << 17;  // elements per aggregate task
 constexpr int kFastTS = 256;
 
+// learned coefficients (ifnso_mlp.hip)
+constexpr int kMlpParams = 5126;
+hipError_t launch_mlp_features(int n, const float *sig, const int32_t *nsig, int smax, float *feats, hipStream_t s);
+hipError_t launch_mlp_forward(int n, const float *feats, const float *params, double *coeffs, hipStream_t s);
+hipError_t launch_mlp_train(int n, const float *feats, const float *sig, const int32_t *nsig, int smax, float *params,
+                            float *m, float *v, int t, float lr, float b1, float b2, float eps, float *gout,
+                            float *lout, float *grads, float *losses, hipStream_t s);
+hipError_t launch_learned(const StageArgs &a, int nprob, const float *params, const double *fixed_slots,
+                          hipStream_t s);
+
 hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
 
 }  // namespace ifnso

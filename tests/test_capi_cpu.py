@@ -63,7 +63,45 @@ def test_sum_one_flag(L):
 def test_unsupported_combinations(L):
     assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_F32, ind=ifn.BF16)[0] == 2
     assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_BF16, ind=ifn.F32)[0] == 2
-    assert _plan(L, [0, 1], [1, 1], mode=1)[0] == 2
+    assert _plan(L, [0, 1], [1, 1], mode=1)[0] == 1  # learned mode without parameters
+
+
+def test_learned_mode_requirements(L):
+    params = (ctypes.c_float * ifn.MLP_NUM_PARAMS)(*([0.0] * ifn.MLP_NUM_PARAMS))
+
+    def plan(exps, basis=0, norm=0, compute=1, n=ifn.MLP_NUM_PARAMS):
+        e = (ctypes.c_int32 * len(exps))(*exps)
+        c = (ctypes.c_double * len(exps))(*([1.0 / len(exps)] * len(exps)))
+        d = ifn.PolyDesc(len(exps), e, c, basis, norm, compute, 1, params, n, 0)
+        r = (ctypes.c_int64 * 1)(64)
+        cc = (ctypes.c_int64 * 1)(96)
+        h = ctypes.c_void_p()
+        return L.ifnso_plan(ctypes.byref(d), 1, r, cc, 1 if compute else 0, 1 if compute else 0, 0, ctypes.byref(h))
+
+    assert plan([0, 1, 2, 4, 8]) == 2                     # other exponents: not predicted
+    assert plan([0, 1, 2, 4, 8, 16], basis=1) == 2        # complement basis
+    assert plan([0, 1, 2, 4, 8, 16], norm=1) == 2
+    assert plan([0, 1, 2, 4, 8, 16], compute=0) == 2      # float32 compute
+    assert plan([0, 1, 2, 4, 8, 16], n=100) == 1          # wrong parameter count
+    params[7] = float("inf")
+    assert plan([0, 1, 2, 4, 8, 16]) == 1                 # non-finite parameter
+    params[7] = 0.0
+
+
+def test_mlp_entry_points_reject_bad_arguments(L):
+    assert L.ifnso_mlp_features(0, 16, 16, 8, 16, None) == 1
+    assert L.ifnso_mlp_forward(1, None, 16, 16, None) == 1
+    assert L.ifnso_mlp_train_workspace_bytes(0) == 0
+    need = L.ifnso_mlp_train_workspace_bytes(4)
+    assert need >= 4 * ifn.MLP_NUM_PARAMS * 4
+    args = [4, 16, 16, 16, 8, 16, 16, 16, 1, 1e-3, 0.9, 0.999, 1e-8, None, None]
+    assert L.ifnso_mlp_train_step(*args, 256, need - 1, None) == 3
+    bad = list(args)
+    bad[10] = 1.5  # beta1 outside [0, 1)
+    assert L.ifnso_mlp_train_step(*bad, 256, need, None) == 1
+    bad = list(args)
+    bad[8] = 0  # step number
+    assert L.ifnso_mlp_train_step(*bad, 256, need, None) == 1
 
 
 def test_null_arguments(L):

@@ -6,3 +6,4 @@ consume the bytes produced by these generators.
 """
 from .gen import *  # noqa: F401,F403
 from .configs import *  # noqa: F401,F403
+from .spectra import *  # noqa: F401,F403
