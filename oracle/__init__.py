@@ -7,3 +7,4 @@ the library itself never does, and this package imports nothing from the library
 from .ifnso import *  # noqa: F401,F403
 from .coeffs import *  # noqa: F401,F403
 from .mlp import *  # noqa: F401,F403
+from . import fp8  # noqa: F401
