@@ -10,6 +10,11 @@ One step = one batched call over all 224 matrices (Gram, 4 squarings, product).
 Prints one JSON line. `value` is matrices/s over the timed region, with the inputs
 already resident in HBM. The roofline entry is for the kernel with the largest time per
 step, timed with HIP events recorded around each stage inside the timed region.
+
+`--workload e4m3` measures the e4m3 variant instead: 64 matrices 2048x8192 built as
+U diag(sigma) V^T with Haar factors and sigma_i = i^-1.5 (seed 3), e4m3 Gram and squarings
+with per-tensor scales, bfloat16 aggregation and product; it reports the error of the
+e4m3 and bfloat16 modes against the FP64 oracle on a sample of the batch.
 """
 from __future__ import annotations
 
@@ -25,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
+PEAK_FP8_TFLOPS = 5000.0   # MI355X dense fp8 MFMA
 PEAK_F32_TFLOPS = 157.3    # MI355X dense fp32 MFMA
 
 
@@ -45,6 +51,19 @@ def make_d3(torch, dev, layers=32):
             m = gen.lowrank_plus_noise_torch(r, c, configs.d3_seed(l, idx), device=dev)
             Ms.append(gen.round_to_bf16_torch(m))
             del m
+    torch.cuda.synchronize()
+    return Ms
+
+
+def make_e4m3_set(torch, dev, batch):
+    from workloads import configs, gen
+    r, c = configs.D4_SHAPE
+    sigma = configs.d4_sigma(min(r, c))
+    Ms = []
+    for i in range(batch):
+        m, u, v = gen.spectral_torch(r, c, sigma, configs.d4_seed(i), device=dev)
+        Ms.append(gen.round_to_bf16_torch(m))
+        del m, u, v
     torch.cuda.synchronize()
     return Ms
 
@@ -77,6 +96,165 @@ def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
                       f"2x 14336x4096, 1x 4096x14336), float64 numpy, {dt:.1f} s"}, rel, orth
 
 
+def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
+    """Warm-up, graph-replay timing, then `steps` timed calls with a HIP event before every
+    launch slot (on the call's stream) and one after the last. Returns per-kernel
+    (ms per step, launches per step, algorithmic flops per step), the timed wall time and
+    the graph-replay ms per step."""
+    import numpy as np
+    nl = plan.num_launches
+    info = [plan.launch_info(i) for i in range(nl)]
+    for _ in range(warmup):
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # graph replay (no events)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(warmup):
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg0) / max(warmup, 1) * 1e3
+
+    # the timed region: K steps, a HIP event before every launch slot and one after the last
+    evs = []
+    for _ in range(steps):
+        row = []
+        for _ in range(nl + 1):
+            e = ctypes.c_void_p()
+            assert hip.hipEventCreate(ctypes.byref(e)) == 0
+            row.append(e.value)
+        evs.append(row)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        plan.launch_events(evs[k])
+        plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {steps} steps: {elapsed:.3f} s")
+    slot_ms = np.zeros((steps, nl))
+    f = ctypes.c_float()
+    for k in range(steps):
+        for i in range(nl):
+            assert hip.hipEventElapsedTime(ctypes.byref(f), evs[k][i], evs[k][i + 1]) == 0
+            slot_ms[k, i] = f.value
+    for row in evs:
+        for e in row:
+            hip.hipEventDestroy(e)
+    per = slot_ms.mean(axis=0)
+    kern = {}
+    for i, nm in enumerate(names):
+        t, n_l, flop = kern.get(nm, (0.0, 0, 0.0))
+        if info[i][1] > 0 or (nm == "aggregate" and per[i] > 0.01):
+            kern[nm] = (t + per[i], n_l + 1, flop + info[i][1])
+    return {"kern": kern, "elapsed": elapsed, "graph_ms": graph_ms, "slot_ms": per}
+
+
+def run_e4m3(args, torch, dev, hip, log):
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs
+    exps, coeffs = configs.load_coeffs("gform_v1")
+    t0 = time.perf_counter()
+    Ms = make_e4m3_set(torch, dev, args.batch)
+    shapes = [tuple(m.shape) for m in Ms]
+    n = len(Ms)
+    log(f"generated {n} matrices in {time.perf_counter() - t0:.1f} s")
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan = ifn.Plan(exps, coeffs, shapes, compute="fp8")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+    nl = plan.num_launches
+    J = nl - 6
+    fl = stage_flops(shapes, J)
+    names = ["prepass_quant", "gram8_wide", "gram8_tall"] + ["square8"] * J + \
+            ["aggregate", "product_wide", "product_tall"]
+    t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
+    kern, elapsed = t["kern"], t["elapsed"]
+    slot = t["slot_ms"]
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n * args.steps / elapsed
+    peak = {"gram8_wide": PEAK_FP8_TFLOPS, "gram8_tall": PEAK_FP8_TFLOPS, "square8": PEAK_FP8_TFLOPS,
+            "product_wide": PEAK_BF16_TFLOPS, "product_tall": PEAK_BF16_TFLOPS}
+    dom = max((k for k in kern if kern[k][2] > 0), key=lambda k: kern[k][0])
+    dur_ms = kern[dom][0] / kern[dom][1]
+    achieved = kern[dom][2] / kern[dom][1] / (dur_ms * 1e-3) / 1e12
+    # mixed roofline of the step: e4m3 Gram and squarings, bfloat16 product
+    t_min_ms = ((fl["gram"] + J * fl["square"]) / (PEAK_FP8_TFLOPS * 1e12) + fl["product"] / (PEAK_BF16_TFLOPS * 1e12)) * 1e3
+    hw = sum(r * c for r, c in shapes)
+    prep_bytes = 5.0 * hw  # pre-pass reads M, quantisation reads M and writes e4m3 A
+    extra = {"graph_ms_per_step": round(t["graph_ms"], 3),
+             "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
+                             "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
+                         for k, v in kern.items()},
+             "prepass_quant_gbps": round(prep_bytes / (slot[0] * 1e-3) / 1e9, 1) if slot[0] > 0 else None,
+             "algorithmic_tflop_per_step": round(fl["step"] / 1e12, 3),
+             "mixed_roofline_ms": round(t_min_ms, 3), "mixed_roofline_frac": round(t_min_ms / ms_per_step, 4)}
+    # the same batch in bfloat16, for the speed ratio and the error comparison
+    Yb = [torch.empty_like(m) for m in Ms]
+    del ws
+    planb = ifn.Plan(exps, coeffs, shapes, compute="bf16")
+    wsb = torch.empty(planb.workspace_bytes, dtype=torch.uint8, device=dev)
+    planb.orthogonalize_batched(Ms, Yb, wsb)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(3):
+        planb.orthogonalize_batched(Ms, Yb, wsb)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - tb) / 3
+    extra["bf16_path"] = {"matrices_per_s": round(n / tb, 2), "speedup_e4m3_over_bf16": round(value / (n / tb), 3)}
+    del wsb, planb
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    hs = np.sqrt([min(s) for s in shapes])
+    ifn.orth_error(Ys, out, ows)
+    extra["orth_err_over_sqrt_h_mean"] = {"e4m3": float((out.cpu().numpy() / hs).mean())}
+    ifn.orth_error(Yb, out, ows)
+    extra["orth_err_over_sqrt_h_mean"]["bf16"] = float((out.cpu().numpy() / hs).mean())
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from oracle import fp8 as F
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        idx = [0, 1]
+        log("running the CPU oracle on 2 matrices ...")
+        rel8, relb, relm = [], [], []
+        dt = 0.0
+        for i in idx:
+            Mh = Ms[i].float().cpu().numpy().astype(np.float64)
+            c0 = time.perf_counter()
+            Yo = oracle.ifnso(Mh, exps, coeffs)
+            dt += time.perf_counter() - c0
+            y8 = Ys[i].float().cpu().numpy().astype(np.float64)
+            yb = Yb[i].float().cpu().numpy().astype(np.float64)
+            rel8.append(float(np.linalg.norm(y8 - Yo) / np.linalg.norm(Yo)))
+            relb.append(float(np.linalg.norm(yb - Yo) / np.linalg.norm(Yo)))
+            Ym = F.ifnso_e4m3(Mh, exps, coeffs)
+            relm.append(float(np.linalg.norm(y8 - Ym) / np.linalg.norm(Ym)))
+        extra["rel_err_vs_fp64_oracle"] = {"e4m3": rel8, "bf16": relb, "e4m3_vs_e4m3_model": relm}
+        cpu = {"value": len(idx) / dt, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{len(idx)} matrices of the batch (2048x8192), float64 numpy, {dt:.1f} s"}
+    line = {
+        "metric": "matrices/s on the e4m3 workload; ||Y - Y_fp64|| vs FP64 oracle",
+        "value": round(value, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp8_e4m3+bf16", "data": "synthetic",
+        "config": {"workload": f"{n} x 2048x8192, U diag(i^-1.5) V^T Haar (seed 3), bf16 storage",
+                   "matrices": n, "exponents": list(exps), "coeffs": "gform_v1", "compute": "fp8_e4m3",
+                   "parallelism": "single GPU, one grouped launch per stage"},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak[dom],
+                     "unit": "TFLOP/s", "frac": round(achieved / peak[dom], 4), "traffic": None,
+                     "avg_launch_ms": round(dur_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +264,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
+    ap.add_argument("--workload", choices=["gradset", "e4m3"], default="gradset",
+                    help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
+                         "heavy-tailed matrices with e4m3 Gram and squarings")
+    ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
@@ -102,6 +284,8 @@ def main():
     torch.cuda.set_device(dev)
     hip = _hip()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.workload == "e4m3":
+        return run_e4m3(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()
@@ -120,51 +304,8 @@ def main():
     # kernel of each launch slot (squaring levels share one kernel)
     names = ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
 
-    for _ in range(args.warmup):
-        plan.orthogonalize_batched(Ms, Ys, ws)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    # graph replay (no events)
-    torch.cuda.synchronize()
-    tg0 = time.perf_counter()
-    for _ in range(args.warmup):
-        plan.orthogonalize_batched(Ms, Ys, ws)
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - tg0) / max(args.warmup, 1) * 1e3
-
-    # the timed region: K steps, a HIP event before every launch slot and one after the last
-    evs = []
-    for _ in range(args.steps):
-        row = []
-        for _ in range(nl + 1):
-            e = ctypes.c_void_p()
-            assert hip.hipEventCreate(ctypes.byref(e)) == 0
-            row.append(e.value)
-        evs.append(row)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        plan.launch_events(evs[k])
-        plan.orthogonalize_batched(Ms, Ys, ws)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} steps: {elapsed:.3f} s")
-    slot_ms = np.zeros((args.steps, nl))
-    f = ctypes.c_float()
-    for k in range(args.steps):
-        for i in range(nl):
-            assert hip.hipEventElapsedTime(ctypes.byref(f), evs[k][i], evs[k][i + 1]) == 0
-            slot_ms[k, i] = f.value
-    for row in evs:
-        for e in row:
-            hip.hipEventDestroy(e)
-    per = slot_ms.mean(axis=0)
-    kern = {}
-    for i, nm in enumerate(names):
-        t, n_l, flop = kern.get(nm, (0.0, 0, 0.0))
-        if info[i][1] > 0 or (nm == "aggregate" and per[i] > 0.01):
-            kern[nm] = (t + per[i], n_l + 1, flop + info[i][1])
+    t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
+    kern, elapsed, graph_ms = t["kern"], t["elapsed"], t["graph_ms"]
     dom = max((k for k in kern if kern[k][2] > 0), key=lambda k: kern[k][0])
     dur_ms = kern[dom][0] / kern[dom][1]
     flop_per_launch = kern[dom][2] / kern[dom][1]

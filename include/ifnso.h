@@ -53,9 +53,12 @@ typedef enum { IFNSO_F32 = 0, IFNSO_BF16 = 1 } ifnso_dtype;
 /* operand type of the matrix products (accumulation is always float32):
  *  F32   float32 operands on the FP32 matrix cores (the plain path; M must be F32)
  *  BF16  bfloat16 operands (M must be BF16)
- *  FP8_E4M3  OCP e4m3 operands for the Gram and the squarings, with one power-of-two
- *        scale per matrix from its absolute maximum; the final product uses bfloat16
- *        (M must be BF16) */
+ *  FP8_E4M3  OCP e4m3 operands (round to nearest even) for the Gram and the squarings, each
+ *        operand with its own power-of-two scale s = 2^floor(log2(448 / amax)) from the
+ *        absolute maximum of the tensor it quantises (A, then each stored power; exponent
+ *        clamped to [-63, 63]); ||A||_F comes from a float64 pre-pass over M; the stored powers,
+ *        their weighted sum and the final product use bfloat16. Gram basis only; M must be
+ *        BF16; problems need h * round_up(w, 16) < 2^31 and h <= 32512. */
 typedef enum { IFNSO_COMPUTE_F32 = 0, IFNSO_COMPUTE_BF16 = 1, IFNSO_COMPUTE_FP8_E4M3 = 2 } ifnso_compute;
 
 typedef enum { IFNSO_BASIS_GRAM = 0, IFNSO_BASIS_COMPLEMENT = 1 } ifnso_basis;
@@ -128,15 +131,19 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
                                          void *const *Y, const int64_t *ldy, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
-/* Launch slots of one call of this plan, in order: Gram for the problems with rows <= cols,
- * Gram for the transposed (rows > cols) problems, one squaring per level, the aggregation of
- * the weighted powers, then the product for the two groups in the same order: J + 5 slots
- * where 2^J is the largest exponent. A slot with no work in a call launches nothing (the
- * aggregation runs only when the levels are kept, i.e. bfloat16 Gram-basis plans with J >= 1).
- * Returns the count, or a negative status for NULL. */
+/* Launch slots of one call of this plan, in order: FP8_E4M3 plans only, the pre-pass
+ * (||A||_F and amax) with the e4m3 quantisation of A; Gram for the problems with
+ * rows <= cols, Gram for the transposed (rows > cols) problems, one squaring per level (in
+ * FP8_E4M3 plans with the quantisation of the power it squares), the aggregation of the
+ * weighted powers, then the product for the two groups in the same order: J + 5 slots
+ * (J + 6 for FP8_E4M3) where 2^J is the largest exponent. A slot with no work in a call
+ * launches nothing (the aggregation runs only when the levels are kept: bfloat16 Gram-basis
+ * plans with J >= 1, and every FP8_E4M3 plan). Returns the count, or a negative status for
+ * NULL. */
 int32_t ifnso_plan_num_launches(ifnso_plan_t plan);
 
-/* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation) and its algorithmic
+/* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation, 4 FP8_E4M3 pre-pass
+ * and input quantisation, with 0 flops) and its algorithmic
  * flop count: h^2 w per problem for the Gram (symmetric), h^3 per problem for a squaring
  * (symmetric), 2 h^2 w per problem for the product, 0 for the (memory-bound) aggregation.
  * Errors: INVALID_ARGUMENT. */
@@ -162,6 +169,18 @@ ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64
 
 /* Workspace bytes for ifnso_classical_ns with these dimensions (0 on bad arguments). */
 size_t ifnso_classical_ns_workspace_bytes(int64_t rows, int64_t cols, int32_t compute);
+
+/* The input side of the FP8_E4M3 mode on its own: A (= M, or M^T when rows > cols; h x w,
+ * h <= w) quantised to OCP e4m3 with the per-tensor power-of-two scale of ifnso_compute,
+ * Q[i][k] = e4m3(s A[i][k]) for k < w and 0 for w <= k < round_up(w, 16): the K-major operand
+ * the e4m3 Gram reads. M: device BF16, rows x cols, ldm. Q: device, h rows of ldq bytes
+ * (ldq >= round_up(w, 16), ldq % 16 == 0, 16-byte aligned). out3: device double[3] =
+ * {||A||_F^2 (float64 sum), max |A|, s}. Workspace: device, 256-byte aligned,
+ * ifnso_quantize_e4m3_workspace_bytes(rows, cols) bytes.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED (h * ldq >= 2^31), WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_quantize_e4m3(const void *M, int64_t rows, int64_t cols, int64_t ldm, void *Q, int64_t ldq,
+                                 double *out3, void *workspace, size_t workspace_bytes, void *stream);
+size_t ifnso_quantize_e4m3_workspace_bytes(int64_t rows, int64_t cols);
 
 /* Orthogonality error of the Experiment section, e = ||Z Z^T - I||_F with Z = Y in the
  * h <= w orientation, computed on the device in float64 for `count` matrices (host arrays

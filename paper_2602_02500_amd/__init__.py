@@ -101,6 +101,10 @@ def load() -> ctypes.CDLL:
     L.ifnso_mlp_train_step.restype = ctypes.c_int
     L.ifnso_mlp_train_workspace_bytes.argtypes = [i32]
     L.ifnso_mlp_train_workspace_bytes.restype = sz
+    L.ifnso_quantize_e4m3.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
+    L.ifnso_quantize_e4m3.restype = ctypes.c_int
+    L.ifnso_quantize_e4m3_workspace_bytes.argtypes = [i64, i64]
+    L.ifnso_quantize_e4m3_workspace_bytes.restype = sz
     L.ifnso_last_error.restype = ctypes.c_char_p
     for name in ("ifnso_plan", "ifnso_plan_workspace_bytes", "ifnso_plan_destroy", "ifnso_orthogonalize",
                  "ifnso_orthogonalize_batched", "ifnso_classical_ns", "ifnso_orth_error"):
@@ -240,6 +244,20 @@ def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=N
     nb = workspace.numel() * workspace.element_size()
     _check(L.ifnso_classical_ns(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
                                 int(steps), abc_c, comp, _ptr(workspace), nb, _stream(stream)))
+
+
+def quantize_e4m3_workspace_bytes(rows: int, cols: int) -> int:
+    return int(load().ifnso_quantize_e4m3_workspace_bytes(int(rows), int(cols)))
+
+
+def quantize_e4m3(M, Q, out3, workspace, stream=None):
+    """e4m3 copy of A (M, or M^T when tall) into the uint8 matrix Q (h x ldq), with
+    out3 (float64, 3) = (||A||_F^2, max |A|, scale)."""
+    L = load()
+    rows, cols = M.shape
+    nb = workspace.numel() * workspace.element_size()
+    _check(L.ifnso_quantize_e4m3(_ptr(M), rows, cols, int(M.stride(0)), _ptr(Q), int(Q.stride(0)), _ptr(out3),
+                                 _ptr(workspace), nb, _stream(stream)))
 
 
 def orth_error(Ys, out, workspace, stream=None):

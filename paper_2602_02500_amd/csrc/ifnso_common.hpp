@@ -36,7 +36,16 @@ struct ProbDev {
   int64_t ldx;
   void *lv;            // level layout: level l (l = 1..J+1) stored at lv + (l-1) * lv_stride bytes,
   int64_t lv_stride;   //   as a full symmetric h x h operand; level 1 later holds P
-  int32_t pad_[2];
+  // e4m3 compute: per-tensor scaled OCP e4m3 copy of A (h rows, leading dimension ldq, K
+  // contiguous, zero beyond w) for the Gram, later of the current level (hp x hp) for a squaring
+  uint8_t *q8;
+  int64_t ldq;
+  double *q_part;      // [nq] pre-pass sums of squares of M, chunks of rq storage rows
+  float *q_amax;       // [nq] pre-pass max |M| per chunk
+  float *amax_part;    // [levels][nt*nt] max |stored level| per tile (upper tiles)
+  float *q_scale;      // [2 (kMaxLevels + 1)]: [2l] scale (a power of two), [2l + 1] max |value|;
+                       //   l = 0 the input, l >= 1 level l
+  int32_t nq, rq;
 };
 
 // One tile of work: problem index, tile row, tile column, stage-specific flags.

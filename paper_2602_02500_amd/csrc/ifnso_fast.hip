@@ -82,7 +82,7 @@ __device__ __forceinline__ int swz(int row) { return (row ^ (row >> 3)) & 7; }
 // operand loaders
 // ---------------------------------------------------------------------------------------------
 // K-major operand of ROWS rows straight into LDS: wave-instruction g covers rows 8g..8g+7.
-template <int ROWS>
+template <int ROWS, int ES = 2>
 __device__ __forceinline__ void issue_kmaj(uint32_t lt, const i32x4 &r, uint32_t ld_bytes, int m0, int mlim, int k0,
                                            int klim) {
   const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -91,8 +91,8 @@ __device__ __forceinline__ void issue_kmaj(uint32_t lt, const i32x4 &r, uint32_t
     const int g = i * 4 + wave;
     const int row = g * 8 + (lane >> 3);
     const int c = (lane & 7) ^ swz(row);
-    const int m = m0 + row, k = k0 + c * 8;
-    const uint32_t off = (m < mlim && k < klim) ? (uint32_t)m * ld_bytes + (uint32_t)k * 2u : OOB;
+    const int m = m0 + row, k = k0 + c * (16 / ES);
+    const uint32_t off = (m < mlim && k < klim) ? (uint32_t)m * ld_bytes + (uint32_t)k * (uint32_t)ES : OOB;
     dma16(r, off, lt + g * 1024);
   }
 }
@@ -190,9 +190,15 @@ __device__ __forceinline__ Operand make_operand(const void *p, uint32_t bytes, u
   return o;
 }
 
-template <bool AMN, bool BMN>
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// F8: both operands K-major OCP e4m3 (1 byte, 128 per LDS row and stage), MFMA 32x32x64.
+template <bool AMN, bool BMN, bool F8 = false>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                            const Operand &B, int bn0, int K, bool want_norm) {
+  static_assert(!F8 || (!AMN && !BMN), "e4m3 operands are K-major");
+  constexpr int ES = F8 ? 1 : 2;
+  constexpr int KST = 128 / ES;  // elements per stage
   const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lg = lane >> 5;
@@ -202,7 +208,7 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
     for (int j = 0; j < FN; j++)
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-  const int nk = (K + BK - 1) / BK;
+  const int nk = (K + KST - 1) / KST;
   double nrm = 0.0;
   uint4 va[8], vb[8];
   // loads issued per stage by one thread (K-major: ROWS/32 per operand)
@@ -210,9 +216,9 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
   const uint32_t lbase = uni(lds_addr(smem));
   auto issue = [&](int kt, int buf) {
     const uint32_t As = lbase + buf * STAGE_BYTES, Bs = As + BM * 128;
-    const int k0 = kt * BK;
-    if constexpr (!AMN) issue_kmaj<BM>(As, A.w, A.ld_bytes, am0, A.lim, k0, K);
-    if constexpr (!BMN) issue_kmaj<BN>(Bs, B.w, B.ld_bytes, bn0, B.lim, k0, K);
+    const int k0 = kt * KST;
+    if constexpr (!AMN) issue_kmaj<BM, ES>(As, A.w, A.ld_bytes, am0, A.lim, k0, K);
+    if constexpr (!BMN) issue_kmaj<BN, ES>(Bs, B.w, B.ld_bytes, bn0, B.lim, k0, K);
     if constexpr (AMN) load_mnmaj<BM>(va, A.r, A.ld_bytes, am0, A.lim, k0, K);
     if constexpr (BMN) load_mnmaj<BN>(vb, B.r, B.ld_bytes, bn0, B.lim, k0, K);
   };
@@ -242,10 +248,35 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
     }
     __syncthreads();
     const char *As = smem + cur * STAGE_BYTES, *Bs = As + BM * 128;
-    if constexpr (!AMN) {
+    if constexpr (!AMN && !F8) {
       if (want_norm) nrm += lds_sumsq(As);
     }
-    {
+    if constexpr (F8) {
+      // two 64-deep slices per stage; a fragment is 32 bytes (two LDS chunks) per lane
+#pragma unroll
+      for (int kk = 0; kk < 2; kk++) {
+        i32x8 fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; i++) {
+          const int row = wm * WM + i * 32 + lr;
+          const uint4 lo = *(const uint4 *)(As + lds_off(row, 4 * kk + 2 * lg));
+          const uint4 hi = *(const uint4 *)(As + lds_off(row, 4 * kk + 2 * lg + 1));
+          fa[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int j = 0; j < FN; j++) {
+          const int row = wn * WN + j * 32 + lr;
+          const uint4 lo = *(const uint4 *)(Bs + lds_off(row, 4 * kk + 2 * lg));
+          const uint4 hi = *(const uint4 *)(Bs + lds_off(row, 4 * kk + 2 * lg + 1));
+          fb[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int j = 0; j < FN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 0, 0, 0);
+      }
+    } else {
       // fragments of K slice kk+1 are read from LDS while slice kk's 16 MFMAs run
       // (one LDS read per two MFMAs)
       bf16x8 fa[2][FM], fb[2][FN];
@@ -430,6 +461,66 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
   }
 }
 
+__device__ __forceinline__ float block_max(float v, float *scratch) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
+  __syncthreads();
+  return v;
+}
+
+// Level-layout epilogue: level `out` = scale * acc is stored as bfloat16 (tile and mirror) at
+// lv + (out - 1) * lv_stride with the partials of its sum of squares and trace (each
+// thread's sum of a row segment in float32, accumulated in float64). With AMAX, also the
+// tile's max |stored value| (the next e4m3 quantisation needs the level's maximum); it is
+// taken before the bfloat16 rounding, which is monotone, so it rounds to the maximum of the
+// stored values.
+template <bool AMAX>
+__device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *smem, const ProbDev &P, int out,
+                                            const Task &task, float scale) {
+  float *ep = (float *)smem;
+  const int m0 = task.tm * BM, n0 = task.tn * BN;
+  const bool diag = task.tm == task.tn;
+  const int64_t hp = P.hp;
+  uint16_t *dst = (uint16_t *)((char *)P.lv + (int64_t)(out - 1) * P.lv_stride);
+  double lv = 0.0, dg = 0.0, unused = 0.0;
+  float mx = 0.f;
+  for (int half = 0; half < 2; half++) {
+    stage_half(acc, ep, half);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
+      const int row = q >> 6, c4 = (q & 63) * 4;
+      const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
+      const float x0 = scale * v.x, x1 = scale * v.y, x2 = scale * v.z, x3 = scale * v.w;
+      lv += (diag ? 1.0 : 2.0) * (double)(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
+      if constexpr (AMAX) mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fmaxf(fabsf(x2), fabsf(x3))));
+      if (diag) {
+        const int d = half * 128 + row - c4;
+        if (d >= 0 && d < 4) dg += d == 0 ? x0 : d == 1 ? x1 : d == 2 ? x2 : x3;
+      }
+    }
+    emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [scale](float v, int, int) { return scale * v; });
+    __syncthreads();
+  }
+  block_sum3(lv, dg, unused, (double *)smem);
+  if constexpr (AMAX) mx = block_max(mx, (float *)smem);
+  if (threadIdx.x == 0) {
+    write_level_partials(P, out, task, lv, dg);
+    if constexpr (AMAX) {
+      const int nt = P.nt, r0 = 2 * task.tm, c0 = 2 * task.tn;
+      float *ap = P.amax_part + (int64_t)out * nt * nt;
+      ap[r0 * nt + c0] = mx;
+      ap[r0 * nt + c0 + 1] = 0.f;
+      ap[(r0 + 1) * nt + c0 + 1] = 0.f;
+      if (task.tm != task.tn) ap[(r0 + 1) * nt + c0] = 0.f;
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
@@ -534,28 +625,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
     if constexpr (AGG) {
-      // level layout: store level+1 = f_out * acc (bf16, tile and mirror) and its partials
-      // (each thread's sum of a row segment in float32, accumulated in float64)
-      for (int half = 0; half < 2; half++) {
-        stage_half(acc, ep, half);
-        __syncthreads();
-        for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
-          const int row = q >> 6, c4 = (q & 63) * 4;
-          const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
-          const float x0 = f_out * v.x, x1 = f_out * v.y, x2 = f_out * v.z, x3 = f_out * v.w;
-          lv += (diag ? 1.0 : 2.0) * (double)(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
-          if (diag) {
-            const int d = half * 128 + row - c4;
-            if (d >= 0 && d < 4) dg += d == 0 ? x0 : d == 1 ? x1 : d == 2 ? x2 : x3;
-          }
-        }
-        const float fo = f_out;
-        emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [fo](float v, int, int) { return fo * v; });
-        __syncthreads();
-      }
-      block_sum3(lv, dg, unused, (double *)smem);
-      if (threadIdx.x == 0) write_level_partials(P, level + 1, task, lv, dg);
-      __syncthreads();
+      store_level<false>(acc, smem, P, level + 1, task, f_out);
       continue;
     } else {
     for (int half = 0; half < 2; half++) {
@@ -624,6 +694,58 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// e4m3 Gram and squaring: both operands are the problem's e4m3 buffer q8 (K contiguous, scale
+// s); the float32 accumulator holds s^2 times the product, removed by the exact power-of-two
+// factor 1/s^2 in the epilogue. Levels are stored as in the bfloat16 level layout, with tile
+// maxima for the quantisation of the next level.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float inv_square(float s) { return 1.f / s / s; }
+
+__global__ __launch_bounds__(kThreads, 1) void kf_gram8(const StageArgs a) {
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  const TaskRange tr = task_range(a);
+  for (int t = tr.start; t < tr.end; t += tr.stride) {
+    Task task = fetch(a, tr.base + t, kStageGram);
+    task.p = uni(task.p);
+    task.tm = uni(task.tm);
+    task.tn = uni(task.tn);
+    const ProbDev &P = prob(a, task);
+    const float dscale = inv_square(P.q_scale[0]);
+    const int ldq = uni((int)P.ldq);
+    const Operand op = make_operand(P.q8, (uint32_t)((int64_t)P.h * ldq), (uint32_t)ldq, P.h);
+    f32x16 acc[FM][FN];
+    mainloop<false, false, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, ldq, false);
+    store_level<true>(acc, smem, P, 1, task, dscale);
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 1) void kf_square8(const StageArgs a) {
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  const int level = a.level;
+  int cur_p = -1;
+  float f_out = 1.f;
+  const TaskRange tr = task_range(a);
+  for (int t = tr.start; t < tr.end; t += tr.stride) {
+    Task task = fetch(a, tr.base + t, kStageSquare);
+    task.p = uni(task.p);
+    task.tm = uni(task.tm);
+    task.tn = uni(task.tn);
+    const ProbDev &P = prob(a, task);
+    if (task.p != cur_p) {
+      cur_p = task.p;
+      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt)) *
+              inv_square(P.q_scale[2 * level]);
+    }
+    const int64_t hp = P.hp;
+    const Operand op = make_operand(P.q8, (uint32_t)(hp * hp), (uint32_t)hp, P.hp);
+    f32x16 acc[FM][FN];
+    mainloop<false, false, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, uni(P.h), false);
+    store_level<true>(acc, smem, P, level + 1, task, f_out);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // product: Y = s (c0 A + P A) in M's orientation (IFNSO only)
 // ---------------------------------------------------------------------------------------------
 template <bool TRANS>
@@ -655,7 +777,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
         ps = 0.0;
       } else if (a.basis == kGram) {
         c0 = P.coef[0];
-        ps = (a.J == 0) ? P.coef[1] * sc.sg : 1.0;
+        ps = (a.J == 0 && !a.agg) ? P.coef[1] * sc.sg : 1.0;  // the aggregate stage folds c_1 S_1 into P
       } else {
         c0 = 0.0;
         for (int k = 0; k < kSlots; k++) c0 += P.coef[k];
@@ -816,6 +938,13 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
     if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
     else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  if (stage == kStageGram) hipLaunchKernelGGL(fast::kf_gram8, dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(fast::kf_square8, dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

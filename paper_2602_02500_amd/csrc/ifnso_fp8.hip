@@ -1,0 +1,259 @@
+// Memory-bound passes of the e4m3 compute mode: per-tensor amax and sum of squares of the
+// input, quantisation of A (transposed for tall inputs) and of each stored level to OCP e4m3
+// with a power-of-two scale. The e4m3 Gram and squaring GEMMs live with the other 256 x 256
+// kernels; they consume what these passes write.
+//
+// Scale rule: s = 2^e with e = floor(log2(448 / amax)) (448 is e4m3's largest finite value),
+// so the scaled maximum lies in (224, 448] and the scaling itself is exact; e is clamped to
+// [-63, 63] so that 1 / s^2 stays a normal float. Conversion: v_cvt_pk_fp8_f32, round to
+// nearest even.
+//
+// These kernels take problems from blockIdx.y (one problem per grid row) and stride over the
+// problem's work with blockIdx.x, so they need no task list.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ifnso_common.hpp"
+#include "ifnso_launch.hpp"
+#include "ifnso_tile.hpp"
+
+namespace ifnso {
+namespace e4m3 {
+
+__device__ __forceinline__ const ProbDev &problem(const StageArgs &a) { return a.probs ? a.probs[blockIdx.y] : a.one; }
+
+__device__ __forceinline__ float scale_from_amax(float amax) {
+  if (!(amax > 0.f) || !isfinite(amax)) return 1.f;
+  int x;
+  const float f = frexpf(amax, &x);  // amax = f 2^x, f in [0.5, 1)
+  int e = (2.f * f <= 1.75f ? 9 : 8) - x;
+  e = e < -63 ? -63 : (e > 63 ? 63 : e);
+  return ldexpf(1.f, e);
+}
+
+// four floats -> four e4m3 bytes, first value in the lowest byte
+__device__ __forceinline__ uint32_t pack4(float a, float b, float c, float d) {
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+  return (uint32_t)v;
+}
+
+__device__ __forceinline__ uint4 pack16(const float (&x)[16], float s) {
+  return make_uint4(pack4(s * x[0], s * x[1], s * x[2], s * x[3]), pack4(s * x[4], s * x[5], s * x[6], s * x[7]),
+                    pack4(s * x[8], s * x[9], s * x[10], s * x[11]),
+                    pack4(s * x[12], s * x[13], s * x[14], s * x[15]));
+}
+
+__device__ __forceinline__ void unpack8(const uint4 &v, float *x) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    x[2 * i] = __uint_as_float(w[i] << 16);
+    x[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
+__device__ __forceinline__ float block_max(float v, float *scratch) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
+  __syncthreads();
+  return v;
+}
+
+// max over the upper tiles (c >= r) of an nt x nt grid of tile maxima
+__device__ __forceinline__ float max_upper(const float *p, int nt, float *scratch) {
+  float m = 0.f;
+  for (int i = threadIdx.x; i < nt * nt; i += blockDim.x) {
+    const int r = i / nt, c = i - r * nt;
+    if (c >= r) m = fmaxf(m, p[i]);
+  }
+  return block_max(m, scratch);
+}
+
+// ---------------------------------------------------------------------------------------------
+// pre-pass: per chunk of rq storage rows of M, the float64 sum of squares and max |value|
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_prepass(const StageArgs a) {
+  __shared__ double dscr[12];
+  __shared__ float fscr[4];
+  const ProbDev &P = problem(a);
+  const int rows = P.trans ? P.w : P.h, cols = P.trans ? P.h : P.w;
+  const uint16_t *M = (const uint16_t *)P.M;
+  const bool vec = P.vecM && (cols % 8) == 0;
+  for (int c = blockIdx.x; c < P.nq; c += gridDim.x) {
+    const int r0 = c * P.rq, r1 = min(rows, r0 + P.rq);
+    double ss = 0.0;
+    float mx = 0.f;
+    if (vec) {
+      const int gpr = cols / 8;  // 8-element groups per row
+      const int64_t ng = (int64_t)(r1 - r0) * gpr;
+      for (int64_t g = threadIdx.x; g < ng; g += kThreads) {
+        const int r = r0 + (int)(g / gpr), k = (int)(g % gpr) * 8;
+        float x[8];
+        unpack8(*(const uint4 *)(M + (int64_t)r * P.ldm + k), x);
+        float s8 = 0.f;  // squares of bfloat16 values are exact in float32
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          s8 = fmaf(x[i], x[i], s8);
+          mx = fmaxf(mx, fabsf(x[i]));
+        }
+        ss += (double)s8;
+      }
+    } else {
+      const int64_t n = (int64_t)(r1 - r0) * cols;
+      for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+        const int r = r0 + (int)(e / cols), k = (int)(e % cols);
+        const float x = bf16_to_f32(M[(int64_t)r * P.ldm + k]);
+        ss = fma((double)x, (double)x, ss);
+        mx = fmaxf(mx, fabsf(x));
+      }
+    }
+    double u0 = 0.0, u1 = 0.0;
+    block_sum3(ss, u0, u1, dscr);
+    mx = block_max(mx, fscr);
+    if (threadIdx.x == 0) {
+      P.q_part[c] = ss;
+      P.q_amax[c] = mx;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// quantise A: q8[i][k] = e4m3(s A[i][k]) for k < w, 0 for w <= k < ldq (A = M, or M^T when tall).
+// Block 0 of each problem also stores ||A||_F^2 (fixed-order sum of the chunk partials) in
+// norm_part[0] (zeros in the other slots), the scale and the maximum.
+// ---------------------------------------------------------------------------------------------
+constexpr int kTile = 64;
+
+__global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
+  __shared__ float fscr[4];
+  __shared__ uint16_t tile[kTile][kTile + 2];
+  const ProbDev &P = problem(a);
+  float mx = 0.f;
+  for (int i = threadIdx.x; i < P.nq; i += kThreads) mx = fmaxf(mx, P.q_amax[i]);
+  mx = block_max(mx, fscr);
+  const float s = scale_from_amax(mx);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) {
+      const double t = wave_sum(P.q_part, P.nq);
+      if (threadIdx.x == 0) {
+        P.norm_part[0] = t;
+        P.q_scale[0] = s;
+        P.q_scale[1] = mx;
+      }
+    }
+    for (int i = 1 + threadIdx.x; i < P.nt; i += kThreads) P.norm_part[i] = 0.0;
+  }
+  const uint16_t *M = (const uint16_t *)P.M;
+  const int h = P.h, w = P.w;
+  const int64_t ldq = P.ldq;
+  const int gpr = (int)(ldq / 16);  // 16-element groups per row of q8
+  if (!P.trans) {
+    const bool vec = P.vecM && (w % 8) == 0;
+    const int64_t ng = (int64_t)h * gpr;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < ng; g += (int64_t)gridDim.x * kThreads) {
+      const int i = (int)(g / gpr), k = (int)(g % gpr) * 16;
+      const uint16_t *src = M + (int64_t)i * P.ldm + k;
+      float x[16];
+      if (vec) {
+        if (k < w) unpack8(*(const uint4 *)src, x);
+        else for (int j = 0; j < 8; j++) x[j] = 0.f;
+        if (k + 8 < w) unpack8(*(const uint4 *)(src + 8), x + 8);
+        else for (int j = 8; j < 16; j++) x[j] = 0.f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; j++) x[j] = k + j < w ? bf16_to_f32(src[j]) : 0.f;
+      }
+      *(uint4 *)(P.q8 + (int64_t)i * ldq + k) = pack16(x, s);
+    }
+    return;
+  }
+  // tall M (w x h storage): 64 x 64 tiles through LDS
+  const bool vec = P.vecM && (h % 8) == 0;
+  const int ti = (h + kTile - 1) / kTile, tk = (int)((ldq + kTile - 1) / kTile);
+  for (int t = blockIdx.x; t < ti * tk; t += gridDim.x) {
+    const int i0 = (t % ti) * kTile, k0 = (t / ti) * kTile;
+    {
+      const int kk = threadIdx.x >> 2, ii = (threadIdx.x & 3) * 16;
+      const int k = k0 + kk;
+      const uint16_t *src = M + (int64_t)k * P.ldm + i0 + ii;
+      if (vec && k < w && i0 + ii + 16 <= h) {
+        const uint4 v0 = *(const uint4 *)src, v1 = *(const uint4 *)(src + 8);
+        const uint16_t *e0 = (const uint16_t *)&v0, *e1 = (const uint16_t *)&v1;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          tile[kk][ii + j] = e0[j];
+          tile[kk][ii + 8 + j] = e1[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; j++) tile[kk][ii + j] = (k < w && i0 + ii + j < h) ? src[j] : (uint16_t)0;
+      }
+    }
+    __syncthreads();
+    {
+      const int ii = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 16;
+      if (i0 + ii < h && k0 + kq < ldq) {
+        float x[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) x[j] = bf16_to_f32(tile[kq + j][ii]);
+        *(uint4 *)(P.q8 + (int64_t)(i0 + ii) * ldq + k0 + kq) = pack16(x, s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// quantise level `a.level` (bfloat16, hp x hp, full symmetric) into q8 with its own scale
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_quant_level(const StageArgs a) {
+  __shared__ float fscr[4];
+  const ProbDev &P = problem(a);
+  const int level = a.level;
+  const float mx = max_upper(P.amax_part + (int64_t)level * P.nt * P.nt, P.nt, fscr);
+  const float s = scale_from_amax(mx);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.q_scale[2 * level] = s;
+    P.q_scale[2 * level + 1] = mx;
+  }
+  const uint16_t *src = (const uint16_t *)((const char *)P.lv + (int64_t)(level - 1) * P.lv_stride);
+  const int64_t ng = (int64_t)P.hp * P.hp / 16;
+  for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < ng; g += (int64_t)gridDim.x * kThreads) {
+    float x[16];
+    unpack8(*(const uint4 *)(src + g * 16), x);
+    unpack8(*(const uint4 *)(src + g * 16 + 8), x + 8);
+    *(uint4 *)(P.q8 + g * 16) = pack16(x, s);
+  }
+}
+
+__global__ void k_export(const ProbDev P, double *out) {
+  if (threadIdx.x == 0) {
+    out[0] = P.norm_part[0];
+    out[1] = (double)P.q_scale[1];
+    out[2] = (double)P.q_scale[0];
+  }
+}
+
+}  // namespace e4m3
+
+// Grid of a memory-bound e4m3 pass: `per_problem` workgroups for each of `nprob` problems.
+hipError_t launch_e4m3_pass(int which, const StageArgs &a, int nprob, int per_problem, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  const dim3 grid(per_problem, nprob);
+  if (which == kE4m3Prepass) hipLaunchKernelGGL(e4m3::k_prepass, grid, dim3(kThreads), 0, s, a);
+  else if (which == kE4m3QuantInput) hipLaunchKernelGGL(e4m3::k_quant_input, grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(e4m3::k_quant_level, grid, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e4m3_export(const ProbDev &P, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(e4m3::k_export, dim3(1), dim3(64), 0, s, P, out);
+  return hipGetLastError();
+}
+
+}  // namespace ifnso

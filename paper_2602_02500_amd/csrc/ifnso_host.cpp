@@ -58,12 +58,26 @@ struct ProbLayout {
   int32_t h, w, trans, hp, nt;
   size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2], off_lv;
   int64_t ldx, lv_stride;
+  // e4m3 compute
+  size_t off_q8, off_qpart, off_qamax, off_amaxp, off_qscale;
+  int64_t ldq;
+  int32_t nq, rq;
   size_t bytes;
 };
 
+// e4m3 pre-pass chunks: about kQElems elements (whole storage rows) each
+constexpr int64_t kQElems = 1 << 16;
+constexpr int kQScaleFloats = 2 * (kMaxLevels + 1);
+
+void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
+  rq = (int32_t)std::max<int64_t>(1, kQElems / cols);
+  nq = (int32_t)((rows + rq - 1) / rq);
+}
+
 // Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
 // float32 D ping-pong; classical NS adds two h x w iterates.
-ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false) {
+ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
+                          bool e4m3 = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -105,6 +119,16 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
     L.off_xbuf[1] = take((size_t)L.h * L.ldx * op_size(op));
   }
+  if (e4m3) {
+    // one e4m3 buffer: A (h x ldq) for the Gram, then each level (hp x hp) for its squaring
+    L.ldq = round_up(L.w, 16);
+    e4m3_chunks(rows, cols, L.rq, L.nq);
+    L.off_q8 = take(std::max((size_t)L.h * L.ldq, hh));
+    L.off_qpart = take((size_t)L.nq * 8);
+    L.off_qamax = take((size_t)L.nq * 4);
+    L.off_amaxp = take((size_t)levels * L.nt * L.nt * 4);
+    L.off_qscale = take(kQScaleFloats * 4);
+  }
   L.bytes = o;
   return L;
 }
@@ -138,6 +162,16 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
   d.ldx = L.ldx;
   d.lv = L.lv_stride ? ws + L.off_lv : nullptr;
   d.lv_stride = L.lv_stride;
+  if (L.ldq) {
+    d.q8 = (uint8_t *)(ws + L.off_q8);
+    d.ldq = L.ldq;
+    d.q_part = (double *)(ws + L.off_qpart);
+    d.q_amax = (float *)(ws + L.off_qamax);
+    d.amax_part = (float *)(ws + L.off_amaxp);
+    d.q_scale = (float *)(ws + L.off_qscale);
+    d.nq = L.nq;
+    d.rq = L.rq;
+  }
 }
 
 bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -220,6 +254,8 @@ struct ifnso_plan_s {
   bool fast = false;  // bfloat16 plan whose squarings use the fast kernels
   bool agg = false;   // level layout + aggregate stage (fast, Gram basis, J >= 1)
   bool learned = false;
+  bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
+  int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
   double *d_fixed = nullptr;       // learned mode: fixed coefficient slots (fallback)
@@ -284,7 +320,8 @@ static ifnso_status validate_desc(const ifnso_poly_desc *d) {
     for (size_t i = 0; i < d->mlp_params_len; i++)
       if (!std::isfinite(d->mlp_params[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "parameter %zu is not finite", i);
   }
-  if (d->compute == IFNSO_COMPUTE_FP8_E4M3) return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute is not built");
+  if (d->compute == IFNSO_COMPUTE_FP8_E4M3 && d->basis != IFNSO_BASIS_GRAM)
+    return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute is built for the Gram basis only");
   return IFNSO_OK;
 }
 
@@ -321,9 +358,21 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
     if (std::min(rows[i], cols[i]) > 65536 || std::max(rows[i], cols[i]) > (1LL << 30))
       return fail(IFNSO_ERR_UNSUPPORTED, "problem %d is larger than this build supports", i);
   }
+  // the e4m3 mode keeps bfloat16 levels, P and product operands; only the Gram and squaring
+  // GEMMs read e4m3
+  const bool e4m3 = desc->compute == IFNSO_COMPUTE_FP8_E4M3;
   const int op = desc->compute == IFNSO_COMPUTE_F32 ? kOpF32 : kOpBF16;
   if ((op == kOpF32 && in_dtype != IFNSO_F32) || (op == kOpBF16 && in_dtype != IFNSO_BF16))
-    return fail(IFNSO_ERR_UNSUPPORTED, "compute type must match the input dtype (F32 with F32, BF16 with BF16)");
+    return fail(IFNSO_ERR_UNSUPPORTED,
+                "compute type must match the input dtype (F32 with F32, BF16 or FP8_E4M3 with BF16)");
+  if (e4m3) {
+    if (!fast_enabled()) return fail(IFNSO_ERR_UNSUPPORTED, "FP8 compute needs the 256-tile kernels (IFNSO_FAST != 0)");
+    for (int i = 0; i < num_problems; i++) {
+      const int64_t h = std::min(rows[i], cols[i]), w = std::max(rows[i], cols[i]);
+      if (round_up(h, kPad) > 32512 || h * round_up(w, 16) >= (1LL << 31))
+        return fail(IFNSO_ERR_UNSUPPORTED, "problem %d is too large for the FP8 path (32-bit buffer offsets)", i);
+    }
+  }
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(IFNSO_ERR_INVALID_ARGUMENT, "device %d not present", device);
@@ -351,7 +400,8 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->fast = op == kOpBF16 && fast_enabled();
   for (int i = 0; i < num_problems; i++)
     if (round_up(std::min(rows[i], cols[i]), kPad) > 32512) p->fast = false;  // bf16 h x h below 2 GiB
-  p->agg = p->fast && p->basis == IFNSO_BASIS_GRAM && p->J >= 1;
+  p->e4m3 = e4m3;
+  p->agg = p->fast && p->basis == IFNSO_BASIS_GRAM && (p->J >= 1 || e4m3);
   p->learned = desc->coeff_mode == IFNSO_COEFF_LEARNED;
   if (p->learned && !p->agg)
     return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
@@ -359,7 +409,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(
-        layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false, p->agg));
+        layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false, p->agg, e4m3));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -476,6 +526,20 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   hipSetDevice(prev);
   if (e != hipSuccess) return cleanup(fail(IFNSO_ERR_HIP, "plan allocation: %s", hipGetErrorString(e)));
+  if (e4m3) {
+    // workgroups per problem for the memory-bound passes: enough work for each, about 8 per
+    // CU over the whole batch
+    int need[3] = {1, 1, 1};
+    for (const ProbLayout &L : p->lay) {
+      need[0] = std::max(need[0], L.nq);
+      const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64)
+                                       : ((int64_t)L.h * L.ldq / 16 + kThreads - 1) / kThreads;
+      need[1] = (int)std::max<int64_t>(need[1], units_in);
+      need[2] = (int)std::max<int64_t>(need[2], ((int64_t)L.hp * L.hp / 16 + kThreads - 1) / kThreads);
+    }
+    const int cap = std::max(1, (8 * p->cus + num_problems - 1) / num_problems);
+    for (int k = 0; k < 3; k++) p->q_grid[k] = std::max(1, std::min(need[k], cap));
+  }
   p->grid[kStageGram] = grid_for(op, kStageGram, p->n_gram, p->cus);
   p->grid[kStageSquare] = grid_for(op, kStageSquare, p->n_square, p->cus);
   p->grid[kStageProduct] = grid_for(op, kStageProduct, p->n_prod, p->cus);
@@ -531,10 +595,11 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   return a;
 }
 
-// Launch slots of one call, in order: Gram (wide, tall), each squaring level, aggregate,
+// Launch slots of one call, in order: [e4m3 plans: pre-pass and input quantisation], Gram
+// (wide, tall), each squaring level (with its quantisation in e4m3 plans), aggregate,
 // product (wide, tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
 // slot i and ev[num_slots] after the last one, so empty slots read as zero time.
-static int num_slots(const ifnso_plan_s *p) { return p->Jsq + 5; }
+static int num_slots(const ifnso_plan_s *p) { return p->Jsq + 5 + (p->e4m3 ? 1 : 0); }
 
 // Problem-level check for the fast kernels: 16-byte aligned rows whose length is a multiple of
 // 8 elements, and an input small enough for 32-bit buffer offsets.
@@ -587,10 +652,26 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   auto ntiles_prod = [&](int ts) {
     return (((L0->trans ? L0->w : L0->h) + ts - 1) / ts) * (((L0->trans ? L0->h : L0->w) + ts - 1) / ts);
   };
+  const int nprob = one ? 1 : p->num;
+  if (p->e4m3) {
+    if ((e = mark()) != hipSuccess) return e;
+    if ((e = launch_e4m3_pass(kE4m3Prepass, a, nprob, p->q_grid[0], s)) != hipSuccess) return e;
+    if ((e = launch_e4m3_pass(kE4m3QuantInput, a, nprob, p->q_grid[1], s)) != hipSuccess) return e;
+  }
   // Gram
   for (int t = 0; t < 2; t++) {
     if ((e = mark()) != hipSuccess) return e;
-    if (fast && fast_io) {
+    if (p->e4m3) {
+      // the e4m3 copy of A is K-major for both orientations; the two lists are kept apart only
+      // so that the launch slots match the other modes
+      a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
+      if (!one) {
+        a.tasks = p->d_tasks + p->offf_gram[t];
+        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1]);
+      }
+      e = launch_e4m3_gemm(kStageGram, a, fast_grid(a, cus), s);
+      a.xcd_sched = 0;
+    } else if (fast && fast_io) {
       a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
       if (!one) {
         a.tasks = p->d_tasks + p->offf_gram[t];
@@ -609,7 +690,16 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     if ((e = mark()) != hipSuccess) return e;
     a.level = lvl;
     a.last = lvl == p->Jsq;
-    if (fast) {
+    if (p->e4m3) {
+      if ((e = launch_e4m3_pass(kE4m3QuantLevel, a, nprob, p->q_grid[2], s)) != hipSuccess) return e;
+      a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
+      if (!one) {
+        a.tasks = p->d_tasks + p->offf_square;
+        set_xcd(a, p->xq_square[0], p->xq_square[1]);
+      }
+      e = launch_e4m3_gemm(kStageSquare, a, fast_grid(a, cus), s);
+      a.xcd_sched = 0;
+    } else if (fast) {
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;
@@ -760,6 +850,14 @@ extern "C" ifnso_status ifnso_plan_launch_info(ifnso_plan_t p, int32_t i, int32_
   if (!p || !stage || !flops) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
   const int n = num_slots(p);
   if (i < 0 || i >= n) return fail(IFNSO_ERR_INVALID_ARGUMENT, "launch slot %d outside 0..%d", i, n - 1);
+  if (p->e4m3) {
+    if (i == 0) {
+      *stage = kStagePrep;
+      *flops = 0.0;
+      return IFNSO_OK;
+    }
+    i--;
+  }
   if (i < 2) {
     *stage = kStageGram;
     *flops = p->fl_gram[i];
@@ -878,6 +976,85 @@ extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t 
     HIP_TRY(launch_stage(op, kTS, kStageProduct, a, grid_for(op, kStageProduct, rt * ct, cus),
                          dtype == IFNSO_BF16, s));
   }
+  return IFNSO_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// e4m3 quantisation of one input on its own
+// ---------------------------------------------------------------------------------------------
+namespace {
+struct QuantLayout {
+  int32_t rq, nq;
+  size_t off_part, off_amax, off_norm, off_scale, bytes;
+};
+
+QuantLayout quant_layout(int64_t rows, int64_t cols) {
+  QuantLayout q{};
+  e4m3_chunks(rows, cols, q.rq, q.nq);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, kAlign);
+    return at;
+  };
+  q.off_part = take((size_t)q.nq * 8);
+  q.off_amax = take((size_t)q.nq * 4);
+  q.off_norm = take(8);
+  q.off_scale = take(kQScaleFloats * 4);
+  q.bytes = o;
+  return q;
+}
+}  // namespace
+
+extern "C" size_t ifnso_quantize_e4m3_workspace_bytes(int64_t rows, int64_t cols) {
+  if (rows < 1 || cols < 1) return 0;
+  return quant_layout(rows, cols).bytes;
+}
+
+extern "C" ifnso_status ifnso_quantize_e4m3(const void *M, int64_t rows, int64_t cols, int64_t ldm, void *Q,
+                                            int64_t ldq, double *out3, void *workspace, size_t workspace_bytes,
+                                            void *stream) {
+  if (!M || !Q || !out3) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (rows < 1 || cols < 1 || ldm < cols) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad shape or leading dimension");
+  const int64_t h = std::min(rows, cols), w = std::max(rows, cols);
+  if (ldq < round_up(w, 16) || ldq % 16 != 0 || (uintptr_t)Q % 16 != 0)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "Q needs ldq >= %lld, a multiple of 16, and 16-byte alignment",
+                (long long)round_up(w, 16));
+  if (h * ldq >= (1LL << 31)) return fail(IFNSO_ERR_UNSUPPORTED, "h * ldq must stay below 2^31");
+  if (ranges_overlap(M, matrix_bytes(rows, ldm, cols, 2), Q, (size_t)h * ldq))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "Q overlaps M");
+  const QuantLayout ql = quant_layout(rows, cols);
+  if (!workspace) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < ql.bytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", workspace_bytes, ql.bytes);
+  if ((uintptr_t)workspace % kAlign) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  char *ws = (char *)workspace;
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  ProbDev &d = a.one;
+  d.M = M;
+  d.ldm = ldm;
+  d.h = (int32_t)h;
+  d.w = (int32_t)w;
+  d.trans = rows > cols;
+  d.nt = 1;
+  d.vecM = ((uintptr_t)M % 16 == 0) && (ldm * 2 % 16 == 0);
+  d.norm_part = (double *)(ws + ql.off_norm);
+  d.q8 = (uint8_t *)Q;
+  d.ldq = ldq;
+  d.q_part = (double *)(ws + ql.off_part);
+  d.q_amax = (float *)(ws + ql.off_amax);
+  d.q_scale = (float *)(ws + ql.off_scale);
+  d.nq = ql.nq;
+  d.rq = ql.rq;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const int cus = dev_cus(dev);
+  const int64_t units_in = d.trans ? ((h + 63) / 64) * ((ldq + 63) / 64) : (h * ldq / 16 + kThreads - 1) / kThreads;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_e4m3_pass(kE4m3Prepass, a, 1, std::max(1, std::min(ql.nq, 8 * cus)), s));
+  HIP_TRY(launch_e4m3_pass(kE4m3QuantInput, a, 1, (int)std::max<int64_t>(1, std::min<int64_t>(units_in, 8 * cus)), s));
+  HIP_TRY(launch_e4m3_export(a.one, out3, s));
   return IFNSO_OK;
 }
 

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
         sout = sc.sout;
         if (a.basis == kGram) {
           c0 = P.coef[0];
-          ps = (a.J == 0) ? P.coef[1] * sc.sg : 1.0;
+          ps = (a.J == 0 && !a.agg) ? P.coef[1] * sc.sg : 1.0;  // the aggregate stage folds c_1 S_1 into P
         } else {
           c0 = 0.0;
           for (int k = 0; k < kSlots; k++) c0 += P.coef[k];

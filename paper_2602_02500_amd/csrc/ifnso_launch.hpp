@@ -7,7 +7,7 @@
 
 namespace ifnso {
 
-enum Stage : int { kStageGram = 0, kStageSquare = 1, kStageProduct = 2, kStageAggregate = 3 };
+enum Stage : int { kStageGram = 0, kStageSquare = 1, kStageProduct = 2, kStageAggregate = 3, kStagePrep = 4 };
 
 struct OrthEntry {
   const void *ptr;
@@ -30,6 +30,14 @@ hipError_t fast_occupancy(int stage, int *blocks_per_cu);
 // P = sum_l c_l S_l B_l over the stored levels (level layout); tasks are (problem, chunk)
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s);
 constexpr int kAggChunk = 1 << 17;  // elements per aggregate task
+
+// e4m3 compute (ifnso_fp8.hip): memory-bound passes, one grid row per problem
+enum E4m3Pass : int { kE4m3Prepass = 0, kE4m3QuantInput = 1, kE4m3QuantLevel = 2 };
+hipError_t launch_e4m3_pass(int which, const StageArgs &a, int nprob, int per_problem, hipStream_t s);
+// device out[3] = {||A||_F^2, max |A|, scale} of a single-problem pass
+hipError_t launch_e4m3_export(const ProbDev &P, double *out, hipStream_t s);
+// e4m3 Gram (level 1 from q8) and squaring (level+1 from the quantised level) on 256 tiles
+hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t s);
 constexpr int kFastTS = 256;
 
 // learned coefficients (ifnso_mlp.hip)

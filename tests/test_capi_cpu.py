@@ -66,6 +66,31 @@ def test_unsupported_combinations(L):
     assert _plan(L, [0, 1], [1, 1], mode=1)[0] == 1  # learned mode without parameters
 
 
+def test_fp8_requirements(L):
+    fp8 = ifn.COMPUTE_FP8
+    assert _plan(L, [0, 1, 2], [0.5, 0.25, 0.25], basis=1, compute=fp8)[0] == 2   # complement basis
+    assert _plan(L, [0, 1, 2], [0.5, 0.25, 0.25], compute=fp8, ind=ifn.F32)[0] == 2  # float32 input
+    # h * round_up(w, 16) must stay below 2^31 (checked before the device is touched)
+    assert _plan(L, [0, 1, 2], [0.5, 0.25, 0.25], compute=fp8, rows=(32000,), cols=(1 << 17,))[0] == 2
+
+
+def test_quantize_e4m3_argument_checks(L):
+    need = L.ifnso_quantize_e4m3_workspace_bytes(64, 100)
+    assert need > 0 and L.ifnso_quantize_e4m3_workspace_bytes(0, 100) == 0
+    # M at 4096 (64 x 100 bf16), Q at 1 << 20, out3 at 1 << 24, workspace at 1 << 25
+    q = lambda **k: L.ifnso_quantize_e4m3(k.get("M", 4096), 64, 100, k.get("ldm", 100), k.get("Q", 1 << 20),
+                                          k.get("ldq", 112), k.get("out", 1 << 24), 1 << 25, k.get("nb", need), None)
+    assert q(M=None) == 1
+    assert q(out=None) == 1
+    assert q(ldm=99) == 1            # ldm < cols
+    assert q(ldq=100) == 1           # below round_up(100, 16)
+    assert q(ldq=120) == 1           # not a multiple of 16
+    assert q(Q=(1 << 20) + 8) == 1   # Q not 16-byte aligned
+    assert q(Q=4096 + 64) == 1       # Q overlaps M
+    assert q(nb=need - 1) == 3
+    assert L.ifnso_quantize_e4m3(4096, 64, 100, 100, 1 << 20, 1 << 26, 1 << 24, 1 << 25, need, None) == 2
+
+
 def test_learned_mode_requirements(L):
     params = (ctypes.c_float * ifn.MLP_NUM_PARAMS)(*([0.0] * ifn.MLP_NUM_PARAMS))
 
@@ -82,6 +107,7 @@ def test_learned_mode_requirements(L):
     assert plan([0, 1, 2, 4, 8, 16], basis=1) == 2        # complement basis
     assert plan([0, 1, 2, 4, 8, 16], norm=1) == 2
     assert plan([0, 1, 2, 4, 8, 16], compute=0) == 2      # float32 compute
+    assert plan([0, 1, 2, 4, 8, 16], compute=2) == 2      # e4m3 compute
     assert plan([0, 1, 2, 4, 8, 16], n=100) == 1          # wrong parameter count
     params[7] = float("inf")
     assert plan([0, 1, 2, 4, 8, 16]) == 1                 # non-finite parameter

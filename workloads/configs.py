@@ -22,7 +22,7 @@ from .gen import uniform_np
 
 __all__ = [
     "MUON_ABC", "CUBIC_ABC", "D1_EXPONENTS", "D2_EXPONENTS", "d1_coeffs", "LAYER_SHAPES",
-    "d3_shapes", "d3_seed", "load_coeffs", "D4_SHAPE", "D4_BATCH", "d4_sigma", "d2_sigma_np",
+    "d3_shapes", "d3_seed", "load_coeffs", "D4_SHAPE", "D4_BATCH", "d4_seed", "d4_sigma", "d2_sigma_np",
     "PAPER_L",
 ]
 
@@ -62,6 +62,11 @@ def d3_seed(layer: int, index: int) -> int:
 def d2_sigma_np(r: int, seed: int) -> np.ndarray:
     """sigma_i = 10^U(-3, 0), stream 3 of ``seed``."""
     return 10.0 ** (-3.0 + 3.0 * uniform_np(seed, 3, r))
+
+
+def d4_seed(index: int) -> int:
+    """Generator seed of matrix `index` of the e4m3 workload's batch (base seed 3)."""
+    return 3000 + index
 
 
 def d4_sigma(r: int) -> np.ndarray:
