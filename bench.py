@@ -147,7 +147,7 @@ def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
     kern = {}
     for i, nm in enumerate(names):
         t, n_l, flop = kern.get(nm, (0.0, 0, 0.0))
-        if info[i][1] > 0 or (nm == "aggregate" and per[i] > 0.01):
+        if info[i][1] > 0 or (info[i][0] in (3, 4) and per[i] > 0.001):  # memory-bound slots
             kern[nm] = (t + per[i], n_l + 1, flop + info[i][1])
     return {"kern": kern, "elapsed": elapsed, "graph_ms": graph_ms, "slot_ms": per}
 
@@ -298,11 +298,10 @@ def main():
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
     nl = plan.num_launches
-    J = nl - 5
+    J = nl - 6
     fl = stage_flops(shapes, J)
-    info = [plan.launch_info(i) for i in range(nl)]
     # kernel of each launch slot (squaring levels share one kernel)
-    names = ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
+    names = ["transpose"] + ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
 
     t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
     kern, elapsed, graph_ms = t["kern"], t["elapsed"], t["graph_ms"]

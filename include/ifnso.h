@@ -131,19 +131,19 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
                                          void *const *Y, const int64_t *ldy, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
-/* Launch slots of one call of this plan, in order: FP8_E4M3 plans only, the pre-pass
- * (||A||_F and amax) with the e4m3 quantisation of A; Gram for the problems with
- * rows <= cols, Gram for the transposed (rows > cols) problems, one squaring per level (in
- * FP8_E4M3 plans with the quantisation of the power it squares), the aggregation of the
- * weighted powers, then the product for the two groups in the same order: J + 5 slots
- * (J + 6 for FP8_E4M3) where 2^J is the largest exponent. A slot with no work in a call
- * launches nothing (the aggregation runs only when the levels are kept: bfloat16 Gram-basis
- * plans with J >= 1, and every FP8_E4M3 plan). Returns the count, or a negative status for
- * NULL. */
+/* Launch slots of one call of this plan, in order: preparation (transposed copies of the inputs
+ * for the bf16/e4m3 256-tile kernels; in FP8_E4M3 plans also the pre-pass (||A||_F and amax)
+ * with the e4m3 quantisation of A), Gram for the problems with rows <= cols, Gram for the
+ * transposed (rows > cols) problems, one squaring per level (in FP8_E4M3 plans with the
+ * quantisation of the power it squares), the aggregation of the weighted powers, then the
+ * product for the two groups in the same order: J + 6 slots where 2^J is the largest exponent.
+ * A slot with no work in a call launches nothing (the aggregation runs only when the levels are
+ * kept: bfloat16 Gram-basis plans with J >= 1, and every FP8_E4M3 plan). Returns the count, or
+ * a negative status for NULL. */
 int32_t ifnso_plan_num_launches(ifnso_plan_t plan);
 
-/* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation, 4 FP8_E4M3 pre-pass
- * and input quantisation, with 0 flops) and its algorithmic
+/* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation, 4 preparation, with
+ * 0 flops) and its algorithmic
  * flop count: h^2 w per problem for the Gram (symmetric), h^3 per problem for a squaring
  * (symmetric), 2 h^2 w per problem for the product, 0 for the (memory-bound) aggregation.
  * Errors: INVALID_ARGUMENT. */

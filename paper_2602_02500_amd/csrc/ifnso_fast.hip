@@ -1,19 +1,21 @@
-// Fast bfloat16 stage kernels for gfx950: 256 x 256 output tiles, 64-deep K steps.
+// Fast bfloat16 (and e4m3) stage kernels for gfx950: 256 x 256 output tiles.
 //
 // Operands are read through buffer resource descriptors: an out-of-range chunk gets an
 // offset past the descriptor's record count and reads as zero, so edge tiles need no
 // branches (the host routes a problem here only when its rows are 16-byte aligned and its
 // column count is a multiple of 8, so every 16-byte chunk is wholly in or out of range).
-// K-contiguous operands go straight from HBM into LDS (buffer_load ... lds, 16 bytes per
-// lane); the XOR swizzle of the LDS rows is applied on the global side, since a wave's
-// LDS-DMA writes land contiguously. Operands whose M/N index is contiguous are loaded
-// into registers, transposed in 8 x 8 blocks, and written to LDS. Two LDS stages: the loads
-// of step k+1 are in flight while step k runs its 64 MFMAs per wave
-// (v_mfma_f32_32x32x16_bf16; each wave owns a 128 x 128 block, 256 AGPR accumulators).
+// Every GEMM operand is K-contiguous: tall inputs (for the Gram) and wide inputs (for the
+// product) are first copied transposed by a memory-bound pass. Operands go straight from
+// HBM into LDS (buffer_load ... lds, 16 bytes per lane); the XOR swizzle of the LDS rows is
+// applied on the global side, since a wave's LDS-DMA writes land contiguously. Two LDS
+// stages of 64 (bfloat16) or 128 (e4m3) K per row; each of the 4 waves owns a 128 x 128 block
+// of the tile (v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x64_f8f6f4, 256 AGPR accumulators).
 // Epilogues stage the float32 tile through LDS (half a tile at a time) so that stores of
-// the tile, of its mirror and of the float32 running sum are 16-byte vector accesses.
+// the tile and of its mirror are 16-byte vector accesses.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "ifnso_common.hpp"
 #include "ifnso_launch.hpp"
@@ -78,60 +80,6 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(
 
 __device__ __forceinline__ int swz(int row) { return (row ^ (row >> 3)) & 7; }
 
-// ---------------------------------------------------------------------------------------------
-// operand loaders
-// ---------------------------------------------------------------------------------------------
-// K-major operand of ROWS rows straight into LDS: wave-instruction g covers rows 8g..8g+7.
-template <int ROWS, int ES = 2>
-__device__ __forceinline__ void issue_kmaj(uint32_t lt, const i32x4 &r, uint32_t ld_bytes, int m0, int mlim, int k0,
-                                           int klim) {
-  const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i = 0; i < ROWS / 32; i++) {
-    const int g = i * 4 + wave;
-    const int row = g * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ swz(row);
-    const int m = m0 + row, k = k0 + c * (16 / ES);
-    const uint32_t off = (m < mlim && k < klim) ? (uint32_t)m * ld_bytes + (uint32_t)k * (uint32_t)ES : OOB;
-    dma16(r, off, lt + g * 1024);
-  }
-}
-
-// MN-major operand (element (m, k) at k*ld + m): one 8(k) x 8(m) block per thread.
-template <int ROWS>
-__device__ __forceinline__ void load_mnmaj(uint4 (&v)[8], __amdgpu_buffer_rsrc_t r, uint32_t ld_bytes, int m0,
-                                           int mlim, int k0, int klim) {
-  constexpr int MB = ROWS / 8, NB = MB * 8;
-  const int blk = threadIdx.x;
-  const int mb = blk % MB, kb = blk / MB;
-  const int m = m0 + mb * 8;
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const int k = k0 + kb * 8 + i;
-    const uint32_t off = (blk < NB && m < mlim && k < klim) ? (uint32_t)k * ld_bytes + (uint32_t)m * 2u : OOB;
-    const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-    v[i] = make_uint4(x[0], x[1], x[2], x[3]);
-  }
-}
-
-template <int ROWS>
-__device__ __forceinline__ void store_mnmaj(const uint4 (&v)[8], char *lt) {
-  constexpr int MB = ROWS / 8, NB = MB * 8;
-  const int blk = threadIdx.x;
-  if (blk >= NB) return;
-  const int mb = blk % MB, kb = blk / MB;
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    uint32_t o[4];
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const uint32_t a = w32(v[2 * e], j >> 1), c = w32(v[2 * e + 1], j >> 1);
-      o[e] = (j & 1) ? ((a >> 16) | (c & 0xffff0000u)) : ((a & 0xffffu) | (c << 16));
-    }
-    *(uint4 *)(lt + lds_off(mb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
-  }
-}
-
 // float64 sum of squares of the A tile held in LDS (diagonal Gram tiles with K-major A).
 __device__ __forceinline__ double lds_sumsq(const char *At) {
   double s = 0.0;
@@ -139,21 +87,6 @@ __device__ __forceinline__ double lds_sumsq(const char *At) {
   for (int i = 0; i < BM * 8 / kThreads; i++) {
     const uint4 q = *(const uint4 *)(At + (threadIdx.x + kThreads * i) * 16);
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const double lo = (double)__uint_as_float(w[e] << 16), hi = (double)__uint_as_float(w[e] & 0xffff0000u);
-      s = fma(lo, lo, s);
-      s = fma(hi, hi, s);
-    }
-  }
-  return s;
-}
-
-__device__ __forceinline__ double regs_sumsq(const uint4 (&v)[8]) {
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const double lo = (double)__uint_as_float(w[e] << 16), hi = (double)__uint_as_float(w[e] & 0xffff0000u);
@@ -192,13 +125,62 @@ __device__ __forceinline__ Operand make_operand(const void *p, uint32_t bytes, u
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// F8: both operands K-major OCP e4m3 (1 byte, 128 per LDS row and stage), MFMA 32x32x64.
-template <bool AMN, bool BMN, bool F8 = false>
-__device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
-                                           const Operand &B, int bn0, int K, bool want_norm) {
-  static_assert(!F8 || (!AMN && !BMN), "e4m3 operands are K-major");
+// Byte offsets of one thread's rows of a K-major operand tile (ROWS / 32 rows; wave-instruction g
+// covers rows 8g..8g+7, lane chunk c = (lane & 7) ^ swz(row)), computed once per tile: the
+// offset of chunk c at k = 0, or OOB for rows outside the operand. A K step adds k0 * ES.
+template <int ROWS>
+struct KRows {
+  uint32_t off[ROWS / 32];
+};
+
+template <int ROWS>
+__device__ __forceinline__ void krows(KRows<ROWS> &R, uint32_t ld_bytes, int m0, int mlim) {
+  const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < ROWS / 32; i++) {
+    const int row = (i * 4 + wave) * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ swz(row);
+    const int m = m0 + row;
+    R.off[i] = m < mlim ? (uint32_t)m * ld_bytes + (uint32_t)c * 16u : OOB;
+  }
+}
+
+// Loads rows [I0, I1) of the thread's rows of stage k0 into the LDS tile at lt. `full`: the
+// whole stage lies below K (otherwise chunks at or beyond K read as zero).
+template <int ROWS, int ES, int I0, int I1, bool FULL>
+__device__ __forceinline__ void issue_krows_(const KRows<ROWS> &R, uint32_t lt, const i32x4 &r, int k0, int K,
+                                             int wave) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = I0; i < I1; i++) {
+    const int g = i * 4 + wave;
+    uint32_t off = R.off[i] + (uint32_t)(k0 * ES);
+    if constexpr (!FULL) {
+      const int row = g * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ swz(row);
+      if (k0 + c * (16 / ES) >= K) off = OOB;
+    }
+    dma16(r, off, lt + g * 1024);
+  }
+}
+
+template <int ROWS, int ES, int I0, int I1>
+__device__ __forceinline__ void issue_krows(const KRows<ROWS> &R, uint32_t lt, const i32x4 &r, int k0, int K,
+                                            bool full, int wave) {
+  if (full) issue_krows_<ROWS, ES, I0, I1, true>(R, lt, r, k0, K, wave);
+  else issue_krows_<ROWS, ES, I0, I1, false>(R, lt, r, k0, K, wave);
+}
+
+// Both operands K-major: one barrier per K step. The loads of step k+1 go into the other LDS
+// stage while step k's MFMAs run (a quarter of them (bf16) or half (e4m3) before each K slice);
+// that stage was last read in step k-1, which every wave finished before this step's barrier.
+template <bool F8>
+__device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
+                                              const Operand &B, int bn0, int K, bool want_norm) {
   constexpr int ES = F8 ? 1 : 2;
-  constexpr int KST = 128 / ES;  // elements per stage
+  constexpr int KST = 128 / ES;           // elements per stage
+  constexpr int NS = F8 ? 2 : BK / 16;    // MFMA K slices per stage
+  constexpr int PER = (BM / 32) / NS;     // rows of each operand issued per slice
   const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lg = lane >> 5;
@@ -209,52 +191,41 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
   const int nk = (K + KST - 1) / KST;
-  double nrm = 0.0;
-  uint4 va[8], vb[8];
-  // loads issued per stage by one thread (K-major: ROWS/32 per operand)
-  constexpr int NDIRECT = (AMN ? 0 : BM / 32) + (BMN ? 0 : BN / 32);
-  const uint32_t lbase = uni(lds_addr(smem));
-  auto issue = [&](int kt, int buf) {
-    const uint32_t As = lbase + buf * STAGE_BYTES, Bs = As + BM * 128;
-    const int k0 = kt * KST;
-    if constexpr (!AMN) issue_kmaj<BM, ES>(As, A.w, A.ld_bytes, am0, A.lim, k0, K);
-    if constexpr (!BMN) issue_kmaj<BN, ES>(Bs, B.w, B.ld_bytes, bn0, B.lim, k0, K);
-    if constexpr (AMN) load_mnmaj<BM>(va, A.r, A.ld_bytes, am0, A.lim, k0, K);
-    if constexpr (BMN) load_mnmaj<BN>(vb, B.r, B.ld_bytes, bn0, B.lim, k0, K);
-  };
-  auto commit_regs = [&](int buf) {
-    char *As = smem + buf * STAGE_BYTES, *Bs = As + BM * 128;
-    if constexpr (AMN) {
-      if (want_norm) nrm += regs_sumsq(va);
-      store_mnmaj<BM>(va, As);
-    }
-    if constexpr (BMN) store_mnmaj<BN>(vb, Bs);
-  };
   if (nk <= 0) return 0.0;
-  issue(0, 0);
-  commit_regs(0);
+  double nrm = 0.0;
+  KRows<BM> RA;
+  KRows<BN> RB;
+  krows<BM>(RA, A.ld_bytes, am0, A.lim);
+  krows<BN>(RB, B.ld_bytes, bn0, B.lim);
+  const uint32_t lbase = uni(lds_addr(smem));
+  {
+    const bool full = KST <= K;
+    issue_krows<BM, ES, 0, BM / 32>(RA, lbase, A.w, 0, K, full, wave);
+    issue_krows<BN, ES, 0, BN / 32>(RB, lbase + BM * 128, B.w, 0, K, full, wave);
+  }
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) issue(kt + 1, cur ^ 1);
-    // this step's direct loads were issued one iteration earlier; the next step's are the
-    // newest NDIRECT (+ register loads) in flight
-    if constexpr (AMN || BMN) {
-      if (more) wait_vmcnt<NDIRECT + (AMN ? 8 : 0) + (BMN ? 8 : 0)>();
-      else wait_vmcnt<0>();
-    } else {
-      if (more) wait_vmcnt<NDIRECT>();
-      else wait_vmcnt<0>();
-    }
+    wait_vmcnt<0>();
     __syncthreads();
     const char *As = smem + cur * STAGE_BYTES, *Bs = As + BM * 128;
-    if constexpr (!AMN && !F8) {
+    if constexpr (!F8) {
       if (want_norm) nrm += lds_sumsq(As);
     }
+    const bool more = kt + 1 < nk;
+    const int k1 = (kt + 1) * KST;
+    const bool full = k1 + KST <= K;
+    const uint32_t An = lbase + (cur ^ 1) * STAGE_BYTES, Bn = An + BM * 128;
+    auto issue_slice = [&](auto sl) {
+      constexpr int s = decltype(sl)::value;
+      if (more) {
+        issue_krows<BM, ES, s * PER, (s + 1) * PER>(RA, An, A.w, k1, K, full, wave);
+        issue_krows<BN, ES, s * PER, (s + 1) * PER>(RB, Bn, B.w, k1, K, full, wave);
+      }
+    };
     if constexpr (F8) {
-      // two 64-deep slices per stage; a fragment is 32 bytes (two LDS chunks) per lane
-#pragma unroll
-      for (int kk = 0; kk < 2; kk++) {
+      auto slice = [&](auto sl) {
+        constexpr int kk = decltype(sl)::value;
+        issue_slice(sl);
         i32x8 fa[FM], fb[FN];
 #pragma unroll
         for (int i = 0; i < FM; i++) {
@@ -275,10 +246,11 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
 #pragma unroll
           for (int j = 0; j < FN; j++)
             acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 0, 0, 0);
-      }
+      };
+      slice(std::integral_constant<int, 0>{});
+      slice(std::integral_constant<int, 1>{});
     } else {
       // fragments of K slice kk+1 are read from LDS while slice kk's 16 MFMAs run
-      // (one LDS read per two MFMAs)
       bf16x8 fa[2][FM], fb[2][FN];
       auto rd = [&](int kk, int sl) {
 #pragma unroll
@@ -286,29 +258,133 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
 #pragma unroll
         for (int j = 0; j < FN; j++) fb[sl][j] = *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
       };
-      rd(0, 0);
-#pragma unroll
-      for (int kk = 0; kk < BK / 16; kk++) {
-        const int sl = kk & 1;
-        if (kk + 1 < BK / 16) rd(kk + 1, sl ^ 1);
+      auto slice = [&](auto slc) {
+        constexpr int kk = decltype(slc)::value;
+        constexpr int sl = kk & 1;
+        issue_slice(slc);
+        if constexpr (kk + 1 < NS) rd(kk + 1, sl ^ 1);
 #pragma unroll
         for (int i = 0; i < FM; i++)
 #pragma unroll
           for (int j = 0; j < FN; j++)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][i], fb[sl][j], acc[i][j], 0, 0, 0);
-        if (kk + 1 < BK / 16) {
+        if constexpr (kk + 1 < NS) {
 #pragma unroll
           for (int q = 0; q < FM + FN; q++) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
             __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
           }
         }
-      }
+      };
+      rd(0, 0);
+      slice(std::integral_constant<int, 0>{});
+      slice(std::integral_constant<int, 1>{});
+      slice(std::integral_constant<int, 2>{});
+      slice(std::integral_constant<int, 3>{});
     }
-    if (more) commit_regs(cur ^ 1);
-    __syncthreads();
   }
+  __syncthreads();  // the epilogue reuses the LDS stages
   return nrm;
+}
+
+// bfloat16, both operands K-major. Per K step (4 slices of 16): the fragments of slice s+1 are
+// read from LDS ahead of slice s's 16 MFMAs. After slice 2 each wave holds slice 3's fragments,
+// waits for its share of the next stage's loads and meets the others at the step's one barrier;
+// past it, stage k's buffer is free and stage k+1 is complete, so the loads of stage k+2 go into
+// stage k's buffer and the fragments of stage k+1's first slice are read while slice 3's MFMAs
+// run (the LDS latency at a step boundary is hidden behind them).
+__device__ __forceinline__ double mainloop_bf16(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
+                                                const Operand &B, int bn0, int K, bool want_norm) {
+  constexpr int ES = 2, KST = 64;
+  const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lg = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+  const int nk = (K + KST - 1) / KST;
+  if (nk <= 0) return 0.0;
+  double nrm = 0.0;
+  KRows<BM> RA;
+  KRows<BN> RB;
+  krows<BM>(RA, A.ld_bytes, am0, A.lim);
+  krows<BN>(RB, B.ld_bytes, bn0, B.lim);
+  const uint32_t lbase = uni(lds_addr(smem));
+  auto issue_stage = [&](int st) {
+    const uint32_t As = lbase + (st & 1) * STAGE_BYTES;
+    const int k0 = st * KST;
+    const bool full = k0 + KST <= K;
+    issue_krows<BM, ES, 0, BM / 32>(RA, As, A.w, k0, K, full, wave);
+    issue_krows<BN, ES, 0, BN / 32>(RB, As + BM * 128, B.w, k0, K, full, wave);
+  };
+  bf16x8 fa[2][FM], fb[2][FN];
+  auto rd = [&](const char *As, int kk, int sl) {
+    const char *Bs = As + BM * 128;
+#pragma unroll
+    for (int i = 0; i < FM; i++) fa[sl][i] = *(const bf16x8 *)(As + lds_off(wm * WM + i * 32 + lr, 2 * kk + lg));
+#pragma unroll
+    for (int j = 0; j < FN; j++) fb[sl][j] = *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
+  };
+  auto mfma = [&](int sl) {
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int j = 0; j < FN; j++)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][i], fb[sl][j], acc[i][j], 0, 0, 0);
+  };
+  // LDS reads of the next slice ahead of this slice's MFMAs
+  auto order = [&]() {
+    __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+  };
+  issue_stage(0);
+  if (nk > 1) {
+    issue_stage(1);
+    wait_vmcnt<BM / 32 + BN / 32>();
+  } else {
+    wait_vmcnt<0>();
+  }
+  __syncthreads();
+  if (want_norm) nrm += lds_sumsq(smem);
+  rd(smem, 0, 0);
+  for (int kt = 0; kt < nk; kt++) {
+    const char *As = smem + (kt & 1) * STAGE_BYTES;
+    rd(As, 1, 1);
+    mfma(0);
+    order();
+    rd(As, 2, 0);
+    mfma(1);
+    order();
+    rd(As, 3, 1);
+    mfma(0);
+    order();
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const char *Nx = smem + ((kt + 1) & 1) * STAGE_BYTES;
+      if (want_norm) nrm += lds_sumsq(Nx);
+      rd(Nx, 0, 0);
+      if (kt + 2 < nk) issue_stage(kt + 2);
+    }
+    mfma(1);
+  }
+  __syncthreads();  // the epilogue reuses the LDS stages
+  return nrm;
+}
+
+// acc = Aop[am0.., :K] * Bop[bn0.., :K]^T with both operands K-contiguous; F8: OCP e4m3
+// operands (1 byte, 128 per LDS row and stage), MFMA 32x32x64.
+// OV: the bfloat16 schedule that overlaps the step boundary (mainloop_bf16); it needs more
+// registers, so kernels whose epilogues keep more state use the simpler schedule.
+template <bool AMN, bool BMN, bool F8 = false, bool OV = false>
+__device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
+                                           const Operand &B, int bn0, int K, bool want_norm) {
+  static_assert(!AMN && !BMN, "operands are K-contiguous (tall inputs and wide products use M^T copies)");
+  if constexpr (OV && !F8) return mainloop_bf16(acc, smem, A, am0, B, bn0, K, want_norm);
+  else return mainloop_kk<F8>(acc, smem, A, am0, B, bn0, K, want_norm);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -524,7 +600,6 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
 // ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
-template <bool TRANS>
 __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -537,13 +612,14 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
     const ProbDev &P = prob(a, task);
     const int m0 = task.tm * BM, n0 = task.tn * BN;
     const bool diag = task.tm == task.tn;
-    const uint32_t mbytes = (uint32_t)(((int64_t)(P.trans ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(P.trans ? P.h : P.w) * 2);
-    const Operand op = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.h);
+    // A = M (wide) or the transposed copy M^T (tall): rows of A are K-contiguous either way
+    // (the copy's rows are padded with zeros to ldxt, so they are read whole)
+    const int64_t lda = P.trans ? P.ldxt : P.ldm;
+    const uint32_t abytes = (uint32_t)(P.trans ? (int64_t)P.h * lda * 2 : ((int64_t)P.h - 1) * lda * 2 + (int64_t)P.w * 2);
+    const Operand op = make_operand(P.trans ? P.xt : P.M, abytes, (uint32_t)(lda * 2), P.h);
     const int K = uni(P.w);
     f32x16 acc[FM][FN];
-    double nrm;
-    const double nrm_t = mainloop<TRANS, TRANS>(acc, smem, op, m0, op, n0, K, diag);
-    nrm = nrm_t;
+    double nrm = mainloop<false, false>(acc, smem, op, m0, op, n0, K, diag);
     uint16_t *dst = (uint16_t *)P.opnd[0];
     const int64_t hp = P.hp;
     const bool keep_f32 = (a.J >= 1 && !a.agg) || a.learned;
@@ -620,7 +696,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
                            : (const void *)P.opnd[(level - 1) & 1];
     const Operand op = make_operand(srcp, bytes, (uint32_t)(hp * 2), P.hp);
     f32x16 acc[FM][FN];
-    mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
+    mainloop<false, false, false, AGG>(acc, smem, op, m0, op, n0, uni(P.h), false);
     uint16_t *dst = AGG ? (uint16_t *)((char *)P.lv + (int64_t)level * P.lv_stride) : (uint16_t *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
@@ -789,8 +865,11 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
     }
     const int64_t hp = P.hp;
     const int m0 = task.tm * BM, n0 = task.tn * BN;
-    const uint32_t mbytes = (uint32_t)(((int64_t)(P.trans ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(P.trans ? P.h : P.w) * 2);
-    const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
+    // tall: rows of M (w x h, K = h contiguous); wide: rows of M^T (w x h, the transposed copy)
+    const void *rp = TRANS ? P.M : P.xt;
+    const int64_t ldr = TRANS ? P.ldm : P.ldxt;
+    const uint32_t rbytes = (uint32_t)(TRANS ? ((int64_t)P.w - 1) * ldr * 2 + (int64_t)P.h * 2 : (int64_t)P.w * ldr * 2);
+    const Operand Mo = make_operand(rp, rbytes, (uint32_t)(ldr * 2), P.w);
     const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
     const int Kp = uni(P.h);
     f32x16 acc[FM][FN];
@@ -806,8 +885,8 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
       // Y_out[n][i] = sum_k M[n][k] P[i][k]
       mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
     } else {
-      // Y[i][n] = sum_k P[i][k] M[k][n]
-      mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
+      // Y[i][n] = sum_k P[i][k] M^T[n][k]
+      mainloop<false, false>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
     const uint16_t *M = (const uint16_t *)P.M;
     for (int half = 0; half < 2; half++) {
@@ -849,6 +928,44 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
         }
       }
       __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// transposed copy X = M^T (cols x rows, leading dimension ldxt; columns rows..ldxt-1 are zero):
+// 128 x 128 tiles, each thread moves one 8 x 8 block (eight 16-byte loads, an in-register
+// transpose, eight 16-byte stores). Problems come from blockIdx.y.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void kf_transpose(const StageArgs a, int wide_only) {
+  const ProbDev &P = a.probs ? a.probs[blockIdx.y] : a.one;
+  if (wide_only && P.trans) return;
+  const int rows = P.trans ? P.w : P.h, cols = P.trans ? P.h : P.w;
+  const int tr = (rows + 127) / 128, tc = (cols + 127) / 128;
+  const uint16_t *M = (const uint16_t *)P.M;
+  uint16_t *X = (uint16_t *)P.xt;
+  // wave w covers the 64 x 64 quarter (w & 1, w >> 1) of the tile; lane (rb, cb) = (lane & 7,
+  // lane >> 3), so that each load reads 8 rows of 128 contiguous bytes and each store writes 8
+  // rows of the copy, 128 contiguous bytes each
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = (wave & 1) * 8 + (lane & 7), cb = (wave >> 1) * 8 + (lane >> 3);
+  for (int t = blockIdx.x; t < tr * tc; t += gridDim.x) {
+    const int r0 = (t / tc) * 128 + rb * 8, c0 = (t % tc) * 128 + cb * 8;
+    if (c0 >= cols) continue;  // cols is a multiple of 8: a block is wholly in or out
+    uint4 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+      v[i] = r0 + i < rows ? *(const uint4 *)(M + (int64_t)(r0 + i) * P.ldm + c0) : make_uint4(0, 0, 0, 0);
+    if (r0 >= P.ldxt) continue;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      uint32_t o[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const uint32_t x = w32(v[2 * e], j >> 1), y = w32(v[2 * e + 1], j >> 1);
+        o[e] = (j & 1) ? ((x >> 16) | (y & 0xffff0000u)) : ((x & 0xffffu) | (y << 16));
+      }
+      *(uint4 *)(X + (int64_t)(c0 + j) * P.ldxt + r0) = make_uint4(o[0], o[1], o[2], o[3]);
     }
   }
 }
@@ -920,6 +1037,12 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
 
 }  // namespace fast
 
+hipError_t launch_transpose(const StageArgs &a, int nprob, int per_problem, int wide_only, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fast::kf_transpose, dim3(per_problem, nprob), dim3(kThreads), 0, s, a, wide_only);
+  return hipGetLastError();
+}
+
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   hipLaunchKernelGGL(fast::kf_aggregate, dim3(grid), dim3(kThreads), 0, s, a);
@@ -929,8 +1052,7 @@ hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   if (stage == kStageGram) {
-    if (trans) hipLaunchKernelGGL(fast::kf_gram<true>, dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL(fast::kf_gram<false>, dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(kThreads), 0, s, a);
   } else if (stage == kStageSquare) {
     if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(kThreads), 0, s, a);
@@ -949,7 +1071,7 @@ hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t
 }
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
-  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false>
+  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram
                  : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
 }

@@ -311,7 +311,8 @@ def test_launch_events_and_info(torch_dev):
     exps, c = configs.load_coeffs("gform_v1")
     plan = ifn.Plan(exps, c, shapes, compute="bf16")
     n = plan.num_launches
-    assert n == 4 + 5
+    assert n == 4 + 6
+    assert plan.launch_info(0) == (4, 0.0)  # preparation: transposed copies
     fl = [plan.launch_info(i) for i in range(n)]
     total = sum(f for _, f in fl)
     want = sum(min(s) ** 2 * max(s) * 3 + 4 * min(s) ** 3 for s in shapes)
