@@ -55,6 +55,23 @@ def make_d3(torch, dev, layers=32):
     return Ms
 
 
+def schedule(args, torch, plan, Ms, Ys, ws, compute, exps, log):
+    """Applies cached tuned schedules for this plan, or tunes them (--tune). Returns a record."""
+    from paper_2602_02500_amd import tune
+    key = tune.plan_key(torch.cuda.get_device_name(0), [tuple(m.shape) for m in Ms], compute, exps)
+    if args.tune:
+        res = tune.tune(plan, Ms, Ys, ws, log=log)
+        os.makedirs(os.path.dirname(args.tune_out), exist_ok=True)
+        tune.save_cache(args.tune_out, key, res, note=f"{len(Ms)} matrices, compute {compute}")
+        return {"source": "tuned now", "key": key, "stages": {k: v["config"] for k, v in res.items()},
+                "ms": {k: [v["default_ms"], v["ms"]] for k, v in res.items()}}
+    entry = tune.load_cache(args.schedules).get(key)
+    if entry:
+        tune.apply(plan, entry)
+        return {"source": os.path.relpath(args.schedules, ROOT), "key": key, "stages": entry["stages"]}
+    return {"source": "defaults", "key": key}
+
+
 def make_e4m3_set(torch, dev, batch):
     from workloads import configs, gen
     r, c = configs.D4_SHAPE
@@ -167,6 +184,7 @@ def run_e4m3(args, torch, dev, hip, log):
     plan = ifn.Plan(exps, coeffs, shapes, compute="fp8")
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+    sched = schedule(args, torch, plan, Ms, Ys, ws, "fp8", exps, log)
     nl = plan.num_launches
     J = nl - 6
     fl = stage_flops(shapes, J)
@@ -186,7 +204,7 @@ def run_e4m3(args, torch, dev, hip, log):
     t_min_ms = ((fl["gram"] + J * fl["square"]) / (PEAK_FP8_TFLOPS * 1e12) + fl["product"] / (PEAK_BF16_TFLOPS * 1e12)) * 1e3
     hw = sum(r * c for r, c in shapes)
     prep_bytes = 5.0 * hw  # pre-pass reads M, quantisation reads M and writes e4m3 A
-    extra = {"graph_ms_per_step": round(t["graph_ms"], 3),
+    extra = {"graph_ms_per_step": round(t["graph_ms"], 3), "schedules": sched,
              "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
                              "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
                          for k, v in kern.items()},
@@ -255,6 +273,91 @@ def run_e4m3(args, torch, dev, hip, log):
     print(json.dumps(line), flush=True)
 
 
+def run_learned(args, torch, dev, hip, log):
+    """Trains the coefficient network on seeded spectra (h in [64, 1024], the three-family
+    mixture), then orthogonalises the gradient set with the learned plan and with the fixed
+    coefficients (the fallback), and reports ||Y Y^T - I||_F / sqrt(h) per shape class."""
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from paper_2602_02500_amd import learn
+    from workloads import configs, spectra
+    import oracle
+    exps, coeffs = configs.load_coeffs("gform_v1")
+    t0 = time.perf_counter()
+    samples = spectra.spectral_mixture(args.train_samples, seed=5)
+    sig, nsig = spectra.pad_spectra(samples)
+    sig_d, nsig_d = torch.from_numpy(sig).to(dev), torch.from_numpy(nsig).to(dev)
+    log(f"generated {len(samples)} training spectra in {time.perf_counter() - t0:.1f} s")
+    params = torch.from_numpy(oracle.mlp_init(0).astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    learn.train(sig_d, nsig_d, params, epochs=args.epochs, batch=256, lr=2e-3, losses=losses)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    steps = len(losses)
+    first = float(torch.stack(losses[:50]).mean())
+    last = float(torch.stack(losses[-50:]).mean())
+    theta = params.cpu().numpy()
+    log(f"trained {steps} steps in {train_s:.2f} s: loss {first:.4f} -> {last:.4f}")
+    # held-out spectra: mean polar distance^2 / h of learned vs fixed coefficients
+    held = spectra.spectral_mixture(1000, seed=6)
+    ll, lf = [], []
+    for _, _, sgm in held:
+        c, _ = oracle.mlp_forward(theta.astype(np.float64), oracle.features_from_spectrum(sgm))
+        ll.append(oracle.spectral_loss(c, sgm)[0])
+        lf.append(oracle.spectral_loss(coeffs, sgm)[0])
+    Ms = make_d3(torch, dev, args.layers)
+    shapes = [tuple(m.shape) for m in Ms]
+    n = len(Ms)
+    res = {}
+    for mode in ["learned", "fixed"]:
+        plan = ifn.Plan(exps, coeffs, shapes, compute="bf16", mlp_params=theta if mode == "learned" else None)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        Ys = [torch.empty_like(m) for m in Ms]
+        for _ in range(args.warmup):
+            plan.orthogonalize_batched(Ms, Ys, ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.orthogonalize_batched(Ms, Ys, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        out = torch.empty(n, dtype=torch.float64, device=dev)
+        ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        ifn.orth_error(Ys, out, ows)
+        oe = out.cpu().numpy() / np.sqrt([min(s) for s in shapes])
+        per = {}
+        for nm, r, c in configs.LAYER_SHAPES:
+            idx = [i for i, s in enumerate(shapes) if s == (r, c)]
+            per[f"{r}x{c}"] = round(float(oe[idx].mean()), 5)
+        entry = {"matrices_per_s": round(n / dt, 2), "ms_per_step": round(dt * 1e3, 3),
+                 "orth_err_over_sqrt_h_mean": round(float(oe.mean()), 5), "per_shape": per}
+        if mode == "learned":
+            st = plan.stats()
+            entry["network_used_fraction"] = float(np.mean([row[25] for row in st]))
+        res[mode] = entry
+        del ws, Ys, plan
+    value = res["learned"]["matrices_per_s"]
+    line = {
+        "metric": "learned coefficients on the 32-layer gradient set: ||YY^T - I||_F / sqrt(h) vs fixed fallback",
+        "value": value, "unit": "matrices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["learned"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"train on {len(samples)} seeded spectra (h 64..1024, w/h 1..4, log-uniform / "
+                               f"power-law / near-1 mixture), run on the d3 gradient set ({n} matrices)",
+                   "exponents": list(exps), "fallback_coeffs": "gform_v1"},
+        "training": {"samples": len(samples), "epochs": args.epochs, "batch": 256, "steps": steps,
+                     "seconds": round(train_s, 3), "loss_first50": first, "loss_last50": last},
+        "held_out_polar_dist2_over_h": {"learned": float(np.mean(ll)), "fixed": float(np.mean(lf)),
+                                        "spectra": len(held)},
+        "gradset": res,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,10 +367,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3"], default="gradset",
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned"], default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
-                         "heavy-tailed matrices with e4m3 Gram and squarings")
+                         "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
+                         "network on the GPU, then run the gradient set with learned and fixed coefficients")
+    ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
+    ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
+    ap.add_argument("--tune", action="store_true",
+                    help="time candidate tile schedules per stage first and keep the fastest (written to --tune-out)")
+    ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "schedules.json"))
+    ap.add_argument("--schedules", default=os.path.join(ROOT, "paper_2602_02500_amd", "schedules.json"),
+                    help="tuned schedules to apply when the plan's key is present")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
@@ -286,6 +397,8 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     if args.workload == "e4m3":
         return run_e4m3(args, torch, dev, hip, log)
+    if args.workload == "learned":
+        return run_learned(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()
@@ -297,6 +410,7 @@ def main():
     plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+    sched = schedule(args, torch, plan, Ms, Ys, ws, "bf16", exps, log)
     nl = plan.num_launches
     J = nl - 6
     fl = stage_flops(shapes, J)
@@ -313,7 +427,7 @@ def main():
     value = n * args.steps / elapsed
     step_tflops = fl["step"] / (ms_per_step * 1e-3) / 1e12
 
-    extra = {"graph_ms_per_step": round(graph_ms, 3),
+    extra = {"graph_ms_per_step": round(graph_ms, 3), "schedules": sched,
              "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
                              "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
                          for k, v in kern.items()},

@@ -16,7 +16,8 @@ __all__ = [
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
     "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
-    "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes",
+    "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes", "StageConfig",
+    "quantize_e4m3", "quantize_e4m3_workspace_bytes", "STAGE_GRAM", "STAGE_SQUARE", "STAGE_PRODUCT",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +43,18 @@ class IfnsoError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+STAGE_GRAM, STAGE_SQUARE, STAGE_PRODUCT = 0, 1, 2
+
+
+class StageConfig(ctypes.Structure):
+    """Schedule of a 256-tile stage (see ifnso_stage_config)."""
+    _fields_ = [("xcd_sched", ctypes.c_int32), ("group", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("block_cols", ctypes.c_int32), ("wg_per_xcd", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class PolyDesc(ctypes.Structure):
@@ -101,6 +114,10 @@ def load() -> ctypes.CDLL:
     L.ifnso_mlp_train_step.restype = ctypes.c_int
     L.ifnso_mlp_train_workspace_bytes.argtypes = [i32]
     L.ifnso_mlp_train_workspace_bytes.restype = sz
+    L.ifnso_plan_get_config.argtypes = [vp, i32, ctypes.POINTER(StageConfig)]
+    L.ifnso_plan_get_config.restype = ctypes.c_int
+    L.ifnso_plan_set_config.argtypes = [vp, i32, ctypes.POINTER(StageConfig)]
+    L.ifnso_plan_set_config.restype = ctypes.c_int
     L.ifnso_quantize_e4m3.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
     L.ifnso_quantize_e4m3.restype = ctypes.c_int
     L.ifnso_quantize_e4m3_workspace_bytes.argtypes = [i64, i64]
@@ -205,6 +222,15 @@ class Plan:
         st, fl = ctypes.c_int32(), ctypes.c_double()
         _check(self._L.ifnso_plan_launch_info(self._h, int(i), ctypes.byref(st), ctypes.byref(fl)))
         return int(st.value), float(fl.value)
+
+    def get_config(self, stage: int) -> dict:
+        c = StageConfig()
+        _check(self._L.ifnso_plan_get_config(self._h, int(stage), ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, stage: int, cfg: dict):
+        c = StageConfig(**{k: int(v) for k, v in cfg.items()})
+        _check(self._L.ifnso_plan_set_config(self._h, int(stage), ctypes.byref(c)))
 
     def launch_events(self, events):
         """Events (raw hipEvent_t handles) for the next call: one before each slot and one after."""

@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
-template <bool AGG>
+template <bool AGG, bool OV = AGG>
 __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
                            : (const void *)P.opnd[(level - 1) & 1];
     const Operand op = make_operand(srcp, bytes, (uint32_t)(hp * 2), P.hp);
     f32x16 acc[FM][FN];
-    mainloop<false, false, false, AGG>(acc, smem, op, m0, op, n0, uni(P.h), false);
+    mainloop<false, false, false, OV>(acc, smem, op, m0, op, n0, uni(P.h), false);
     uint16_t *dst = AGG ? (uint16_t *)((char *)P.lv + (int64_t)level * P.lv_stride) : (uint16_t *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
@@ -1054,8 +1054,9 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
   if (stage == kStageGram) {
     hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(kThreads), 0, s, a);
   } else if (stage == kStageSquare) {
-    if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(kThreads), 0, s, a);
+    if (a.agg && a.variant) hipLaunchKernelGGL((fast::kf_square<true, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    else if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(kThreads), 0, s, a);
   } else {
     if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
     else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
@@ -1072,7 +1073,7 @@ hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
   const void *fn = stage == kStageGram ? (const void *)fast::kf_gram
-                 : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
+                 : stage == kStageSquare ? (const void *)fast::kf_square<true, true> : (const void *)fast::kf_product<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
 }
 

@@ -207,24 +207,24 @@ int grid_for(int op, int stage, int ntasks, int cus) {
 
 
 
-// Tiles of one problem in panel-sharing blocks of kBlkR x kBlkC tiles (row-major inside a
-// block, blocks row-major); `upper` keeps only tiles with tn >= tm.
-constexpr int kBlkR = 4, kBlkC = 8, kXcds = 8, kGroup = 32;
+// Tiles of one problem in panel-sharing blocks of br x bc tiles (row-major inside a block,
+// blocks row-major); `upper` keeps only tiles with tn >= tm.
+constexpr int kXcds = 8;
 
-void block_order(std::vector<Task> &out, int p, int rows, int cols, bool upper) {
-  for (int br = 0; br < rows; br += kBlkR)
-    for (int bc = upper ? (br / kBlkC) * kBlkC : 0; bc < cols; bc += kBlkC)
-      for (int tm = br; tm < std::min(rows, br + kBlkR); tm++)
-        for (int tn = bc; tn < std::min(cols, bc + kBlkC); tn++)
+void block_order(std::vector<Task> &out, int p, int rows, int cols, bool upper, int br_, int bc_) {
+  for (int br = 0; br < rows; br += br_)
+    for (int bc = upper ? (br / bc_) * bc_ : 0; bc < cols; bc += bc_)
+      for (int tm = br; tm < std::min(rows, br + br_); tm++)
+        for (int tn = bc; tn < std::min(cols, bc + bc_); tn++)
           if (!upper || tn >= tm) out.push_back(Task{p, tm, tn, 0});
 }
 
-// Deals groups of kGroup consecutive tiles to the XCDs in turn; returns the tasks grouped
+// Deals groups of `group` consecutive tiles to the XCDs in turn; returns the tasks grouped
 // by XCD with per-XCD offsets (relative to the start of the returned list) and counts.
-std::vector<Task> xcd_queues(const std::vector<Task> &tiles, int off[kXcds], int cnt[kXcds]) {
+std::vector<Task> xcd_queues(const std::vector<Task> &tiles, int group, int off[kXcds], int cnt[kXcds]) {
   std::vector<std::vector<Task>> q(kXcds);
-  for (size_t g = 0; g * kGroup < tiles.size(); g++) {
-    const size_t b = g * kGroup, e = std::min(tiles.size(), b + kGroup);
+  for (size_t g = 0; g * group < tiles.size(); g++) {
+    const size_t b = g * group, e = std::min(tiles.size(), b + group);
     q[g % kXcds].insert(q[g % kXcds].end(), tiles.begin() + b, tiles.begin() + e);
   }
   std::vector<Task> out;
@@ -276,6 +276,9 @@ struct ifnso_plan_s {
   size_t offf_gram[2] = {0, 0}, offf_square = 0, offf_prod[2] = {0, 0};
   int xq_gram[2][2][kXcds] = {}, xq_square[2][kXcds] = {}, xq_prod[2][2][kXcds] = {};  // [off/cnt]
   double fl_gram[2] = {0, 0}, fl_square = 0, fl_prod[2] = {0, 0};  // algorithmic flops per launch
+  ifnso_stage_config cfg[3];  // 256-tile schedule of the Gram, squaring and product stages
+  std::vector<int> order;     // problems, largest first
+  size_t n_all = 0;           // tasks in d_tasks
   double *d_coef = nullptr;   // [num][kSlots]
   double *d_stats = nullptr;  // [num][kStatsPerProblem]
   int grid[3] = {1, 1, 1};
@@ -291,6 +294,79 @@ struct ifnso_plan_s {
   std::vector<hipEvent_t> stage_events;  // pending measurement request (one call)
   std::mutex mu;
 };
+
+static ifnso_stage_config default_config(int stage) {
+  ifnso_stage_config c;
+  c.xcd_sched = 1;
+  c.group = 32;
+  c.block_rows = 4;
+  c.block_cols = 8;
+  c.wg_per_xcd = 32;
+  c.variant = stage == kStageSquare ? 1 : 0;
+  return c;
+}
+
+// Host task list of a plan: the generic 128-tile lists, then the 256-tile lists (Gram and
+// product split by orientation, each dealt into per-XCD queues as the stage's config says),
+// then the aggregation chunks. Offsets and counts are stored in the plan.
+static std::vector<Task> build_schedule(ifnso_plan_s *p) {
+  std::vector<Task> gram, square, prod;
+  for (int i : p->order) {
+    const ProbLayout &L = p->lay[i];
+    for (int tm = 0; tm < L.nt; tm++)
+      for (int tn = tm; tn < L.nt; tn++) {
+        gram.push_back(Task{i, tm, tn, 0});
+        square.push_back(Task{i, tm, tn, 0});
+      }
+    const int rt = ((L.trans ? L.w : L.h) + kTS - 1) / kTS, ct = ((L.trans ? L.h : L.w) + kTS - 1) / kTS;
+    for (int tm = 0; tm < rt; tm++)
+      for (int tn = 0; tn < ct; tn++) prod.push_back(Task{i, tm, tn, 0});
+  }
+  p->n_gram = (int)gram.size();
+  p->n_square = (int)square.size();
+  p->n_prod = (int)prod.size();
+  std::vector<Task> all;
+  p->off_gram = 0;
+  all.insert(all.end(), gram.begin(), gram.end());
+  p->off_square = all.size();
+  all.insert(all.end(), square.begin(), square.end());
+  p->off_prod = all.size();
+  all.insert(all.end(), prod.begin(), prod.end());
+  if (!p->fast) return all;
+  const ifnso_stage_config &cg = p->cfg[kStageGram], &cs = p->cfg[kStageSquare], &cp = p->cfg[kStageProduct];
+  std::vector<Task> fg[2], fs, fp[2];
+  for (int i : p->order) {
+    const ProbLayout &L = p->lay[i];
+    const int nt = L.hp / kFastTS, tr = L.trans;
+    block_order(fg[tr], i, nt, nt, true, cg.block_rows, cg.block_cols);
+    block_order(fs, i, nt, nt, true, cs.block_rows, cs.block_cols);
+    const int rt = ((tr ? L.w : L.h) + kFastTS - 1) / kFastTS, ct = ((tr ? L.h : L.w) + kFastTS - 1) / kFastTS;
+    block_order(fp[tr], i, rt, ct, false, cp.block_rows, cp.block_cols);
+  }
+  for (int t = 0; t < 2; t++) {
+    p->offf_gram[t] = all.size();
+    p->nf_gram[t] = (int)fg[t].size();
+    const std::vector<Task> qg = xcd_queues(fg[t], cg.group, p->xq_gram[t][0], p->xq_gram[t][1]);
+    all.insert(all.end(), qg.begin(), qg.end());
+    p->offf_prod[t] = all.size();
+    p->nf_prod[t] = (int)fp[t].size();
+    const std::vector<Task> qp = xcd_queues(fp[t], cp.group, p->xq_prod[t][0], p->xq_prod[t][1]);
+    all.insert(all.end(), qp.begin(), qp.end());
+  }
+  p->offf_square = all.size();
+  p->nf_square = (int)fs.size();
+  const std::vector<Task> qs = xcd_queues(fs, cs.group, p->xq_square[0], p->xq_square[1]);
+  all.insert(all.end(), qs.begin(), qs.end());
+  if (p->agg) {
+    p->off_agg = all.size();
+    for (int i : p->order) {
+      const int64_t n = (int64_t)p->lay[i].hp * p->lay[i].hp;
+      for (int64_t c = 0; c * kAggChunk < n; c++) all.push_back(Task{i, (int)c, 0, 0});
+    }
+    p->n_agg = (int)(all.size() - p->off_agg);
+  }
+  return all;
+}
 
 static ifnso_status validate_desc(const ifnso_poly_desc *d) {
   if (!d) return fail(IFNSO_ERR_INVALID_ARGUMENT, "descriptor is NULL");
@@ -427,83 +503,23 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->ws_bytes = off;
 
   // tile schedules: largest problems first (longest-processing-time order)
-  std::vector<int> order(num_problems);
-  for (int i = 0; i < num_problems; i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+  p->order.resize(num_problems);
+  for (int i = 0; i < num_problems; i++) p->order[i] = i;
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
     const double fa = (double)p->lay[a].h * p->lay[a].h * p->lay[a].w;
     const double fb = (double)p->lay[b].h * p->lay[b].h * p->lay[b].w;
     return fa > fb;
   });
-  std::vector<Task> gram, square, prod;
-  for (int i : order) {
+  for (int st = 0; st < 3; st++) p->cfg[st] = default_config(st);
+  for (int i = 0; i < num_problems; i++) {
     const ProbLayout &L = p->lay[i];
-    const int nt = (L.h + kTS - 1) / kTS;  // tiles that hold data; the padding tiles are zero
-    for (int tm = 0; tm < L.nt; tm++)
-      for (int tn = tm; tn < L.nt; tn++) {
-        gram.push_back(Task{i, tm, tn, 0});
-        square.push_back(Task{i, tm, tn, 0});
-      }
-    (void)nt;
-    const int rt = ((L.trans ? L.w : L.h) + kTS - 1) / kTS, ct = ((L.trans ? L.h : L.w) + kTS - 1) / kTS;
-    for (int tm = 0; tm < rt; tm++)
-      for (int tn = 0; tn < ct; tn++) prod.push_back(Task{i, tm, tn, 0});
+    const int tr = p->fast ? L.trans : 0;
+    const double h = L.h, w = L.w;
+    p->fl_gram[tr] += h * h * w;
+    p->fl_square += h * h * h;
+    p->fl_prod[tr] += 2 * h * h * w;
   }
-  p->n_gram = (int)gram.size();
-  p->n_square = (int)square.size();
-  p->n_prod = (int)prod.size();
-  std::vector<Task> all;
-  p->off_gram = 0;
-  all.insert(all.end(), gram.begin(), gram.end());
-  p->off_square = all.size();
-  all.insert(all.end(), square.begin(), square.end());
-  p->off_prod = all.size();
-  all.insert(all.end(), prod.begin(), prod.end());
-  // fast lists (256 tiles): Gram and product split by orientation, one kernel each
-  if (p->fast) {
-    std::vector<Task> fg[2], fs, fp[2];
-    for (int i : order) {
-      const ProbLayout &L = p->lay[i];
-      const int nt = L.hp / kFastTS, tr = L.trans;
-      block_order(fg[tr], i, nt, nt, true);
-      block_order(fs, i, nt, nt, true);
-      const int rt = ((tr ? L.w : L.h) + kFastTS - 1) / kFastTS, ct = ((tr ? L.h : L.w) + kFastTS - 1) / kFastTS;
-      block_order(fp[tr], i, rt, ct, false);
-      const double h = L.h, w = L.w;
-      p->fl_gram[tr] += h * h * w;
-      p->fl_square += h * h * h;
-      p->fl_prod[tr] += 2 * h * h * w;
-    }
-    for (int t = 0; t < 2; t++) {
-      p->offf_gram[t] = all.size();
-      p->nf_gram[t] = (int)fg[t].size();
-      const std::vector<Task> qg = xcd_queues(fg[t], p->xq_gram[t][0], p->xq_gram[t][1]);
-      all.insert(all.end(), qg.begin(), qg.end());
-      p->offf_prod[t] = all.size();
-      p->nf_prod[t] = (int)fp[t].size();
-      const std::vector<Task> qp = xcd_queues(fp[t], p->xq_prod[t][0], p->xq_prod[t][1]);
-      all.insert(all.end(), qp.begin(), qp.end());
-    }
-    p->offf_square = all.size();
-    p->nf_square = (int)fs.size();
-    const std::vector<Task> qs = xcd_queues(fs, p->xq_square[0], p->xq_square[1]);
-    all.insert(all.end(), qs.begin(), qs.end());
-    if (p->agg) {
-      p->off_agg = all.size();
-      for (int i : order) {
-        const int64_t n = (int64_t)p->lay[i].hp * p->lay[i].hp;
-        for (int64_t c = 0; c * kAggChunk < n; c++) all.push_back(Task{i, (int)c, 0, 0});
-      }
-      p->n_agg = (int)(all.size() - p->off_agg);
-    }
-  } else {
-    for (int i = 0; i < num_problems; i++) {
-      const ProbLayout &L = p->lay[i];
-      const double h = L.h, w = L.w;
-      p->fl_gram[0] += h * h * w;
-      p->fl_square += h * h * h;
-      p->fl_prod[0] += 2 * h * h * w;
-    }
-  }
+  std::vector<Task> all = build_schedule(p);
 
   auto cleanup = [&](ifnso_status s) {
     ifnso_plan_destroy(p);
@@ -519,6 +535,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->cus = dev_cus(device);
   if (e == hipSuccess) e = hipMalloc(&p->d_tasks, all.size() * sizeof(Task));
   if (e == hipSuccess) e = hipMemcpy(p->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice);
+  p->n_all = all.size();
   if (e == hipSuccess) e = hipMalloc(&p->d_coef, coef.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_stats, (size_t)num_problems * kStatsPerProblem * sizeof(double));
@@ -631,8 +648,10 @@ static bool fast_io_ok(const ifnso_plan_s *p, const ProbDev &d, const ProbLayout
 
 static bool use_xcd_sched();
 
-static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds]) {
-  a.xcd_sched = use_xcd_sched() ? 1 : 0;
+static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds], const ifnso_stage_config &c) {
+  a.xcd_sched = (use_xcd_sched() && c.xcd_sched) ? 1 : 0;
+  a.wg_per_xcd = c.wg_per_xcd;
+  a.variant = c.variant;
   for (int x = 0; x < kXcds; x++) {
     a.xcd_off[x] = off[x];
     a.xcd_cnt[x] = cnt[x];
@@ -641,11 +660,18 @@ static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds]) {
 
 // One workgroup per CU; with XCD queues, a multiple of 8 workgroups, no more than the
 // longest queue needs.
+// Launch parameters of a stage's config that apply to single-problem calls too.
+static void apply_cfg(StageArgs &a, const ifnso_stage_config &c) {
+  a.wg_per_xcd = c.wg_per_xcd;
+  a.variant = c.variant;
+}
+
 static int fast_grid(const StageArgs &a, int cus) {
-  if (!a.xcd_sched) return std::max(1, std::min(a.ntasks, cus));
+  const int per_xcd = std::max(1, std::min(cus / kXcds, a.wg_per_xcd > 0 ? a.wg_per_xcd : cus / kXcds));
+  if (!a.xcd_sched) return std::max(1, std::min(a.ntasks, kXcds * per_xcd));
   int mx = 1;
   for (int x = 0; x < kXcds; x++) mx = std::max(mx, a.xcd_cnt[x]);
-  return kXcds * std::max(1, std::min(cus / kXcds, mx));
+  return kXcds * std::max(1, std::min(per_xcd, mx));
 }
 
 // Enqueues every stage of a plan on `s`, reading problems from `table` (batched) or `one`.
@@ -687,16 +713,18 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
       if (!one) {
         a.tasks = p->d_tasks + p->offf_gram[t];
-        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1]);
+        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1], p->cfg[kStageGram]);
       }
+      apply_cfg(a, p->cfg[kStageGram]);
       e = launch_e4m3_gemm(kStageGram, a, fast_grid(a, cus), s);
       a.xcd_sched = 0;
     } else if (fast && fast_io) {
       a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
       if (!one) {
         a.tasks = p->d_tasks + p->offf_gram[t];
-        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1]);
+        set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1], p->cfg[kStageGram]);
       }
+      apply_cfg(a, p->cfg[kStageGram]);
       e = launch_fast_stage(kStageGram, t, a, fast_grid(a, cus), outbf, s);
       a.xcd_sched = 0;
     } else if (t == 0) {
@@ -715,16 +743,18 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;
-        set_xcd(a, p->xq_square[0], p->xq_square[1]);
+        set_xcd(a, p->xq_square[0], p->xq_square[1], p->cfg[kStageSquare]);
       }
+      apply_cfg(a, p->cfg[kStageSquare]);
       e = launch_e4m3_gemm(kStageSquare, a, fast_grid(a, cus), s);
       a.xcd_sched = 0;
     } else if (fast) {
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;
-        set_xcd(a, p->xq_square[0], p->xq_square[1]);
+        set_xcd(a, p->xq_square[0], p->xq_square[1], p->cfg[kStageSquare]);
       }
+      apply_cfg(a, p->cfg[kStageSquare]);
       e = launch_fast_stage(kStageSquare, 0, a, fast_grid(a, cus), outbf, s);
       a.xcd_sched = 0;
     } else {
@@ -755,8 +785,9 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       a.ntasks = one ? (t == tr0 ? ntiles_prod(kFastTS) : 0) : p->nf_prod[t];
       if (!one) {
         a.tasks = p->d_tasks + p->offf_prod[t];
-        set_xcd(a, p->xq_prod[t][0], p->xq_prod[t][1]);
+        set_xcd(a, p->xq_prod[t][0], p->xq_prod[t][1], p->cfg[kStageProduct]);
       }
+      apply_cfg(a, p->cfg[kStageProduct]);
       e = launch_fast_stage(kStageProduct, t, a, fast_grid(a, cus), outbf, s);
       a.xcd_sched = 0;
     } else if (t == 0) {
@@ -889,6 +920,46 @@ extern "C" ifnso_status ifnso_plan_launch_info(ifnso_plan_t p, int32_t i, int32_
     *stage = kStageProduct;
     *flops = p->fl_prod[i - 3 - p->Jsq];
   }
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_get_config(ifnso_plan_t p, int32_t stage, ifnso_stage_config *cfg) {
+  if (!p || !cfg) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (stage < kStageGram || stage > kStageProduct) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad stage %d", stage);
+  std::lock_guard<std::mutex> lock(p->mu);
+  *cfg = p->cfg[stage];
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_plan_set_config(ifnso_plan_t p, int32_t stage, const ifnso_stage_config *cfg) {
+  if (!p || !cfg) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (stage < kStageGram || stage > kStageProduct) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad stage %d", stage);
+  const ifnso_stage_config &c = *cfg;
+  if ((c.xcd_sched != 0 && c.xcd_sched != 1) || c.group < 1 || c.group > 4096 || c.block_rows < 1 ||
+      c.block_rows > 64 || c.block_cols < 1 || c.block_cols > 64 || c.wg_per_xcd < 1 || c.wg_per_xcd > 1024 ||
+      c.variant < 0 || c.variant > 1)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "stage config out of range");
+  std::lock_guard<std::mutex> lock(p->mu);
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != p->device) HIP_TRY(hipSetDevice(p->device));
+  struct Restore {
+    int d, cur;
+    ~Restore() {
+      if (d != cur) (void)hipSetDevice(d);
+    }
+  } restore{prev, p->device};
+  // the task list changes: wait for calls in flight, drop the captured graphs
+  HIP_TRY(hipDeviceSynchronize());
+  p->cfg[stage] = c;
+  const std::vector<Task> all = build_schedule(p);
+  if (all.size() != p->n_all) return fail(IFNSO_ERR_INTERNAL, "schedule size changed");
+  HIP_TRY(hipMemcpy(p->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice));
+  for (int g = 0; g < 2 * kSlotsRing; g++)
+    if (p->gexec[g]) {
+      (void)hipGraphExecDestroy(p->gexec[g]);
+      p->gexec[g] = nullptr;
+    }
   return IFNSO_OK;
 }
 

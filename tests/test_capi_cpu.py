@@ -159,3 +159,9 @@ def test_workspace_sizes_grow_with_shape(L):
     assert 0 < a < b and b == c
     assert L.ifnso_orth_error_workspace_bytes(0) == 0
     assert L.ifnso_orth_error_workspace_bytes(224) > 224 * 32
+
+
+def test_stage_config_argument_checks(L):
+    c = ifn.StageConfig(1, 32, 4, 8, 32, 0)
+    assert L.ifnso_plan_get_config(None, 0, ctypes.byref(c)) == 1
+    assert L.ifnso_plan_set_config(None, 0, ctypes.byref(c)) == 1

@@ -331,3 +331,40 @@ def test_launch_events_and_info(torch_dev):
     assert all(t >= 0 for t in times) and sum(times) > 0
     with pytest.raises(ifn.IfnsoError):
         plan.launch_events([evs[0].cuda_event])
+
+
+def test_schedule_configs_leave_results_bitwise(torch_dev):
+    """Every 256-tile schedule (tile order, XCD queues, grid, mainloop variant) computes each tile
+    the same way, so outputs are bitwise equal; the tuner picks one of them."""
+    torch, dev = torch_dev
+    import paper_2602_02500_amd as ifn
+    from paper_2602_02500_amd import tune
+    shapes = [(512, 768), (768, 512), (256, 1024), (520, 264)]
+    exps, c = configs.load_coeffs("gform_v1")
+    plan = ifn.Plan(exps, c, shapes, compute="bf16")
+    Ms = [_to_dev(torch, dev, gen.gaussian_np(*s, seed=11 + i), "bf16")[0] for i, s in enumerate(shapes)]
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+
+    def run():
+        Ys = [torch.empty_like(m) for m in Ms]
+        plan.orthogonalize_batched(Ms, Ys, ws)
+        torch.cuda.synchronize()
+        return [y.float().cpu().numpy() for y in Ys]
+
+    ref = run()
+    for st in (ifn.STAGE_GRAM, ifn.STAGE_SQUARE, ifn.STAGE_PRODUCT):
+        for cfg in tune.candidates(st)[::5]:
+            plan.set_config(st, cfg)
+            assert plan.get_config(st) == cfg
+            out = run()
+            assert all(np.array_equal(a, b) for a, b in zip(out, ref)), (st, cfg)
+    res = tune.tune(plan, Ms, [torch.empty_like(m) for m in Ms], ws, reps=1)
+    assert set(res) == {"gram", "square", "product"}
+    for name, r in res.items():
+        assert r["config"] in tune.candidates(tune.STAGES[name]) or r["config"] == plan.get_config(tune.STAGES[name])
+        assert r["ms"] <= r["default_ms"] + 1e-9
+    out = run()
+    assert all(np.array_equal(a, b) for a, b in zip(out, ref))
+    with pytest.raises(ifn.IfnsoError):
+        plan.set_config(ifn.STAGE_GRAM, dict(xcd_sched=2, group=32, block_rows=4, block_cols=8, wg_per_xcd=32,
+                                             variant=0))
