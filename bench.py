@@ -58,7 +58,9 @@ def make_d3(torch, dev, layers=32):
 def schedule(args, torch, plan, Ms, Ys, ws, compute, exps, log):
     """Applies cached tuned schedules for this plan, or tunes them (--tune). Returns a record."""
     from paper_2602_02500_amd import tune
-    key = tune.plan_key(torch.cuda.get_device_name(0), [tuple(m.shape) for m in Ms], compute, exps)
+    props = torch.cuda.get_device_properties(0)
+    device = f"{getattr(props, 'gcnArchName', 'gpu').split(':')[0]}-{props.multi_processor_count}cu"
+    key = tune.plan_key(device, [tuple(m.shape) for m in Ms], compute, exps)
     if args.tune:
         res = tune.tune(plan, Ms, Ys, ws, log=log)
         os.makedirs(os.path.dirname(args.tune_out), exist_ok=True)
@@ -374,6 +376,9 @@ def main():
     ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
     ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run a plain elementwise copy (out = x + 0, float32) that reads and writes BYTES, "
+                         "as a known-size reference for hardware byte counters")
     ap.add_argument("--tune", action="store_true",
                     help="time candidate tile schedules per stage first and keep the fastest (written to --tune-out)")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "schedules.json"))
@@ -395,6 +400,12 @@ def main():
     torch.cuda.set_device(dev)
     hip = _hip()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.copy_calibration > 0:
+        x = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.add(x, 0, out=y)
+        torch.cuda.synchronize()
+        del x, y
     if args.workload == "e4m3":
         return run_e4m3(args, torch, dev, hip, log)
     if args.workload == "learned":

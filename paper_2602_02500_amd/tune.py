@@ -79,7 +79,8 @@ def tune(plan, Ms, Ys, ws, stages: Iterable[str] = ("gram", "square", "product")
 
 
 def plan_key(device_name: str, shapes, compute: str, exponents) -> str:
-    """Cache key: device, compute type, exponents and the multiset of problem shapes."""
+    """Cache key: device (architecture and compute-unit count), compute type, exponents and the
+    multiset of problem shapes."""
     sig = json.dumps({"compute": compute, "exponents": list(map(int, exponents)),
                       "shapes": sorted([list(map(int, s)) for s in shapes])})
     return f"{device_name}|{hashlib.sha1(sig.encode()).hexdigest()[:16]}"
