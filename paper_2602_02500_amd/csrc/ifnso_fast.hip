@@ -27,7 +27,17 @@ namespace fast {
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int BM = 256, BN = 256, BK = 64;
-constexpr int WM = 128, WN = 128, FM = 4, FN = 4;
+#ifndef IFNSO_FAST_WAVES
+#define IFNSO_FAST_WAVES 8
+#endif
+// Waves per workgroup: 8 in a 2 x 4 arrangement (two waves per SIMD, so one wave's LDS reads,
+// address arithmetic and waits overlap the other's MFMAs), each owning a 128 x 64 block of the
+// tile; 4 (2 x 2, 128 x 128 per wave) also builds.
+constexpr int NW = IFNSO_FAST_WAVES;
+constexpr int NT = NW * 64;                     // threads per workgroup
+constexpr int WGN = NW / 2;                     // waves along N
+constexpr int WM = 128, WN = BN / WGN, FM = WM / 32, FN = WN / 32;
+constexpr int RPT = BM / (8 * NW);              // rows of an operand tile one thread loads per stage
 constexpr int STAGE_BYTES = (BM + BN) * 128;  // 64 KiB
 constexpr int LDS_BYTES = 2 * STAGE_BYTES;    // 128 KiB
 constexpr uint32_t OOB = 0x80000000u;
@@ -84,8 +94,8 @@ __device__ __forceinline__ int swz(int row) { return (row ^ (row >> 3)) & 7; }
 __device__ __forceinline__ double lds_sumsq(const char *At) {
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < BM * 8 / kThreads; i++) {
-    const uint4 q = *(const uint4 *)(At + (threadIdx.x + kThreads * i) * 16);
+  for (int i = 0; i < BM * 8 / NT; i++) {
+    const uint4 q = *(const uint4 *)(At + (threadIdx.x + NT * i) * 16);
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -125,20 +135,20 @@ __device__ __forceinline__ Operand make_operand(const void *p, uint32_t bytes, u
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// Byte offsets of one thread's rows of a K-major operand tile (ROWS / 32 rows; wave-instruction g
-// covers rows 8g..8g+7, lane chunk c = (lane & 7) ^ swz(row)), computed once per tile: the
+// Byte offsets of one thread's rows of a K-major operand tile (ROWS / (8 NW) rows; wave-instruction
+// g covers rows 8g..8g+7, lane chunk c = (lane & 7) ^ swz(row)), computed once per tile: the
 // offset of chunk c at k = 0, or OOB for rows outside the operand. A K step adds k0 * ES.
 template <int ROWS>
 struct KRows {
-  uint32_t off[ROWS / 32];
+  uint32_t off[ROWS / (8 * NW)];
 };
 
 template <int ROWS>
 __device__ __forceinline__ void krows(KRows<ROWS> &R, uint32_t ld_bytes, int m0, int mlim) {
   const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < ROWS / 32; i++) {
-    const int row = (i * 4 + wave) * 8 + (lane >> 3);
+  for (int i = 0; i < ROWS / (8 * NW); i++) {
+    const int row = (i * NW + wave) * 8 + (lane >> 3);
     const int c = (lane & 7) ^ swz(row);
     const int m = m0 + row;
     R.off[i] = m < mlim ? (uint32_t)m * ld_bytes + (uint32_t)c * 16u : OOB;
@@ -153,7 +163,7 @@ __device__ __forceinline__ void issue_krows_(const KRows<ROWS> &R, uint32_t lt, 
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = I0; i < I1; i++) {
-    const int g = i * 4 + wave;
+    const int g = i * NW + wave;
     uint32_t off = R.off[i] + (uint32_t)(k0 * ES);
     if constexpr (!FULL) {
       const int row = g * 8 + (lane >> 3);
@@ -180,9 +190,9 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   constexpr int ES = F8 ? 1 : 2;
   constexpr int KST = 128 / ES;           // elements per stage
   constexpr int NS = F8 ? 2 : BK / 16;    // MFMA K slices per stage
-  constexpr int PER = (BM / 32) / NS;     // rows of each operand issued per slice
+  constexpr int PER = RPT / NS;           // rows of each operand issued per slice
   const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   const int lr = lane & 31, lg = lane >> 5;
 #pragma unroll
   for (int i = 0; i < FM; i++)
@@ -200,8 +210,8 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   const uint32_t lbase = uni(lds_addr(smem));
   {
     const bool full = KST <= K;
-    issue_krows<BM, ES, 0, BM / 32>(RA, lbase, A.w, 0, K, full, wave);
-    issue_krows<BN, ES, 0, BN / 32>(RB, lbase + BM * 128, B.w, 0, K, full, wave);
+    issue_krows<BM, ES, 0, RPT>(RA, lbase, A.w, 0, K, full, wave);
+    issue_krows<BN, ES, 0, RPT>(RB, lbase + BM * 128, B.w, 0, K, full, wave);
   }
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
@@ -260,8 +270,19 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
       };
       auto slice = [&](auto slc) {
         constexpr int kk = decltype(slc)::value;
-        constexpr int sl = kk & 1;
+        constexpr int sl = NW == 8 ? 0 : (kk & 1);
         issue_slice(slc);
+        if constexpr (NW == 8) {
+          // two waves per SIMD: the other wave's MFMAs cover this slice's LDS latency, so one
+          // fragment set suffices (the register budget is 256 per wave)
+          rd(kk, 0);
+#pragma unroll
+          for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][i], fb[0][j], acc[i][j], 0, 0, 0);
+          return;
+        }
         if constexpr (kk + 1 < NS) rd(kk + 1, sl ^ 1);
 #pragma unroll
         for (int i = 0; i < FM; i++)
@@ -276,7 +297,7 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
           }
         }
       };
-      rd(0, 0);
+      if constexpr (NW != 8) rd(0, 0);
       slice(std::integral_constant<int, 0>{});
       slice(std::integral_constant<int, 1>{});
       slice(std::integral_constant<int, 2>{});
@@ -297,7 +318,7 @@ __device__ __forceinline__ double mainloop_bf16(f32x16 (&acc)[FM][FN], char *sme
                                                 const Operand &B, int bn0, int K, bool want_norm) {
   constexpr int ES = 2, KST = 64;
   const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   const int lr = lane & 31, lg = lane >> 5;
 #pragma unroll
   for (int i = 0; i < FM; i++)
@@ -317,8 +338,8 @@ __device__ __forceinline__ double mainloop_bf16(f32x16 (&acc)[FM][FN], char *sme
     const uint32_t As = lbase + (st & 1) * STAGE_BYTES;
     const int k0 = st * KST;
     const bool full = k0 + KST <= K;
-    issue_krows<BM, ES, 0, BM / 32>(RA, As, A.w, k0, K, full, wave);
-    issue_krows<BN, ES, 0, BN / 32>(RB, As + BM * 128, B.w, k0, K, full, wave);
+    issue_krows<BM, ES, 0, RPT>(RA, As, A.w, k0, K, full, wave);
+    issue_krows<BN, ES, 0, RPT>(RB, As + BM * 128, B.w, k0, K, full, wave);
   };
   bf16x8 fa[2][FM], fb[2][FN];
   auto rd = [&](const char *As, int kk, int sl) {
@@ -343,7 +364,7 @@ __device__ __forceinline__ double mainloop_bf16(f32x16 (&acc)[FM][FN], char *sme
   issue_stage(0);
   if (nk > 1) {
     issue_stage(1);
-    wait_vmcnt<BM / 32 + BN / 32>();
+    wait_vmcnt<2 * RPT>();
   } else {
     wait_vmcnt<0>();
   }
@@ -383,7 +404,7 @@ template <bool AMN, bool BMN, bool F8 = false, bool OV = false>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                            const Operand &B, int bn0, int K, bool want_norm) {
   static_assert(!AMN && !BMN, "operands are K-contiguous (tall inputs and wide products use M^T copies)");
-  if constexpr (OV && !F8) return mainloop_bf16(acc, smem, A, am0, B, bn0, K, want_norm);
+  if constexpr (OV && !F8 && NW == 4) return mainloop_bf16(acc, smem, A, am0, B, bn0, K, want_norm);
   else return mainloop_kk<F8>(acc, smem, A, am0, B, bn0, K, want_norm);
 }
 
@@ -392,7 +413,7 @@ __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, co
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void stage_half(const f32x16 (&acc)[FM][FN], float *ep, int half) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   if (wm != half) return;
 #pragma unroll
   for (int i = 0; i < FM; i++)
@@ -510,7 +531,7 @@ template <typename F>
 __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, int64_t hp, int m0, int n0, int half,
                                               bool diag, F f) {
   // direct: 128 rows x 32 chunks of 8
-  for (int q = threadIdx.x; q < 128 * 32; q += kThreads) {
+  for (int q = threadIdx.x; q < 128 * 32; q += NT) {
     const int row = q >> 5, c8 = (q & 31) * 8;
     const float *src = ep + row * EP_LD + c8;
     uint4 o;
@@ -523,7 +544,7 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
   if (diag) return;
   // mirror: element (row, col) of the tile goes to (n0 + col, m0 + row); 256 mirror rows x
   // 16 chunks of 8 consecutive tile rows
-  for (int q = threadIdx.x; q < 256 * 16; q += kThreads) {
+  for (int q = threadIdx.x; q < 256 * 16; q += NT) {
     const int col = q >> 4, r8 = (q & 15) * 8;
     float v[8];
 #pragma unroll
@@ -537,23 +558,75 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
   }
 }
 
+// Sums of three float64 values over the workgroup in a fixed order (lanes, then waves 0..NW-1).
+__device__ __forceinline__ void block_sum3w(double &a, double &b, double &c, double *scratch) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    scratch[wave * 3 + 0] = a;
+    scratch[wave * 3 + 1] = b;
+    scratch[wave * 3 + 2] = c;
+  }
+  __syncthreads();
+  a = scratch[0];
+  b = scratch[1];
+  c = scratch[2];
+#pragma unroll
+  for (int w = 1; w < NW; w++) {
+    a += scratch[w * 3 + 0];
+    b += scratch[w * 3 + 1];
+    c += scratch[w * 3 + 2];
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ float block_max(float v, float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
   __syncthreads();
   if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
   __syncthreads();
-  v = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
+  v = scratch[0];
+#pragma unroll
+  for (int w = 1; w < NW; w++) v = fmaxf(v, scratch[w]);
   __syncthreads();
   return v;
 }
 
+// Sum of squares and (AMAX) max |value| of scale * tile straight from the accumulators (each
+// lane's 32 x 32 blocks summed in float32, accumulated in float64); off-diagonal tiles count
+// twice (mirror).
+template <bool AMAX>
+__device__ __forceinline__ void reg_partials(const f32x16 (&acc)[FM][FN], float scale, bool diag, double &lv,
+                                             float &mx) {
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const float x = scale * acc[i][j][r];
+        s2 = fmaf(x, x, s2);
+        if constexpr (AMAX) mx = fmaxf(mx, fabsf(x));
+      }
+      lv += (double)s2;
+    }
+  if (!diag) lv *= 2.0;
+}
+
 // Level-layout epilogue: level `out` = scale * acc is stored as bfloat16 (tile and mirror) at
-// lv + (out - 1) * lv_stride with the partials of its sum of squares and trace (each
-// thread's sum of a row segment in float32, accumulated in float64). With AMAX, also the
-// tile's max |stored value| (the next e4m3 quantisation needs the level's maximum); it is
-// taken before the bfloat16 rounding, which is monotone, so it rounds to the maximum of the
-// stored values.
+// lv + (out - 1) * lv_stride with the partials of its sum of squares (reg_partials) and trace
+// (diagonal tiles: from the staged tile). With AMAX, also the tile's max |stored value| (the
+// next e4m3 quantisation needs the level's maximum); it is taken before the bfloat16 rounding,
+// which is monotone, so it rounds to the maximum of the stored values.
+
 template <bool AMAX>
 __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *smem, const ProbDev &P, int out,
                                             const Task &task, float scale) {
@@ -564,24 +637,15 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
   uint16_t *dst = (uint16_t *)((char *)P.lv + (int64_t)(out - 1) * P.lv_stride);
   double lv = 0.0, dg = 0.0, unused = 0.0;
   float mx = 0.f;
+  reg_partials<AMAX>(acc, scale, diag, lv, mx);
   for (int half = 0; half < 2; half++) {
     stage_half(acc, ep, half);
     __syncthreads();
-    for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
-      const int row = q >> 6, c4 = (q & 63) * 4;
-      const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
-      const float x0 = scale * v.x, x1 = scale * v.y, x2 = scale * v.z, x3 = scale * v.w;
-      lv += (diag ? 1.0 : 2.0) * (double)(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
-      if constexpr (AMAX) mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fmaxf(fabsf(x2), fabsf(x3))));
-      if (diag) {
-        const int d = half * 128 + row - c4;
-        if (d >= 0 && d < 4) dg += d == 0 ? x0 : d == 1 ? x1 : d == 2 ? x2 : x3;
-      }
-    }
+    if (diag && threadIdx.x < 128) dg += (double)(scale * ep[threadIdx.x * EP_LD + half * 128 + threadIdx.x]);
     emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [scale](float v, int, int) { return scale * v; });
     __syncthreads();
   }
-  block_sum3(lv, dg, unused, (double *)smem);
+  block_sum3w(lv, dg, unused, (double *)smem);
   if constexpr (AMAX) mx = block_max(mx, (float *)smem);
   if (threadIdx.x == 0) {
     write_level_partials(P, out, task, lv, dg);
@@ -600,7 +664,7 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
 // ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
+__global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
   const TaskRange tr = task_range(a);
@@ -624,12 +688,19 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
     const int64_t hp = P.hp;
     const bool keep_f32 = (a.J >= 1 && !a.agg) || a.learned;
     double lv = 0.0, dg = 0.0;
+    float unused_mx = 0.f;
+    if (!keep_f32) reg_partials<false>(acc, 1.f, diag, lv, unused_mx);
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
       emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+      if (!keep_f32) {
+        if (diag && threadIdx.x < 128) dg += (double)ep[threadIdx.x * EP_LD + half * 128 + threadIdx.x];
+        __syncthreads();
+        continue;
+      }
       // float32 upper tile, partial sums
-      for (int q = threadIdx.x; q < 128 * 64; q += kThreads) {
+      for (int q = threadIdx.x; q < 128 * 64; q += NT) {
         const int row = q >> 6, c4 = (q & 63) * 4;
         const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
         if (keep_f32) *(float4 *)(P.accf + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4) = v;
@@ -643,7 +714,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
       __syncthreads();
     }
     if (!diag) nrm = 0.0;
-    block_sum3(lv, dg, nrm, (double *)smem);
+    block_sum3w(lv, dg, nrm, (double *)smem);
     if (threadIdx.x == 0) {
       write_level_partials(P, 1, task, lv, dg);
       if (diag) {
@@ -659,7 +730,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram(const StageArgs a) {
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
 template <bool AGG, bool OV = AGG>
-__global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
+__global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
   const int level = a.level;
@@ -710,12 +781,12 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
       // pass 1 (row-wise, upper tile): new level value `out`, running sum P; the staged value
       // is replaced by what is stored (out, or P on the last level) for the bf16 emit. The
       // float32 reads of a batch are issued together (they do not wait on the batch's stores).
-      constexpr int PER = 128 * 64 / kThreads, BATCH = 8;
+      constexpr int PER = 128 * 64 / NT, BATCH = 8;
       for (int b0 = 0; b0 < PER; b0 += BATCH) {
         float4 pin[BATCH], dpv[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int q = threadIdx.x + NT * (b0 + u);
           const int row = q >> 6, c4 = (q & 63) * 4;
           const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
           pin[u] = *(const float4 *)(P.accf + gi);
@@ -723,7 +794,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int q = threadIdx.x + NT * (b0 + u);
           const int row = q >> 6, c4 = (q & 63) * 4;
           float *sp = ep + row * EP_LD + c4;
           const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
@@ -762,7 +833,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
       emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
       __syncthreads();
     }
-    block_sum3(lv, dg, unused, (double *)smem);
+    block_sum3w(lv, dg, unused, (double *)smem);
     if (threadIdx.x == 0) write_level_partials(P, level + 1, task, lv, dg);
     __syncthreads();
     }
@@ -777,7 +848,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ float inv_square(float s) { return 1.f / s / s; }
 
-__global__ __launch_bounds__(kThreads, 1) void kf_gram8(const StageArgs a) {
+__global__ __launch_bounds__(NT, 1) void kf_gram8(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   const TaskRange tr = task_range(a);
   for (int t = tr.start; t < tr.end; t += tr.stride) {
@@ -795,7 +866,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_gram8(const StageArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kThreads, 1) void kf_square8(const StageArgs a) {
+__global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   const int level = a.level;
   int cur_p = -1;
@@ -825,7 +896,7 @@ __global__ __launch_bounds__(kThreads, 1) void kf_square8(const StageArgs a) {
 // product: Y = s (c0 A + P A) in M's orientation (IFNSO only)
 // ---------------------------------------------------------------------------------------------
 template <bool TRANS>
-__global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, const int out_bf16) {
+__global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int out_bf16) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
   int cur_p = -1;
@@ -892,19 +963,19 @@ __global__ __launch_bounds__(kThreads, 1) void kf_product(const StageArgs a, con
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
-      constexpr int PER = 128 * 32 / kThreads, BATCH = 8;
+      constexpr int PER = 128 * 32 / NT, BATCH = 8;
       for (int b0 = 0; b0 < PER; b0 += BATCH) {
         uint4 xm[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int q = threadIdx.x + NT * (b0 + u);
           const int row = q >> 5, c8 = (q & 31) * 8;
           const int r = m0 + half * 128 + row, c = n0 + c8;
           xm[u] = (r < rows_out && c < cols_out) ? *(const uint4 *)(M + (int64_t)r * P.ldm + c) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int q = threadIdx.x + NT * (b0 + u);
           const int row = q >> 5, c8 = (q & 31) * 8;
           const int r = m0 + half * 128 + row, c = n0 + c8;
           if (r >= rows_out || c >= cols_out) continue;
@@ -1052,29 +1123,29 @@ hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   if (stage == kStageGram) {
-    hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(fast::NT), 0, s, a);
   } else if (stage == kStageSquare) {
-    if (a.agg && a.variant) hipLaunchKernelGGL((fast::kf_square<true, true>), dim3(grid), dim3(kThreads), 0, s, a);
-    else if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    if (a.agg && a.variant) hipLaunchKernelGGL((fast::kf_square<true, true>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
   } else {
-    if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
-    else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(kThreads), 0, s, a, out_bf16);
+    if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
+    else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
-  if (stage == kStageGram) hipLaunchKernelGGL(fast::kf_gram8, dim3(grid), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(fast::kf_square8, dim3(grid), dim3(kThreads), 0, s, a);
+  if (stage == kStageGram) hipLaunchKernelGGL(fast::kf_gram8, dim3(grid), dim3(fast::NT), 0, s, a);
+  else hipLaunchKernelGGL(fast::kf_square8, dim3(grid), dim3(fast::NT), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
   const void *fn = stage == kStageGram ? (const void *)fast::kf_gram
                  : stage == kStageSquare ? (const void *)fast::kf_square<true, true> : (const void *)fast::kf_product<false>;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, fast::NT, 0);
 }
 
 }  // namespace ifnso
