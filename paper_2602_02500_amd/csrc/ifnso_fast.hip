@@ -530,22 +530,22 @@ __device__ __forceinline__ void write_level_partials(const ProbDev &P, int level
 template <typename F>
 __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, int64_t hp, int m0, int n0, int half,
                                               bool diag, F f) {
-  // direct: 128 rows x 32 chunks of 8
-  for (int q = threadIdx.x; q < 128 * 32; q += NT) {
-    const int row = q >> 5, c8 = (q & 31) * 8;
-    const float *src = ep + row * EP_LD + c8;
-    uint4 o;
-    o.x = pack_bf16x2(f(src[0], row, c8 + 0), f(src[1], row, c8 + 1));
-    o.y = pack_bf16x2(f(src[2], row, c8 + 2), f(src[3], row, c8 + 3));
-    o.z = pack_bf16x2(f(src[4], row, c8 + 4), f(src[5], row, c8 + 5));
-    o.w = pack_bf16x2(f(src[6], row, c8 + 6), f(src[7], row, c8 + 7));
-    *(uint4 *)(dst + (int64_t)(m0 + half * 128 + row) * hp + n0 + c8) = o;
+  // direct: each wave instruction reads one staged row (64 lanes x 16 contiguous bytes, no bank
+  // conflict) and stores it as 512 contiguous bytes of bfloat16
+  for (int q = threadIdx.x; q < 128 * 64; q += NT) {
+    const int row = q >> 6, c4 = (q & 63) * 4;
+    const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
+    const uint2 o = make_uint2(pack_bf16x2(f(v.x, row, c4), f(v.y, row, c4 + 1)),
+                               pack_bf16x2(f(v.z, row, c4 + 2), f(v.w, row, c4 + 3)));
+    *(uint2 *)(dst + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4) = o;
   }
   if (diag) return;
-  // mirror: element (row, col) of the tile goes to (n0 + col, m0 + row); 256 mirror rows x
-  // 16 chunks of 8 consecutive tile rows
+  // mirror: element (row, col) of the tile goes to (n0 + col, m0 + row). Four consecutive lanes
+  // cover 32 tile rows (four chunks of 8) of one column, so a store instruction writes 64
+  // contiguous bytes into each of 16 mirror rows; with the column varying across lane groups
+  // the column reads of the staged half meet at most a 4-way bank conflict.
   for (int q = threadIdx.x; q < 256 * 16; q += NT) {
-    const int col = q >> 4, r8 = (q & 15) * 8;
+    const int col = (q >> 2) & 255, r8 = (((q >> 10) << 2) | (q & 3)) * 8;
     float v[8];
 #pragma unroll
     for (int e = 0; e < 8; e++) v[e] = f(ep[(r8 + e) * EP_LD + col], r8 + e, col);
