@@ -415,16 +415,16 @@ __device__ __forceinline__ void stage_half(const f32x16 (&acc)[FM][FN], float *e
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   if (wm != half) return;
+  // one base address per 32-row block; the rest are immediate offsets of the LDS stores
+  float *base = ep + 4 * (lane >> 5) * EP_LD + wn * WN + (lane & 31);
 #pragma unroll
-  for (int i = 0; i < FM; i++)
+  for (int i = 0; i < FM; i++) {
+    float *pi = base + uni(i * 32 * EP_LD);
 #pragma unroll
     for (int j = 0; j < FN; j++)
 #pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = wn * WN + j * 32 + (lane & 31);
-        ep[row * EP_LD + col] = acc[i][j][r];
-      }
+      for (int r = 0; r < 16; r++) pi[(8 * (r >> 2) + (r & 3)) * EP_LD + j * 32] = acc[i][j][r];
+  }
 }
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
@@ -531,30 +531,44 @@ template <typename F>
 __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, int64_t hp, int m0, int n0, int half,
                                               bool diag, F f) {
   // direct: each wave instruction reads one staged row (64 lanes x 16 contiguous bytes, no bank
-  // conflict) and stores it as 512 contiguous bytes of bfloat16
-  for (int q = threadIdx.x; q < 128 * 64; q += NT) {
-    const int row = q >> 6, c4 = (q & 63) * 4;
-    const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
-    const uint2 o = make_uint2(pack_bf16x2(f(v.x, row, c4), f(v.y, row, c4 + 1)),
-                               pack_bf16x2(f(v.z, row, c4 + 2), f(v.w, row, c4 + 3)));
-    *(uint2 *)(dst + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4) = o;
+  // conflict) and stores it as 512 contiguous bytes of bfloat16. Per-iteration offsets are
+  // uniform (scalar) additions to one per-thread base.
+  {
+    constexpr int RS = NT / 64;  // rows per iteration
+    const int row0 = threadIdx.x >> 6, c4 = (threadIdx.x & 63) * 4;
+    const float *src = ep + row0 * EP_LD + c4;
+    uint16_t *d = dst + (int64_t)(m0 + half * 128 + row0) * hp + n0 + c4;
+#pragma unroll 4
+    for (int it = 0; it < 128 / RS; it++) {
+      const float4 v = *(const float4 *)(src + it * RS * EP_LD);
+      const int row = row0 + it * RS;
+      *(uint2 *)(d + (int64_t)uni(it * RS) * hp) = make_uint2(pack_bf16x2(f(v.x, row, c4), f(v.y, row, c4 + 1)),
+                                                              pack_bf16x2(f(v.z, row, c4 + 2), f(v.w, row, c4 + 3)));
+    }
   }
   if (diag) return;
   // mirror: element (row, col) of the tile goes to (n0 + col, m0 + row). Four consecutive lanes
   // cover 32 tile rows (four chunks of 8) of one column, so a store instruction writes 64
   // contiguous bytes into each of 16 mirror rows; with the column varying across lane groups
   // the column reads of the staged half meet at most a 4-way bank conflict.
-  for (int q = threadIdx.x; q < 256 * 16; q += NT) {
-    const int col = (q >> 2) & 255, r8 = (((q >> 10) << 2) | (q & 3)) * 8;
-    float v[8];
+  {
+    constexpr int CPI = NT / 4, NC = 256 / CPI;  // columns per iteration, iterations per 32 rows
+    const int c0 = threadIdx.x >> 2, r0 = (threadIdx.x & 3) * 8;
+    const float *src = ep + r0 * EP_LD + c0;
+    uint16_t *d = dst + (int64_t)(n0 + c0) * hp + m0 + half * 128 + r0;
+#pragma unroll 8
+    for (int it = 0; it < 4 * NC; it++) {
+      const int dc = CPI * (it % NC), dr = 32 * (it / NC);
+      float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; e++) v[e] = f(ep[(r8 + e) * EP_LD + col], r8 + e, col);
-    uint4 o;
-    o.x = pack_bf16x2(v[0], v[1]);
-    o.y = pack_bf16x2(v[2], v[3]);
-    o.z = pack_bf16x2(v[4], v[5]);
-    o.w = pack_bf16x2(v[6], v[7]);
-    *(uint4 *)(dst + (int64_t)(n0 + col) * hp + m0 + half * 128 + r8) = o;
+      for (int e = 0; e < 8; e++) v[e] = f(src[(dr + e) * EP_LD + dc], r0 + dr + e, c0 + dc);
+      uint4 o;
+      o.x = pack_bf16x2(v[0], v[1]);
+      o.y = pack_bf16x2(v[2], v[3]);
+      o.z = pack_bf16x2(v[4], v[5]);
+      o.w = pack_bf16x2(v[6], v[7]);
+      *(uint4 *)(d + (int64_t)uni(dc) * hp + dr) = o;
+    }
   }
 }
 
