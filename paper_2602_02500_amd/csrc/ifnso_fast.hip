@@ -973,43 +973,41 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
       // Y[i][n] = sum_k P[i][k] M^T[n][k]
       mainloop<false, false>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
-    const uint16_t *M = (const uint16_t *)P.M;
+    // each thread owns one 8-column chunk of RS rows apart; row offsets are uniform additions
+    constexpr int RS = NT / 32, PER = 128 / RS;
+    const int row0 = threadIdx.x >> 5, c8 = (threadIdx.x & 31) * 8;
+    const int c = n0 + c8;
+    const bool cin = c < cols_out;
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
-      constexpr int PER = 128 * 32 / NT, BATCH = 8;
-      for (int b0 = 0; b0 < PER; b0 += BATCH) {
-        uint4 xm[BATCH];
+      const int r0 = m0 + half * 128 + row0;
+      const uint16_t *mp = (const uint16_t *)P.M + (int64_t)r0 * P.ldm + c;
+      const float *src = ep + row0 * EP_LD + c8;
+      uint4 xm[PER];
 #pragma unroll
-        for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + NT * (b0 + u);
-          const int row = q >> 5, c8 = (q & 31) * 8;
-          const int r = m0 + half * 128 + row, c = n0 + c8;
-          xm[u] = (r < rows_out && c < cols_out) ? *(const uint4 *)(M + (int64_t)r * P.ldm + c) : make_uint4(0, 0, 0, 0);
+      for (int u = 0; u < PER; u++)
+        xm[u] = (cin && r0 + u * RS < rows_out) ? *(const uint4 *)(mp + (int64_t)uni(u * RS) * P.ldm)
+                                                 : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        if (!cin || r0 + u * RS >= rows_out) continue;
+        const float *sp = src + u * RS * EP_LD;
+        const uint32_t xw[4] = {xm[u].x, xm[u].y, xm[u].z, xm[u].w};
+        float y[8];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          y[2 * e] = sc0 * __uint_as_float(xw[e] << 16) + sps * sp[2 * e];
+          y[2 * e + 1] = sc0 * __uint_as_float(xw[e] & 0xffff0000u) + sps * sp[2 * e + 1];
         }
-#pragma unroll
-        for (int u = 0; u < BATCH; u++) {
-          const int q = threadIdx.x + NT * (b0 + u);
-          const int row = q >> 5, c8 = (q & 31) * 8;
-          const int r = m0 + half * 128 + row, c = n0 + c8;
-          if (r >= rows_out || c >= cols_out) continue;
-          const float *src = ep + row * EP_LD + c8;
-          const uint32_t xw[4] = {xm[u].x, xm[u].y, xm[u].z, xm[u].w};
-          float y[8];
-#pragma unroll
-          for (int e = 0; e < 4; e++) {
-            y[2 * e] = sc0 * __uint_as_float(xw[e] << 16) + sps * src[2 * e];
-            y[2 * e + 1] = sc0 * __uint_as_float(xw[e] & 0xffff0000u) + sps * src[2 * e + 1];
-          }
-          if (out_bf16) {
-            uint4 o = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]), pack_bf16x2(y[4], y[5]),
-                                 pack_bf16x2(y[6], y[7]));
-            *(uint4 *)((uint16_t *)P.Y + (int64_t)r * P.ldy + c) = o;
-          } else {
-            float *yp = (float *)P.Y + (int64_t)r * P.ldy + c;
-            *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
-            *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
-          }
+        const int64_t yo = (int64_t)(r0 + u * RS) * P.ldy + c;
+        if (out_bf16) {
+          *(uint4 *)((uint16_t *)P.Y + yo) = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]),
+                                                        pack_bf16x2(y[4], y[5]), pack_bf16x2(y[6], y[7]));
+        } else {
+          float *yp = (float *)P.Y + yo;
+          *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
+          *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
         }
       }
       __syncthreads();
