@@ -8,8 +8,9 @@
 // product) are first copied transposed by a memory-bound pass. Operands go straight from
 // HBM into LDS (buffer_load ... lds, 16 bytes per lane); the XOR swizzle of the LDS rows is
 // applied on the global side, since a wave's LDS-DMA writes land contiguously. Two LDS
-// stages of 64 (bfloat16) or 128 (e4m3) K per row; each of the 4 waves owns a 128 x 128 block
-// of the tile (v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x64_f8f6f4, 256 AGPR accumulators).
+// stages of 64 (bfloat16) or 128 (e4m3) K per row; each of the 8 waves (2 x 4, two per SIMD) owns
+// a 128 x 64 block of the tile (v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x64_f8f6f4, 128
+// float32 accumulators per lane).
 // Epilogues stage the float32 tile through LDS (half a tile at a time) so that stores of
 // the tile and of its mirror are 16-byte vector accesses.
 #include <hip/hip_runtime.h>
@@ -182,15 +183,17 @@ __device__ __forceinline__ void issue_krows(const KRows<ROWS> &R, uint32_t lt, c
 }
 
 // Both operands K-major: one barrier per K step. The loads of step k+1 go into the other LDS
-// stage while step k's MFMAs run (a quarter of them (bf16) or half (e4m3) before each K slice);
-// that stage was last read in step k-1, which every wave finished before this step's barrier.
+// stage while step k's MFMAs run, half of them before each of the step's first two K slices (so
+// the later half still has half a step to land before the next barrier); that stage was last
+// read in step k-1, which every wave finished before this step's barrier. bfloat16 fragments are
+// double-buffered: slice kk+1's are read from LDS while slice kk's MFMAs run.
 template <bool F8>
 __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                               const Operand &B, int bn0, int K, bool want_norm) {
   constexpr int ES = F8 ? 1 : 2;
   constexpr int KST = 128 / ES;           // elements per stage
   constexpr int NS = F8 ? 2 : BK / 16;    // MFMA K slices per stage
-  constexpr int PER = RPT / NS;           // rows of each operand issued per slice
+  constexpr int PER = RPT / 2;            // rows of each operand issued in each of the first two slices
   const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
   const int wm = wave / WGN, wn = wave % WGN;
   const int lr = lane & 31, lg = lane >> 5;
@@ -227,9 +230,11 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
     const uint32_t An = lbase + (cur ^ 1) * STAGE_BYTES, Bn = An + BM * 128;
     auto issue_slice = [&](auto sl) {
       constexpr int s = decltype(sl)::value;
-      if (more) {
-        issue_krows<BM, ES, s * PER, (s + 1) * PER>(RA, An, A.w, k1, K, full, wave);
-        issue_krows<BN, ES, s * PER, (s + 1) * PER>(RB, Bn, B.w, k1, K, full, wave);
+      if constexpr (s < 2) {
+        if (more) {
+          issue_krows<BM, ES, s * PER, (s + 1) * PER>(RA, An, A.w, k1, K, full, wave);
+          issue_krows<BN, ES, s * PER, (s + 1) * PER>(RB, Bn, B.w, k1, K, full, wave);
+        }
       }
     };
     if constexpr (F8) {
@@ -260,7 +265,6 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
       slice(std::integral_constant<int, 0>{});
       slice(std::integral_constant<int, 1>{});
     } else {
-      // fragments of K slice kk+1 are read from LDS while slice kk's 16 MFMAs run
       bf16x8 fa[2][FM], fb[2][FN];
       auto rd = [&](int kk, int sl) {
 #pragma unroll
@@ -270,19 +274,8 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
       };
       auto slice = [&](auto slc) {
         constexpr int kk = decltype(slc)::value;
-        constexpr int sl = NW == 8 ? 0 : (kk & 1);
+        constexpr int sl = kk & 1;
         issue_slice(slc);
-        if constexpr (NW == 8) {
-          // two waves per SIMD: the other wave's MFMAs cover this slice's LDS latency, so one
-          // fragment set suffices (the register budget is 256 per wave)
-          rd(kk, 0);
-#pragma unroll
-          for (int i = 0; i < FM; i++)
-#pragma unroll
-            for (int j = 0; j < FN; j++)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][i], fb[0][j], acc[i][j], 0, 0, 0);
-          return;
-        }
         if constexpr (kk + 1 < NS) rd(kk + 1, sl ^ 1);
 #pragma unroll
         for (int i = 0; i < FM; i++)
@@ -297,7 +290,7 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
           }
         }
       };
-      if constexpr (NW != 8) rd(0, 0);
+      rd(0, 0);
       slice(std::integral_constant<int, 0>{});
       slice(std::integral_constant<int, 1>{});
       slice(std::integral_constant<int, 2>{});
