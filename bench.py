@@ -96,6 +96,30 @@ def stage_flops(shapes, J):
     return {"gram": float(g), "square": float(s), "product": float(p), "step": float(g + J * s + p)}
 
 
+# kernel of a bench launch name -> its name in the rocprofv3 traffic summary
+PROFILE_KERNEL = {"square": "kf_square<true, false>", "gram_wide": "kf_gram", "gram_tall": "kf_gram",
+                  "product_wide": "kf_product<false>", "product_tall": "kf_product<true>",
+                  "aggregate": "kf_aggregate", "transpose": "kf_transpose"}
+
+
+def measured_traffic(kernel, summary):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (calibrated against a plain copy of known size), or None when the summary is missing, lacks
+    the kernel, or was taken on a different revision of the kernel source."""
+    import hashlib
+    try:
+        with open(summary) as f:
+            prof = json.load(f)
+        with open(os.path.join(ROOT, prof["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != prof["source_sha256"]:
+                return None
+        k = prof["kernels"][PROFILE_KERNEL[kernel]]
+    except (OSError, KeyError, ValueError):
+        return None
+    return {"bytes": k["read_bytes"] + k["write_bytes"], "read": k["read_bytes"], "write": k["write_bytes"],
+            "source": os.path.relpath(summary, ROOT)}
+
+
 def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
     """The FP64 oracle on a bounded sample (layer 0: its 7 matrices), on the host cores."""
     import numpy as np
@@ -503,6 +527,11 @@ def main():
                      "avg_launch_ms": round(dur_ms, 3)},
         "cpu_baseline": cpu,
     }
+    tr = measured_traffic(dom, os.path.join(ROOT, "profiles", "traffic_gradset_224_bf16.json")) \
+        if args.layers == 32 else None
+    if tr is not None:
+        line["roofline"].update({"traffic": round(tr["bytes"]), "traffic_read": round(tr["read"]),
+                                 "traffic_write": round(tr["write"]), "traffic_source": tr["source"]})
     line.update(extra)
     print(json.dumps(line), flush=True)
 
