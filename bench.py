@@ -97,7 +97,7 @@ def stage_flops(shapes, J):
 
 
 # kernel of a bench launch name -> its name in the rocprofv3 traffic summary
-PROFILE_KERNEL = {"square": "kf_square<true, false>", "gram_wide": "kf_gram", "gram_tall": "kf_gram",
+PROFILE_KERNEL = {"square": "kf_square<true>", "gram_wide": "kf_gram", "gram_tall": "kf_gram",
                   "product_wide": "kf_product<false>", "product_tall": "kf_product<true>",
                   "aggregate": "kf_aggregate", "transpose": "kf_transpose"}
 

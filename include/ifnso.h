@@ -153,15 +153,13 @@ ifnso_status ifnso_plan_launch_info(ifnso_plan_t plan, int32_t i, int32_t *stage
  * ordered in panel-sharing blocks of block_rows x block_cols tiles; with xcd_sched, groups of
  * `group` consecutive tiles are dealt to the 8 XCDs in turn (workgroup b runs on XCD b % 8, so
  * tiles that share operand panels meet in one XCD's L2), and each XCD runs wg_per_xcd
- * workgroups. variant (squaring only): 1 selects the mainloop that overlaps the K-step
- * boundary with the last slice's MFMAs. Defaults: 1, 32, 4, 8, 32, 1 (squaring) / 0. */
+ * workgroups. Defaults: 1, 32, 4, 8, 32. */
 typedef struct {
   int32_t xcd_sched;   /* 0 or 1 */
   int32_t group;       /* 1..4096 */
   int32_t block_rows;  /* 1..64 */
   int32_t block_cols;  /* 1..64 */
   int32_t wg_per_xcd;  /* 1..1024 (capped at the XCD's CU count) */
-  int32_t variant;     /* 0 or 1 */
 } ifnso_stage_config;
 
 /* Reads / replaces the schedule of stage 0 (Gram), 1 (squaring) or 2 (product). Setting a

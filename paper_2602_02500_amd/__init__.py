@@ -51,7 +51,7 @@ STAGE_GRAM, STAGE_SQUARE, STAGE_PRODUCT = 0, 1, 2
 class StageConfig(ctypes.Structure):
     """Schedule of a 256-tile stage (see ifnso_stage_config)."""
     _fields_ = [("xcd_sched", ctypes.c_int32), ("group", ctypes.c_int32), ("block_rows", ctypes.c_int32),
-                ("block_cols", ctypes.c_int32), ("wg_per_xcd", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("block_cols", ctypes.c_int32), ("wg_per_xcd", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -81,7 +81,6 @@ struct StageArgs {
   int32_t xcd_off[8];
   int32_t xcd_cnt[8];
   int32_t wg_per_xcd;  // host only: workgroups per XCD of a fast launch
-  int32_t variant;     // fast squaring: 1 selects the mainloop that overlaps the step boundary
   ProbDev one;         // the problem of a single-problem launch
 };
 

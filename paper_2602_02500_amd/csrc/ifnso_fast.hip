@@ -28,13 +28,10 @@ namespace fast {
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int BM = 256, BN = 256, BK = 64;
-#ifndef IFNSO_FAST_WAVES
-#define IFNSO_FAST_WAVES 8
-#endif
 // Waves per workgroup: 8 in a 2 x 4 arrangement (two waves per SIMD, so one wave's LDS reads,
 // address arithmetic and waits overlap the other's MFMAs), each owning a 128 x 64 block of the
-// tile; 4 (2 x 2, 128 x 128 per wave) also builds.
-constexpr int NW = IFNSO_FAST_WAVES;
+// tile.
+constexpr int NW = 8;
 constexpr int NT = NW * 64;                     // threads per workgroup
 constexpr int WGN = NW / 2;                     // waves along N
 constexpr int WM = 128, WN = BN / WGN, FM = WM / 32, FN = WN / 32;
@@ -301,104 +298,13 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   return nrm;
 }
 
-// bfloat16, both operands K-major. Per K step (4 slices of 16): the fragments of slice s+1 are
-// read from LDS ahead of slice s's 16 MFMAs. After slice 2 each wave holds slice 3's fragments,
-// waits for its share of the next stage's loads and meets the others at the step's one barrier;
-// past it, stage k's buffer is free and stage k+1 is complete, so the loads of stage k+2 go into
-// stage k's buffer and the fragments of stage k+1's first slice are read while slice 3's MFMAs
-// run (the LDS latency at a step boundary is hidden behind them).
-__device__ __forceinline__ double mainloop_bf16(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
-                                                const Operand &B, int bn0, int K, bool want_norm) {
-  constexpr int ES = 2, KST = 64;
-  const int lane = threadIdx.x & 63, wave = uni((int)(threadIdx.x >> 6));
-  const int wm = wave / WGN, wn = wave % WGN;
-  const int lr = lane & 31, lg = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < FM; i++)
-#pragma unroll
-    for (int j = 0; j < FN; j++)
-#pragma unroll
-      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-  const int nk = (K + KST - 1) / KST;
-  if (nk <= 0) return 0.0;
-  double nrm = 0.0;
-  KRows<BM> RA;
-  KRows<BN> RB;
-  krows<BM>(RA, A.ld_bytes, am0, A.lim);
-  krows<BN>(RB, B.ld_bytes, bn0, B.lim);
-  const uint32_t lbase = uni(lds_addr(smem));
-  auto issue_stage = [&](int st) {
-    const uint32_t As = lbase + (st & 1) * STAGE_BYTES;
-    const int k0 = st * KST;
-    const bool full = k0 + KST <= K;
-    issue_krows<BM, ES, 0, RPT>(RA, As, A.w, k0, K, full, wave);
-    issue_krows<BN, ES, 0, RPT>(RB, As + BM * 128, B.w, k0, K, full, wave);
-  };
-  bf16x8 fa[2][FM], fb[2][FN];
-  auto rd = [&](const char *As, int kk, int sl) {
-    const char *Bs = As + BM * 128;
-#pragma unroll
-    for (int i = 0; i < FM; i++) fa[sl][i] = *(const bf16x8 *)(As + lds_off(wm * WM + i * 32 + lr, 2 * kk + lg));
-#pragma unroll
-    for (int j = 0; j < FN; j++) fb[sl][j] = *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
-  };
-  auto mfma = [&](int sl) {
-#pragma unroll
-    for (int i = 0; i < FM; i++)
-#pragma unroll
-      for (int j = 0; j < FN; j++)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][i], fb[sl][j], acc[i][j], 0, 0, 0);
-  };
-  // LDS reads of the next slice ahead of this slice's MFMAs
-  auto order = [&]() {
-    __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
-  };
-  issue_stage(0);
-  if (nk > 1) {
-    issue_stage(1);
-    wait_vmcnt<2 * RPT>();
-  } else {
-    wait_vmcnt<0>();
-  }
-  __syncthreads();
-  if (want_norm) nrm += lds_sumsq(smem);
-  rd(smem, 0, 0);
-  for (int kt = 0; kt < nk; kt++) {
-    const char *As = smem + (kt & 1) * STAGE_BYTES;
-    rd(As, 1, 1);
-    mfma(0);
-    order();
-    rd(As, 2, 0);
-    mfma(1);
-    order();
-    rd(As, 3, 1);
-    mfma(0);
-    order();
-    wait_vmcnt<0>();
-    __syncthreads();
-    if (kt + 1 < nk) {
-      const char *Nx = smem + ((kt + 1) & 1) * STAGE_BYTES;
-      if (want_norm) nrm += lds_sumsq(Nx);
-      rd(Nx, 0, 0);
-      if (kt + 2 < nk) issue_stage(kt + 2);
-    }
-    mfma(1);
-  }
-  __syncthreads();  // the epilogue reuses the LDS stages
-  return nrm;
-}
-
 // acc = Aop[am0.., :K] * Bop[bn0.., :K]^T with both operands K-contiguous; F8: OCP e4m3
 // operands (1 byte, 128 per LDS row and stage), MFMA 32x32x64.
-// OV: the bfloat16 schedule that overlaps the step boundary (mainloop_bf16); it needs more
-// registers, so kernels whose epilogues keep more state use the simpler schedule.
-template <bool AMN, bool BMN, bool F8 = false, bool OV = false>
+template <bool AMN, bool BMN, bool F8 = false>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                            const Operand &B, int bn0, int K, bool want_norm) {
   static_assert(!AMN && !BMN, "operands are K-contiguous (tall inputs and wide products use M^T copies)");
-  if constexpr (OV && !F8 && NW == 4) return mainloop_bf16(acc, smem, A, am0, B, bn0, K, want_norm);
-  else return mainloop_kk<F8>(acc, smem, A, am0, B, bn0, K, want_norm);
+  return mainloop_kk<F8>(acc, smem, A, am0, B, bn0, K, want_norm);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -736,7 +642,7 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
-template <bool AGG, bool OV = AGG>
+template <bool AGG>
 __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -774,7 +680,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
                            : (const void *)P.opnd[(level - 1) & 1];
     const Operand op = make_operand(srcp, bytes, (uint32_t)(hp * 2), P.hp);
     f32x16 acc[FM][FN];
-    mainloop<false, false, false, OV>(acc, smem, op, m0, op, n0, uni(P.h), false);
+    mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
     uint16_t *dst = AGG ? (uint16_t *)((char *)P.lv + (int64_t)level * P.lv_stride) : (uint16_t *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
@@ -1130,9 +1036,8 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
   if (stage == kStageGram) {
     hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(fast::NT), 0, s, a);
   } else if (stage == kStageSquare) {
-    if (a.agg && a.variant) hipLaunchKernelGGL((fast::kf_square<true, true>), dim3(grid), dim3(fast::NT), 0, s, a);
-    else if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
-    else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
+    if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(fast::NT), 0, s, a);
+    else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(fast::NT), 0, s, a);
   } else {
     if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
     else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
@@ -1149,7 +1054,7 @@ hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
   const void *fn = stage == kStageGram ? (const void *)fast::kf_gram
-                 : stage == kStageSquare ? (const void *)fast::kf_square<true, true> : (const void *)fast::kf_product<false>;
+                 : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, fast::NT, 0);
 }
 

@@ -302,7 +302,6 @@ static ifnso_stage_config default_config(int stage) {
   c.block_rows = 4;
   c.block_cols = 8;
   c.wg_per_xcd = 32;
-  c.variant = stage == kStageSquare ? 1 : 0;
   return c;
 }
 
@@ -651,7 +650,6 @@ static bool use_xcd_sched();
 static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds], const ifnso_stage_config &c) {
   a.xcd_sched = (use_xcd_sched() && c.xcd_sched) ? 1 : 0;
   a.wg_per_xcd = c.wg_per_xcd;
-  a.variant = c.variant;
   for (int x = 0; x < kXcds; x++) {
     a.xcd_off[x] = off[x];
     a.xcd_cnt[x] = cnt[x];
@@ -663,7 +661,6 @@ static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds], co
 // Launch parameters of a stage's config that apply to single-problem calls too.
 static void apply_cfg(StageArgs &a, const ifnso_stage_config &c) {
   a.wg_per_xcd = c.wg_per_xcd;
-  a.variant = c.variant;
 }
 
 static int fast_grid(const StageArgs &a, int cus) {
@@ -936,8 +933,7 @@ extern "C" ifnso_status ifnso_plan_set_config(ifnso_plan_t p, int32_t stage, con
   if (stage < kStageGram || stage > kStageProduct) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad stage %d", stage);
   const ifnso_stage_config &c = *cfg;
   if ((c.xcd_sched != 0 && c.xcd_sched != 1) || c.group < 1 || c.group > 4096 || c.block_rows < 1 ||
-      c.block_rows > 64 || c.block_cols < 1 || c.block_cols > 64 || c.wg_per_xcd < 1 || c.wg_per_xcd > 1024 ||
-      c.variant < 0 || c.variant > 1)
+      c.block_rows > 64 || c.block_cols < 1 || c.block_cols > 64 || c.wg_per_xcd < 1 || c.wg_per_xcd > 1024)
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "stage config out of range");
   std::lock_guard<std::mutex> lock(p->mu);
   int prev = 0;

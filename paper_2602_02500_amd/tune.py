@@ -1,5 +1,5 @@
 """Autotuner of the 256-tile schedules: per stage (Gram, squaring, product) it times candidate
-schedules (tile order blocks, XCD queue groups, grid, mainloop variant) on the caller's real
+schedules (tile order blocks, XCD queue groups, grid) on the caller's real
 inputs, keeps the fastest, and caches the choice in a JSON file keyed by device and plan.
 
 Timing uses the library's per-launch-slot events: a call records an event before every slot, so
@@ -21,15 +21,13 @@ STAGES = {"gram": STAGE_GRAM, "square": STAGE_SQUARE, "product": STAGE_PRODUCT}
 
 
 def candidates(stage: int) -> List[dict]:
-    """Schedules tried for a stage: XCD queues with three group sizes and four block shapes,
-    plain striding, and (squaring) both mainloop variants."""
+    """Schedules tried for a stage: XCD queues with three group sizes and four block shapes, and
+    plain striding. The same list serves every stage."""
     out = []
-    variants = (1, 0) if stage == STAGE_SQUARE else (0,)
-    for v in variants:
-        for group in (16, 32, 64):
-            for br, bc in ((4, 8), (8, 8), (2, 16), (8, 4)):
-                out.append(dict(xcd_sched=1, group=group, block_rows=br, block_cols=bc, wg_per_xcd=32, variant=v))
-        out.append(dict(xcd_sched=0, group=32, block_rows=4, block_cols=8, wg_per_xcd=32, variant=v))
+    for group in (16, 32, 64):
+        for br, bc in ((4, 8), (8, 8), (2, 16), (8, 4)):
+            out.append(dict(xcd_sched=1, group=group, block_rows=br, block_cols=bc, wg_per_xcd=32))
+    out.append(dict(xcd_sched=0, group=32, block_rows=4, block_cols=8, wg_per_xcd=32))
     return out
 
 

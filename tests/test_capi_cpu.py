@@ -162,6 +162,6 @@ def test_workspace_sizes_grow_with_shape(L):
 
 
 def test_stage_config_argument_checks(L):
-    c = ifn.StageConfig(1, 32, 4, 8, 32, 0)
+    c = ifn.StageConfig(1, 32, 4, 8, 32)
     assert L.ifnso_plan_get_config(None, 0, ctypes.byref(c)) == 1
     assert L.ifnso_plan_set_config(None, 0, ctypes.byref(c)) == 1

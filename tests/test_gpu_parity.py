@@ -334,7 +334,7 @@ def test_launch_events_and_info(torch_dev):
 
 
 def test_schedule_configs_leave_results_bitwise(torch_dev):
-    """Every 256-tile schedule (tile order, XCD queues, grid, mainloop variant) computes each tile
+    """Every 256-tile schedule (tile order, XCD queues, grid) computes each tile
     the same way, so outputs are bitwise equal; the tuner picks one of them."""
     torch, dev = torch_dev
     import paper_2602_02500_amd as ifn
@@ -366,5 +366,4 @@ def test_schedule_configs_leave_results_bitwise(torch_dev):
     out = run()
     assert all(np.array_equal(a, b) for a, b in zip(out, ref))
     with pytest.raises(ifn.IfnsoError):
-        plan.set_config(ifn.STAGE_GRAM, dict(xcd_sched=2, group=32, block_rows=4, block_cols=8, wg_per_xcd=32,
-                                             variant=0))
+        plan.set_config(ifn.STAGE_GRAM, dict(xcd_sched=2, group=32, block_rows=4, block_cols=8, wg_per_xcd=32))
