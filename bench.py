@@ -97,9 +97,9 @@ def stage_flops(shapes, J):
 
 
 # kernel of a bench launch name -> its name in the rocprofv3 traffic summary
-PROFILE_KERNEL = {"square": "kf_square<true>", "gram_wide": "kf_gram", "gram_tall": "kf_gram",
+PROFILE_KERNEL = {"square": "kf_square<true>", "gram_wide": "kf_gram<false>", "gram_tall": "kf_gram<true>",
                   "product_wide": "kf_product<false>", "product_tall": "kf_product<true>",
-                  "aggregate": "kf_aggregate", "transpose": "kf_transpose"}
+                  "aggregate": "kf_aggregate"}
 
 
 def measured_traffic(kernel, summary):
@@ -450,7 +450,7 @@ def main():
     J = nl - 6
     fl = stage_flops(shapes, J)
     # kernel of each launch slot (squaring levels share one kernel)
-    names = ["transpose"] + ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
+    names = ["prep"] + ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
 
     t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
     kern, elapsed, graph_ms = t["kern"], t["elapsed"], t["graph_ms"]

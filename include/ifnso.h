@@ -131,9 +131,9 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
                                          void *const *Y, const int64_t *ldy, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
-/* Launch slots of one call of this plan, in order: preparation (transposed copies of the inputs
- * for the bf16/e4m3 256-tile kernels; in FP8_E4M3 plans also the pre-pass (||A||_F and amax)
- * with the e4m3 quantisation of A), Gram for the problems with rows <= cols, Gram for the
+/* Launch slots of one call of this plan, in order: preparation (in FP8_E4M3 plans the pre-pass
+ * (||A||_F and amax) with the e4m3 quantisation of A; empty in other plans), Gram for the
+ * problems with rows <= cols, Gram for the
  * transposed (rows > cols) problems, one squaring per level (in FP8_E4M3 plans with the
  * quantisation of the power it squares), the aggregation of the weighted powers, then the
  * product for the two groups in the same order: J + 6 slots where 2^J is the largest exponent.

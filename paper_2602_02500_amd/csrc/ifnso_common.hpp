@@ -46,11 +46,6 @@ struct ProbDev {
   float *q_scale;      // [2 (kMaxLevels + 1)]: [2l] scale (a power of two), [2l + 1] max |value|;
                        //   l = 0 the input, l >= 1 level l
   int32_t nq, rq;
-  // 256-tile kernels: M^T (cols x rows of M, leading dimension ldxt, zero beyond rows), so that
-  // the tall Gram (A = M^T) and the wide product (contraction over the rows of M) read
-  // K-contiguous operands
-  void *xt;
-  int64_t ldxt;
 };
 
 // One tile of work: problem index, tile row, tile column, stage-specific flags.

@@ -4,10 +4,11 @@
 // offset past the descriptor's record count and reads as zero, so edge tiles need no
 // branches (the host routes a problem here only when its rows are 16-byte aligned and its
 // column count is a multiple of 8, so every 16-byte chunk is wholly in or out of range).
-// Every GEMM operand is K-contiguous: tall inputs (for the Gram) and wide inputs (for the
-// product) are first copied transposed by a memory-bound pass. Operands go straight from
-// HBM into LDS (buffer_load ... lds, 16 bytes per lane); the XOR swizzle of the LDS rows is
-// applied on the global side, since a wave's LDS-DMA writes land contiguously. Two LDS
+// Operands go straight from HBM into LDS (buffer_load ... lds, 16 bytes per lane); the XOR
+// swizzle of the LDS rows is applied on the global side, since a wave's LDS-DMA writes land
+// contiguously. An operand is K-major (levels, wide Gram inputs, tall product inputs) or
+// MN-major (tall Gram inputs, wide product inputs: M read as stored, its rows running along
+// K); MN-major fragments come from transposing LDS reads, so no input is copied. Two LDS
 // stages of 64 (bfloat16) or 128 (e4m3) K per row; each of the 8 waves (2 x 4, two per SIMD) owns
 // a 128 x 64 block of the tile (v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x64_f8f6f4, 128
 // float32 accumulators per lane).
@@ -153,30 +154,74 @@ __device__ __forceinline__ void krows(KRows<ROWS> &R, uint32_t ld_bytes, int m0,
   }
 }
 
+// MN-major operand tile (bfloat16): a stage holds 64 K rows of the tile's 256 MN-contiguous
+// values, 512 bytes per LDS row. Wave-instruction g covers LDS rows 2g and 2g+1; lane l loads
+// LDS chunk p = l % 32 of row 2g + l / 32 from the operand's chunk p ^ mswz(row). Chunk offsets
+// of the rows differ by multiples of 4, so the transposing fragment reads (four rows of four
+// chunks per 16 lanes) meet no bank conflict. The per-tile offset is that of K row `row` (k0 = 0);
+// a K step adds k0 * ld_bytes.
+__device__ __forceinline__ int mswz(int row) { return (row & 3) << 2; }
+
+template <int ROWS>
+__device__ __forceinline__ void krows_mn(KRows<ROWS> &R, uint32_t ld_bytes, int mn0, int mnlim) {
+  const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < ROWS / (8 * NW); i++) {
+    const int row = 2 * (i * NW + wave) + (lane >> 5);
+    const int mn = mn0 + 8 * ((lane & 31) ^ mswz(row));
+    R.off[i] = mn < mnlim ? (uint32_t)row * ld_bytes + (uint32_t)mn * 2u : OOB;
+  }
+}
+
 // Loads rows [I0, I1) of the thread's rows of stage k0 into the LDS tile at lt. `full`: the
-// whole stage lies below K (otherwise chunks at or beyond K read as zero).
-template <int ROWS, int ES, int I0, int I1, bool FULL>
+// whole stage lies below K (otherwise chunks (K-major) or rows (MN-major) at or beyond K read
+// as zero).
+template <int ROWS, int ES, int I0, int I1, bool FULL, bool MN>
 __device__ __forceinline__ void issue_krows_(const KRows<ROWS> &R, uint32_t lt, const i32x4 &r, int k0, int K,
-                                             int wave) {
+                                             uint32_t ld_bytes, int wave) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = I0; i < I1; i++) {
     const int g = i * NW + wave;
-    uint32_t off = R.off[i] + (uint32_t)(k0 * ES);
+    uint32_t off = R.off[i] + (MN ? (uint32_t)k0 * ld_bytes : (uint32_t)(k0 * ES));
     if constexpr (!FULL) {
-      const int row = g * 8 + (lane >> 3);
-      const int c = (lane & 7) ^ swz(row);
-      if (k0 + c * (16 / ES) >= K) off = OOB;
+      if constexpr (MN) {
+        if (k0 + 2 * g + (lane >> 5) >= K) off = OOB;
+      } else {
+        const int row = g * 8 + (lane >> 3);
+        const int c = (lane & 7) ^ swz(row);
+        if (k0 + c * (16 / ES) >= K) off = OOB;
+      }
     }
     dma16(r, off, lt + g * 1024);
   }
 }
 
-template <int ROWS, int ES, int I0, int I1>
+template <int ROWS, int ES, int I0, int I1, bool MN = false>
 __device__ __forceinline__ void issue_krows(const KRows<ROWS> &R, uint32_t lt, const i32x4 &r, int k0, int K,
-                                            bool full, int wave) {
-  if (full) issue_krows_<ROWS, ES, I0, I1, true>(R, lt, r, k0, K, wave);
-  else issue_krows_<ROWS, ES, I0, I1, false>(R, lt, r, k0, K, wave);
+                                            bool full, uint32_t ld_bytes, int wave) {
+  if (full) issue_krows_<ROWS, ES, I0, I1, true, MN>(R, lt, r, k0, K, ld_bytes, wave);
+  else issue_krows_<ROWS, ES, I0, I1, false, MN>(R, lt, r, k0, K, ld_bytes, wave);
+}
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// MFMA fragment (32 MN x 8 K per lane: lane l holds MN index mn_off + l % 32, K 8 (l / 32) ..
+// + 7 of slice kk) of an MN-major stage, by two transposing LDS reads (ds_read_b64_tr_b16). In
+// each group of 16 lanes, lane 4e + q addresses four MN values (4q .. 4q+3) of K row e, and
+// lane j of the group receives value j % 4 of the row addressed by lane 4e + j / 4 as element e:
+// MN index j, K rows 0..3. The second read covers K rows 4..7.
+__device__ __forceinline__ bf16x8 tr_frag(const char *S, int mn_off, int kk) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, q = lane & 15;
+  const int kr = 16 * kk + 8 * (g >> 1) + (q >> 2);
+  const int mn = mn_off + 16 * (g & 1) + 4 * (q & 3);
+  const char *p = S + kr * 512 + (((mn >> 3) ^ mswz(kr)) << 4) + (mn & 7) * 2;
+  const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)p);
+  const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(p + 4 * 512));  // mswz(kr + 4) == mswz(kr)
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
 }
 
 // Both operands K-major: one barrier per K step. The loads of step k+1 go into the other LDS
@@ -184,9 +229,10 @@ __device__ __forceinline__ void issue_krows(const KRows<ROWS> &R, uint32_t lt, c
 // the later half still has half a step to land before the next barrier); that stage was last
 // read in step k-1, which every wave finished before this step's barrier. bfloat16 fragments are
 // double-buffered: slice kk+1's are read from LDS while slice kk's MFMAs run.
-template <bool F8>
+template <bool F8, bool AMN = false, bool BMN = false>
 __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                               const Operand &B, int bn0, int K, bool want_norm) {
+  static_assert(!F8 || (!AMN && !BMN), "e4m3 operands are K-major");
   constexpr int ES = F8 ? 1 : 2;
   constexpr int KST = 128 / ES;           // elements per stage
   constexpr int NS = F8 ? 2 : BK / 16;    // MFMA K slices per stage
@@ -205,13 +251,15 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   double nrm = 0.0;
   KRows<BM> RA;
   KRows<BN> RB;
-  krows<BM>(RA, A.ld_bytes, am0, A.lim);
-  krows<BN>(RB, B.ld_bytes, bn0, B.lim);
+  if constexpr (AMN) krows_mn<BM>(RA, A.ld_bytes, am0, A.lim);
+  else krows<BM>(RA, A.ld_bytes, am0, A.lim);
+  if constexpr (BMN) krows_mn<BN>(RB, B.ld_bytes, bn0, B.lim);
+  else krows<BN>(RB, B.ld_bytes, bn0, B.lim);
   const uint32_t lbase = uni(lds_addr(smem));
   {
     const bool full = KST <= K;
-    issue_krows<BM, ES, 0, RPT>(RA, lbase, A.w, 0, K, full, wave);
-    issue_krows<BN, ES, 0, RPT>(RB, lbase + BM * 128, B.w, 0, K, full, wave);
+    issue_krows<BM, ES, 0, RPT, AMN>(RA, lbase, A.w, 0, K, full, A.ld_bytes, wave);
+    issue_krows<BN, ES, 0, RPT, BMN>(RB, lbase + BM * 128, B.w, 0, K, full, B.ld_bytes, wave);
   }
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
@@ -229,8 +277,8 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
       constexpr int s = decltype(sl)::value;
       if constexpr (s < 2) {
         if (more) {
-          issue_krows<BM, ES, s * PER, (s + 1) * PER>(RA, An, A.w, k1, K, full, wave);
-          issue_krows<BN, ES, s * PER, (s + 1) * PER>(RB, Bn, B.w, k1, K, full, wave);
+          issue_krows<BM, ES, s * PER, (s + 1) * PER, AMN>(RA, An, A.w, k1, K, full, A.ld_bytes, wave);
+          issue_krows<BN, ES, s * PER, (s + 1) * PER, BMN>(RB, Bn, B.w, k1, K, full, B.ld_bytes, wave);
         }
       }
     };
@@ -265,9 +313,13 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
       bf16x8 fa[2][FM], fb[2][FN];
       auto rd = [&](int kk, int sl) {
 #pragma unroll
-        for (int i = 0; i < FM; i++) fa[sl][i] = *(const bf16x8 *)(As + lds_off(wm * WM + i * 32 + lr, 2 * kk + lg));
+        for (int i = 0; i < FM; i++)
+          fa[sl][i] = AMN ? tr_frag(As, wm * WM + i * 32, kk)
+                          : *(const bf16x8 *)(As + lds_off(wm * WM + i * 32 + lr, 2 * kk + lg));
 #pragma unroll
-        for (int j = 0; j < FN; j++) fb[sl][j] = *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
+        for (int j = 0; j < FN; j++)
+          fb[sl][j] = BMN ? tr_frag(Bs, wn * WN + j * 32, kk)
+                          : *(const bf16x8 *)(Bs + lds_off(wn * WN + j * 32 + lr, 2 * kk + lg));
       };
       auto slice = [&](auto slc) {
         constexpr int kk = decltype(slc)::value;
@@ -298,13 +350,14 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   return nrm;
 }
 
-// acc = Aop[am0.., :K] * Bop[bn0.., :K]^T with both operands K-contiguous; F8: OCP e4m3
-// operands (1 byte, 128 per LDS row and stage), MFMA 32x32x64.
+// acc = Aop[am0.., :K] * Bop[bn0.., :K]^T. An operand is K-major (rows am0.. of a row-major
+// array whose rows run along K) or, with AMN / BMN, MN-major (the array's rows run along K and
+// its columns am0.. are the tile's rows: Aop = X^T). F8: OCP e4m3 operands (1 byte, 128 per LDS
+// row and stage, K-major), MFMA 32x32x64.
 template <bool AMN, bool BMN, bool F8 = false>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                            const Operand &B, int bn0, int K, bool want_norm) {
-  static_assert(!AMN && !BMN, "operands are K-contiguous (tall inputs and wide products use M^T copies)");
-  return mainloop_kk<F8>(acc, smem, A, am0, B, bn0, K, want_norm);
+  return mainloop_kk<F8, AMN, BMN>(acc, smem, A, am0, B, bn0, K, want_norm);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -577,6 +630,8 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
 // ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
+// TALL: A = M^T, read MN-major straight from M (K = rows of M); otherwise A = M, K-major.
+template <bool TALL>
 __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -589,14 +644,12 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
     const ProbDev &P = prob(a, task);
     const int m0 = task.tm * BM, n0 = task.tn * BN;
     const bool diag = task.tm == task.tn;
-    // A = M (wide) or the transposed copy M^T (tall): rows of A are K-contiguous either way
-    // (the copy's rows are padded with zeros to ldxt, so they are read whole)
-    const int64_t lda = P.trans ? P.ldxt : P.ldm;
-    const uint32_t abytes = (uint32_t)(P.trans ? (int64_t)P.h * lda * 2 : ((int64_t)P.h - 1) * lda * 2 + (int64_t)P.w * 2);
-    const Operand op = make_operand(P.trans ? P.xt : P.M, abytes, (uint32_t)(lda * 2), P.h);
+    // M is rows x cols with (rows, cols) = (w, h) when tall, (h, w) when wide
+    const uint32_t mbytes = (uint32_t)(((int64_t)(TALL ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(TALL ? P.h : P.w) * 2);
+    const Operand op = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.h);
     const int K = uni(P.w);
     f32x16 acc[FM][FN];
-    double nrm = mainloop<false, false>(acc, smem, op, m0, op, n0, K, diag);
+    double nrm = mainloop<TALL, TALL>(acc, smem, op, m0, op, n0, K, diag);
     uint16_t *dst = (uint16_t *)P.opnd[0];
     const int64_t hp = P.hp;
     const bool keep_f32 = (a.J >= 1 && !a.agg) || a.learned;
@@ -849,11 +902,10 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
     }
     const int64_t hp = P.hp;
     const int m0 = task.tm * BM, n0 = task.tn * BN;
-    // tall: rows of M (w x h, K = h contiguous); wide: rows of M^T (w x h, the transposed copy)
-    const void *rp = TRANS ? P.M : P.xt;
-    const int64_t ldr = TRANS ? P.ldm : P.ldxt;
-    const uint32_t rbytes = (uint32_t)(TRANS ? ((int64_t)P.w - 1) * ldr * 2 + (int64_t)P.h * 2 : (int64_t)P.w * ldr * 2);
-    const Operand Mo = make_operand(rp, rbytes, (uint32_t)(ldr * 2), P.w);
+    // M is rows x cols with (rows, cols) = (w, h) when tall, (h, w) when wide; its w index is
+    // the output tile's row (tall, K-major) or column (wide, MN-major) index either way
+    const uint32_t mbytes = (uint32_t)(((int64_t)(TRANS ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(TRANS ? P.h : P.w) * 2);
+    const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
     const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
     const int Kp = uni(P.h);
     f32x16 acc[FM][FN];
@@ -869,8 +921,8 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
       // Y_out[n][i] = sum_k M[n][k] P[i][k]
       mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
     } else {
-      // Y[i][n] = sum_k P[i][k] M^T[n][k]
-      mainloop<false, false>(acc, smem, Po, m0, Mo, n0, Kp, false);
+      // Y[i][n] = sum_k P[i][k] M[k][n]
+      mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
     // each thread owns one 8-column chunk of RS rows apart; row offsets are uniform additions
     constexpr int RS = NT / 32, PER = 128 / RS;
@@ -914,43 +966,6 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// transposed copy X = M^T (cols x rows, leading dimension ldxt; columns rows..ldxt-1 are zero):
-// 128 x 128 tiles, each thread moves one 8 x 8 block (eight 16-byte loads, an in-register
-// transpose, eight 16-byte stores). Problems come from blockIdx.y.
-// ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void kf_transpose(const StageArgs a, int wide_only) {
-  const ProbDev &P = a.probs ? a.probs[blockIdx.y] : a.one;
-  if (wide_only && P.trans) return;
-  const int rows = P.trans ? P.w : P.h, cols = P.trans ? P.h : P.w;
-  const int tr = (rows + 127) / 128, tc = (cols + 127) / 128;
-  const uint16_t *M = (const uint16_t *)P.M;
-  uint16_t *X = (uint16_t *)P.xt;
-  // wave w covers the 64 x 64 quarter (w & 1, w >> 1) of the tile; lane (rb, cb) = (lane & 7,
-  // lane >> 3), so that each load reads 8 rows of 128 contiguous bytes and each store writes 8
-  // rows of the copy, 128 contiguous bytes each
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rb = (wave & 1) * 8 + (lane & 7), cb = (wave >> 1) * 8 + (lane >> 3);
-  for (int t = blockIdx.x; t < tr * tc; t += gridDim.x) {
-    const int r0 = (t / tc) * 128 + rb * 8, c0 = (t % tc) * 128 + cb * 8;
-    if (c0 >= cols) continue;  // cols is a multiple of 8: a block is wholly in or out
-    uint4 v[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++)
-      v[i] = r0 + i < rows ? *(const uint4 *)(M + (int64_t)(r0 + i) * P.ldm + c0) : make_uint4(0, 0, 0, 0);
-    if (r0 >= P.ldxt) continue;
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      uint32_t o[4];
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const uint32_t x = w32(v[2 * e], j >> 1), y = w32(v[2 * e + 1], j >> 1);
-        o[e] = (j & 1) ? ((x >> 16) | (y & 0xffff0000u)) : ((x & 0xffffu) | (y << 16));
-      }
-      *(uint4 *)(X + (int64_t)(c0 + j) * P.ldxt + r0) = make_uint4(o[0], o[1], o[2], o[3]);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------------------------
 // aggregate: P = sum_{l=1}^{J+1} c_l S_l B_l (level layout); P overwrites level 1 in place
@@ -1019,11 +1034,6 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
 
 }  // namespace fast
 
-hipError_t launch_transpose(const StageArgs &a, int nprob, int per_problem, int wide_only, hipStream_t s) {
-  if (nprob <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fast::kf_transpose, dim3(per_problem, nprob), dim3(kThreads), 0, s, a, wide_only);
-  return hipGetLastError();
-}
 
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
@@ -1034,7 +1044,8 @@ hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   if (stage == kStageGram) {
-    hipLaunchKernelGGL(fast::kf_gram, dim3(grid), dim3(fast::NT), 0, s, a);
+    if (trans) hipLaunchKernelGGL(fast::kf_gram<true>, dim3(grid), dim3(fast::NT), 0, s, a);
+    else hipLaunchKernelGGL(fast::kf_gram<false>, dim3(grid), dim3(fast::NT), 0, s, a);
   } else if (stage == kStageSquare) {
     if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(fast::NT), 0, s, a);
     else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(fast::NT), 0, s, a);
@@ -1053,7 +1064,7 @@ hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t
 }
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
-  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram
+  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false>
                  : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, fast::NT, 0);
 }

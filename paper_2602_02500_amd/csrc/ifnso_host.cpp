@@ -61,8 +61,6 @@ struct ProbLayout {
   // e4m3 compute
   size_t off_q8, off_qpart, off_qamax, off_amaxp, off_qscale;
   int64_t ldq;
-  size_t off_xt;  // 256-tile plans: M^T, cols x ldxt
-  int64_t ldxt;
   int32_t nq, rq;
   size_t bytes;
 };
@@ -79,7 +77,7 @@ void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
 // Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
 // float32 D ping-pong; classical NS adds two h x w iterates.
 ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
-                          bool e4m3 = false, bool xt = false) {
+                          bool e4m3 = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -120,10 +118,6 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.ldx = round_up(L.w, 8);
     L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
     L.off_xbuf[1] = take((size_t)L.h * L.ldx * op_size(op));
-  }
-  if (xt) {
-    L.ldxt = round_up(rows, 8);
-    L.off_xt = take((size_t)cols * L.ldxt * 2);
   }
   if (e4m3) {
     // one e4m3 buffer: A (h x ldq) for the Gram, then each level (hp x hp) for its squaring
@@ -168,10 +162,6 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
   d.ldx = L.ldx;
   d.lv = L.lv_stride ? ws + L.off_lv : nullptr;
   d.lv_stride = L.lv_stride;
-  if (L.ldxt) {
-    d.xt = ws + L.off_xt;
-    d.ldxt = L.ldxt;
-  }
   if (L.ldq) {
     d.q8 = (uint8_t *)(ws + L.off_q8);
     d.ldq = L.ldq;
@@ -266,7 +256,6 @@ struct ifnso_plan_s {
   bool learned = false;
   bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
   int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
-  int t_grid = 1;             // transposed copies: workgroups per problem
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
   double *d_fixed = nullptr;       // learned mode: fixed coefficient slots (fallback)
@@ -495,7 +484,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
-                                    p->agg, e4m3, p->fast));
+                                    p->agg, e4m3));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -553,11 +542,6 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   hipSetDevice(prev);
   if (e != hipSuccess) return cleanup(fail(IFNSO_ERR_HIP, "plan allocation: %s", hipGetErrorString(e)));
-  if (p->fast) {
-    int need = 1;
-    for (const ProbLayout &L : p->lay) need = std::max<int64_t>(need, ((L.rows + 127) / 128) * ((L.cols + 127) / 128));
-    p->t_grid = std::max(1, std::min(need, std::max(1, (8 * p->cus + num_problems - 1) / num_problems)));
-  }
   if (e4m3) {
     // workgroups per problem for the memory-bound passes: enough work for each, about 8 per
     // CU over the whole batch
@@ -627,10 +611,11 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   return a;
 }
 
-// Launch slots of one call, in order: preparation (M^T copies for the 256-tile kernels; e4m3
-// pre-pass and input quantisation), Gram (wide, tall), each squaring level (with its
-// quantisation in e4m3 plans), aggregate, product (wide, tall). A slot that has no work in a call is skipped; with `ev`, ev[i] is recorded before
-// slot i and ev[num_slots] after the last one, so empty slots read as zero time.
+// Launch slots of one call, in order: preparation (e4m3 pre-pass and input quantisation; empty
+// in other plans), Gram (wide, tall), each squaring level (with its quantisation in e4m3
+// plans), aggregate, product (wide, tall). A slot that has no work in a call is skipped; with
+// `ev`, ev[i] is recorded before slot i and ev[num_slots] after the last one, so empty slots
+// read as zero time.
 static int num_slots(const ifnso_plan_s *p) { return p->Jsq + 6; }
 
 // Problem-level check for the fast kernels: 16-byte aligned rows whose length is a multiple of
@@ -639,9 +624,7 @@ static bool fast_io_ok(const ifnso_plan_s *p, const ProbDev &d, const ProbLayout
   const int64_t cols = L.cols;
   const size_t in_bytes = ((size_t)(L.rows - 1) * d.ldm + cols) * 2;
   const int oes = p->out_dtype == IFNSO_F32 ? 4 : 2;
-  const size_t xt_bytes = (size_t)cols * (size_t)round_up(L.rows, 8) * 2;
   return cols % 8 == 0 && d.ldm % 8 == 0 && ((uintptr_t)d.M % 16) == 0 && in_bytes < (1ull << 31) &&
-         xt_bytes < (1ull << 31) &&
          ((size_t)d.ldy * oes) % 16 == 0 && ((uintptr_t)d.Y % 16) == 0;
 }
 
@@ -695,8 +678,6 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   };
   const int nprob = one ? 1 : p->num;
   if ((e = mark()) != hipSuccess) return e;
-  // the e4m3 Gram reads its own e4m3 copy, so only wide problems (for the product) need M^T
-  if (fast && fast_io && (e = launch_transpose(a, nprob, p->t_grid, p->e4m3 ? 1 : 0, s)) != hipSuccess) return e;
   if (p->e4m3) {
     if ((e = launch_e4m3_pass(kE4m3Prepass, a, nprob, p->q_grid[0], s)) != hipSuccess) return e;
     if ((e = launch_e4m3_pass(kE4m3QuantInput, a, nprob, p->q_grid[1], s)) != hipSuccess) return e;

@@ -27,8 +27,6 @@ hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu);
 // bfloat16 fast path, 256 x 256 tiles (see ifnso_fast.hip for the operand requirements)
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
 hipError_t fast_occupancy(int stage, int *blocks_per_cu);
-// M^T copies for the 256-tile kernels (one grid row per problem; wide_only: skip tall problems)
-hipError_t launch_transpose(const StageArgs &a, int nprob, int per_problem, int wide_only, hipStream_t s);
 // P = sum_l c_l S_l B_l over the stored levels (level layout); tasks are (problem, chunk)
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s);
 constexpr int kAggChunk = 1 << 17;  // elements per aggregate task

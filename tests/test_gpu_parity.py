@@ -312,7 +312,7 @@ def test_launch_events_and_info(torch_dev):
     plan = ifn.Plan(exps, c, shapes, compute="bf16")
     n = plan.num_launches
     assert n == 4 + 6
-    assert plan.launch_info(0) == (4, 0.0)  # preparation: transposed copies
+    assert plan.launch_info(0) == (4, 0.0)  # preparation (empty in bf16 plans)
     fl = [plan.launch_info(i) for i in range(n)]
     total = sum(f for _, f in fl)
     want = sum(min(s) ** 2 * max(s) * 3 + 4 * min(s) ** 3 for s in shapes)
