@@ -14,7 +14,9 @@ step, timed with HIP events recorded around each stage inside the timed region.
 `--workload e4m3` measures the e4m3 variant instead: 64 matrices 2048x8192 built as
 U diag(sigma) V^T with Haar factors and sigma_i = i^-1.5 (seed 3), e4m3 Gram and squarings
 with per-tensor scales, bfloat16 aggregation and product; it reports the error of the
-e4m3 and bfloat16 modes against the FP64 oracle on a sample of the batch.
+e4m3 and bfloat16 modes against the FP64 oracle on a sample of the batch. `--workload
+learned` trains the coefficient network and runs the set with it; `--workload tform` runs
+the paper's complement-basis form (depth 14) on the set in bfloat16.
 """
 from __future__ import annotations
 
@@ -384,6 +386,89 @@ def run_learned(args, torch, dev, hip, log):
     print(json.dumps(line), flush=True)
 
 
+def run_tform(args, torch, dev, hip, log):
+    """The paper's own form on the gradient set: complement basis T = I - XX^T with
+    X = A / ||AA^T||_F^(1/2), depth L = 14 (exponents 0, 1, 2, ..., 2^13: 13 squarings of the
+    shifted power D = T - I), coefficients "paper_L14", bfloat16 operands. Reports throughput,
+    the orthogonality error on all matrices beside the Gram-basis form's, and the parity of
+    layer 0's two 1024x4096 matrices against the float64 oracle."""
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs
+    import oracle
+    exps, coeffs = configs.load_coeffs("paper_L14")
+    Ms = make_d3(torch, dev, args.layers)
+    shapes = [tuple(m.shape) for m in Ms]
+    n = len(Ms)
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan = ifn.Plan(exps, coeffs, shapes, basis="complement", norm="gram_frobenius", compute="bf16")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+    nl = plan.num_launches
+    J = nl - 6
+    names = ["prep"] + ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
+    t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
+    kern, elapsed = t["kern"], t["elapsed"]
+    dom = max((k for k in kern if kern[k][2] > 0), key=lambda k: kern[k][0])
+    dur_ms = kern[dom][0] / kern[dom][1]
+    achieved = kern[dom][2] / kern[dom][1] / (dur_ms * 1e-3) / 1e12
+    ms_per_step = elapsed / args.steps * 1e3
+
+    def orth(Yl):
+        out = torch.empty(n, dtype=torch.float64, device=dev)
+        ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        ifn.orth_error(Yl, out, ows)
+        oe = out.cpu().numpy() / np.sqrt([min(s) for s in shapes])
+        per = {}
+        for nm, r, c in configs.LAYER_SHAPES:
+            idx = [i for i, s in enumerate(shapes) if s == (r, c)]
+            per[f"{r}x{c}"] = round(float(oe[idx].mean()), 5)
+        return {"mean": float(oe.mean()), "max": float(oe.max()), "per_shape": per}
+
+    err_t = orth(Ys)
+    # layer 0's Wk, Wv against the float64 oracle (13 squarings of 1024^2 in numpy)
+    rel, orth_o = [], []
+    for i in range(min(n, 7)):
+        if shapes[i] != (1024, 4096):
+            continue
+        Mh = Ms[i].float().cpu().numpy().astype(np.float64)
+        Yo = oracle.ifnso(Mh, exps, coeffs, "complement", "gram_frobenius")
+        Yg = Ys[i].float().cpu().numpy().astype(np.float64)
+        rel.append(float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)))
+        orth_o.append(float(oracle.orth_error(Yo) / np.sqrt(1024)))
+    del ws, plan
+    eg, cg = configs.load_coeffs("gform_v1")
+    plan_g = ifn.Plan(eg, cg, shapes, compute="bf16")
+    ws = torch.empty(plan_g.workspace_bytes, dtype=torch.uint8, device=dev)
+    Yg = [torch.empty_like(m) for m in Ms]
+    plan_g.orthogonalize_batched(Ms, Yg, ws)
+    torch.cuda.synchronize()
+    err_g = orth(Yg)
+    line = {
+        "metric": "paper form (complement basis, L = 14) on the 32-layer gradient set: matrices/s and "
+                  "||YY^T - I||_F / sqrt(h)",
+        "value": round(n * args.steps / elapsed, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices; complement basis, "
+                               "Gram-Frobenius scaling, exponents 0..2^13", "matrices": n,
+                   "coeffs": "paper_L14", "compute": "bf16"},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "avg_launch_ms": round(dur_ms, 3)},
+        "cpu_baseline": None,
+        "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
+                        "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
+                    for k, v in kern.items()},
+        "orth_err_over_sqrt_h": err_t,
+        "gram_basis_gform_v1_orth_err_over_sqrt_h": err_g,
+        "parity_layer0_1024x4096_rel_vs_oracle": rel,
+        "oracle_orth_err_over_sqrt_h_layer0_1024x4096": orth_o,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,10 +478,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned"], default="gradset",
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform"], default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
                          "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
-                         "network on the GPU, then run the gradient set with learned and fixed coefficients")
+                         "network on the GPU, then run the gradient set with learned and fixed coefficients; "
+                         "tform: the paper's complement-basis form (L = 14) on the gradient set")
     ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
     ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
@@ -434,6 +520,8 @@ def main():
         return run_e4m3(args, torch, dev, hip, log)
     if args.workload == "learned":
         return run_learned(args, torch, dev, hip, log)
+    if args.workload == "tform":
+        return run_tform(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()
