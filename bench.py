@@ -99,8 +99,9 @@ def stage_flops(shapes, J):
 
 
 # kernel of a bench launch name -> its name in the rocprofv3 traffic summary
-PROFILE_KERNEL = {"square": "kf_square<true>", "gram_wide": "kf_gram<false>", "gram_tall": "kf_gram<true>",
-                  "product_wide": "kf_product<false>", "product_tall": "kf_product<true>",
+PROFILE_KERNEL = {"square": "kf_square<true, false>", "gram_wide": "kf_gram<false, false>",
+                  "gram_tall": "kf_gram<true, false>", "product_wide": "kf_product<false, false>",
+                  "product_tall": "kf_product<true, false>",
                   "aggregate": "kf_aggregate"}
 
 
@@ -389,9 +390,10 @@ def run_learned(args, torch, dev, hip, log):
 def run_tform(args, torch, dev, hip, log):
     """The paper's own form on the gradient set: complement basis T = I - XX^T with
     X = A / ||AA^T||_F^(1/2), depth L = 14 (exponents 0, 1, 2, ..., 2^13: 13 squarings of the
-    shifted power D = T - I), coefficients "paper_L14", bfloat16 operands. Reports throughput,
-    the orthogonality error on all matrices beside the Gram-basis form's, and the parity of
-    layer 0's two 1024x4096 matrices against the float64 oracle."""
+    shifted power D = T - I), coefficients "paper_L14", bfloat16 compute with split (hi + lo)
+    operands; `--unsplit` uses single bfloat16 operands instead. Reports throughput, the
+    orthogonality error on all matrices beside the Gram-basis form's, and the parity of layer
+    0's two 1024x4096 matrices against the float64 oracle."""
     import numpy as np
 
     import paper_2602_02500_amd as ifn
@@ -402,7 +404,9 @@ def run_tform(args, torch, dev, hip, log):
     shapes = [tuple(m.shape) for m in Ms]
     n = len(Ms)
     Ys = [torch.empty_like(m) for m in Ms]
-    plan = ifn.Plan(exps, coeffs, shapes, basis="complement", norm="gram_frobenius", compute="bf16")
+    split = not args.unsplit
+    plan = ifn.Plan(exps, coeffs, shapes, basis="complement", norm="gram_frobenius", compute="bf16",
+                    flags=ifn.FLAG_SPLIT_BF16 if split else 0)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"workspace {plan.workspace_bytes / 2**30:.1f} GiB")
     nl = plan.num_launches
@@ -453,7 +457,7 @@ def run_tform(args, torch, dev, hip, log):
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices; complement basis, "
                                "Gram-Frobenius scaling, exponents 0..2^13", "matrices": n,
-                   "coeffs": "paper_L14", "compute": "bf16"},
+                   "coeffs": "paper_L14", "compute": "bf16", "operands": "split bf16 pairs" if split else "bf16"},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                      "avg_launch_ms": round(dur_ms, 3)},
@@ -486,6 +490,7 @@ def main():
     ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
     ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
+    ap.add_argument("--unsplit", action="store_true", help="tform workload: single bf16 operands")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain elementwise copy (out = x + 0, float32) that reads and writes BYTES, "
                          "as a known-size reference for hardware byte counters")

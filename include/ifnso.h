@@ -79,7 +79,17 @@ typedef enum {
 typedef enum { IFNSO_COEFF_FIXED = 0, IFNSO_COEFF_LEARNED = 1 } ifnso_coeff_mode;
 
 enum {
-  IFNSO_FLAG_ENFORCE_SUM_ONE = 1  /* reject coefficients with |sum c - 1| > 1e-12 */
+  IFNSO_FLAG_ENFORCE_SUM_ONE = 1, /* reject coefficients with |sum c - 1| > 1e-12 */
+  /* Complement basis with bf16 compute: carry every squaring operand and P as a split pair
+   * X = X_hi + X_lo of bf16 values (X_hi = bf16(X), X_lo = bf16(X - X_hi)), so a squaring forms
+   * X_hi X_hi + X_hi X_lo + X_lo X_hi (three bf16 products, float32 accumulation) and the
+   * product P M as P_hi M + P_lo M. The shifted powers D_l = T^(2^(l-1)) - I of the paper's
+   * form (Sec. 2.4, Algorithm 1) are then held to about 16 significant bits instead of 8, which
+   * the large alternating coefficients of a depth-14 polynomial need. Costs about 3x the
+   * squaring and 2x the product work. Needs fixed coefficients and problems that take the
+   * 256-tile kernels (16-byte aligned rows, a multiple of 8 columns; otherwise a call returns
+   * IFNSO_ERR_UNSUPPORTED). */
+  IFNSO_FLAG_SPLIT_BF16 = 2
 };
 
 /* Polynomial descriptor. Arrays are read during ifnso_plan() only (copied). */

@@ -15,6 +15,7 @@ __all__ = [
     "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes",
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
+    "FLAG_SPLIT_BF16",
     "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
     "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes", "StageConfig",
     "quantize_e4m3", "quantize_e4m3_workspace_bytes", "STAGE_GRAM", "STAGE_SQUARE", "STAGE_PRODUCT",
@@ -30,6 +31,7 @@ BASIS_GRAM, BASIS_COMPLEMENT = 0, 1
 NORM_FROBENIUS, NORM_GRAM_FROBENIUS, NORM_NONE = 0, 1, 2
 COEFF_FIXED, COEFF_LEARNED = 0, 1
 FLAG_ENFORCE_SUM_ONE = 1
+FLAG_SPLIT_BF16 = 2
 STATS_PER_PROBLEM = 26
 MLP_NUM_PARAMS = 5126
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "WORKSPACE_TOO_SMALL", 4: "HIP", 5: "INTERNAL"}

@@ -76,6 +76,7 @@ struct StageArgs {
   int32_t xcd_off[8];
   int32_t xcd_cnt[8];
   int32_t wg_per_xcd;  // host only: workgroups per XCD of a fast launch
+  int32_t split;       // complement basis, fast path: operands stored as split bf16 pairs
   ProbDev one;         // the problem of a single-problem launch
 };
 

@@ -224,15 +224,41 @@ __device__ __forceinline__ bf16x8 tr_frag(const char *S, int mn_off, int kk) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// K-segment maps of an operand in split-bfloat16 products (a value carried as hi + lo bf16 halves
+// stored side by side: [X_hi | X_lo], seg columns each). The product runs over a logical K of
+// several segments; segment s of the logical range reads physical segment map(s) of the operand:
+//   KMAP_ID   identity (physical = logical)
+//   KMAP_MOD  every segment reads segment 0 (the operand is used as is against [Y_hi | Y_lo])
+//   KMAP_HHL  segments (0, 0, 1): [X_hi | X_hi | X_lo]
+//   KMAP_HLH  segments (0, 1, 0): [X_hi | X_lo | X_hi]
+// so that [X_hi | X_hi | X_lo] . [X_hi | X_lo | X_hi]^T = X_hi X_hi^T + X_hi X_lo^T + X_lo X_hi^T.
+enum KMapKind : int { KMAP_ID = 0, KMAP_MOD = 1, KMAP_HHL = 2, KMAP_HLH = 3 };
+
+template <int MAP>
+__device__ __forceinline__ int kphys(int k, int seg) {
+  if constexpr (MAP == KMAP_ID) {
+    return k;
+  } else {
+    const int sg = k / seg, r = k - sg * seg;
+    if constexpr (MAP == KMAP_MOD) return r;
+    else if constexpr (MAP == KMAP_HHL) return r + (sg == 2 ? seg : 0);
+    else return r + (sg == 1 ? seg : 0);
+  }
+}
+
 // Both operands K-major: one barrier per K step. The loads of step k+1 go into the other LDS
 // stage while step k's MFMAs run, half of them before each of the step's first two K slices (so
 // the later half still has half a step to land before the next barrier); that stage was last
 // read in step k-1, which every wave finished before this step's barrier. bfloat16 fragments are
 // double-buffered: slice kk+1's are read from LDS while slice kk's MFMAs run.
-template <bool F8, bool AMN = false, bool BMN = false>
+// PA / PB: K-segment maps (segments of `seg`, a multiple of the stage depth); K is then the
+// logical depth, and kvA / kvB bound the physical K of each operand (beyond it reads as zero).
+template <bool F8, bool AMN = false, bool BMN = false, int PA = KMAP_ID, int PB = KMAP_ID>
 __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
-                                              const Operand &B, int bn0, int K, bool want_norm) {
+                                              const Operand &B, int bn0, int K, bool want_norm, int seg = 0,
+                                              int kvA = 0, int kvB = 0) {
   static_assert(!F8 || (!AMN && !BMN), "e4m3 operands are K-major");
+  const int KA = PA == KMAP_ID ? K : kvA, KB = PB == KMAP_ID ? K : kvB;
   constexpr int ES = F8 ? 1 : 2;
   constexpr int KST = 128 / ES;           // elements per stage
   constexpr int NS = F8 ? 2 : BK / 16;    // MFMA K slices per stage
@@ -257,9 +283,9 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
   else krows<BN>(RB, B.ld_bytes, bn0, B.lim);
   const uint32_t lbase = uni(lds_addr(smem));
   {
-    const bool full = KST <= K;
-    issue_krows<BM, ES, 0, RPT, AMN>(RA, lbase, A.w, 0, K, full, A.ld_bytes, wave);
-    issue_krows<BN, ES, 0, RPT, BMN>(RB, lbase + BM * 128, B.w, 0, K, full, B.ld_bytes, wave);
+    const int ka = kphys<PA>(0, seg), kb = kphys<PB>(0, seg);
+    issue_krows<BM, ES, 0, RPT, AMN>(RA, lbase, A.w, ka, KA, ka + KST <= KA, A.ld_bytes, wave);
+    issue_krows<BN, ES, 0, RPT, BMN>(RB, lbase + BM * 128, B.w, kb, KB, kb + KST <= KB, B.ld_bytes, wave);
   }
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
@@ -271,14 +297,15 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
     }
     const bool more = kt + 1 < nk;
     const int k1 = (kt + 1) * KST;
-    const bool full = k1 + KST <= K;
+    const int ka = kphys<PA>(k1, seg), kb = kphys<PB>(k1, seg);
+    const bool fulla = ka + KST <= KA, fullb = kb + KST <= KB;
     const uint32_t An = lbase + (cur ^ 1) * STAGE_BYTES, Bn = An + BM * 128;
     auto issue_slice = [&](auto sl) {
       constexpr int s = decltype(sl)::value;
       if constexpr (s < 2) {
         if (more) {
-          issue_krows<BM, ES, s * PER, (s + 1) * PER, AMN>(RA, An, A.w, k1, K, full, A.ld_bytes, wave);
-          issue_krows<BN, ES, s * PER, (s + 1) * PER, BMN>(RB, Bn, B.w, k1, K, full, B.ld_bytes, wave);
+          issue_krows<BM, ES, s * PER, (s + 1) * PER, AMN>(RA, An, A.w, ka, KA, fulla, A.ld_bytes, wave);
+          issue_krows<BN, ES, s * PER, (s + 1) * PER, BMN>(RB, Bn, B.w, kb, KB, fullb, B.ld_bytes, wave);
         }
       }
     };
@@ -354,10 +381,11 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
 // array whose rows run along K) or, with AMN / BMN, MN-major (the array's rows run along K and
 // its columns am0.. are the tile's rows: Aop = X^T). F8: OCP e4m3 operands (1 byte, 128 per LDS
 // row and stage, K-major), MFMA 32x32x64.
-template <bool AMN, bool BMN, bool F8 = false>
+template <bool AMN, bool BMN, bool F8 = false, int PA = KMAP_ID, int PB = KMAP_ID>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
-                                           const Operand &B, int bn0, int K, bool want_norm) {
-  return mainloop_kk<F8, AMN, BMN>(acc, smem, A, am0, B, bn0, K, want_norm);
+                                           const Operand &B, int bn0, int K, bool want_norm, int seg = 0,
+                                           int kvA = 0, int kvB = 0) {
+  return mainloop_kk<F8, AMN, BMN, PA, PB>(acc, smem, A, am0, B, bn0, K, want_norm, seg, kvA, kvB);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -524,6 +552,22 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
   }
 }
 
+// bfloat16 value of v (round to nearest even), as a float
+__device__ __forceinline__ float bf16_value(float v) { return __uint_as_float((uint32_t)f32_to_bf16(v) << 16); }
+
+// Staged half tile as a bfloat16 operand: plain (leading dimension hp), or with SPLIT as the
+// pair hi = bf16(v), lo = bf16(v - hi) stored side by side ([X_hi | X_lo], leading dimension 2 hp).
+template <bool SPLIT>
+__device__ __forceinline__ void emit_operand(const float *ep, uint16_t *dst, int64_t hp, int m0, int n0, int half,
+                                             bool diag) {
+  if constexpr (SPLIT) {
+    emit_sym_bf16(ep, dst, 2 * hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+    emit_sym_bf16(ep, dst + hp, 2 * hp, m0, n0, half, diag, [](float v, int, int) { return v - bf16_value(v); });
+  } else {
+    emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+  }
+}
+
 // Sums of three float64 values over the workgroup in a fixed order (lanes, then waves 0..NW-1).
 __device__ __forceinline__ void block_sum3w(double &a, double &b, double &c, double *scratch) {
 #pragma unroll
@@ -631,7 +675,8 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
 // Gram
 // ---------------------------------------------------------------------------------------------
 // TALL: A = M^T, read MN-major straight from M (K = rows of M); otherwise A = M, K-major.
-template <bool TALL>
+// SPLIT: the Gram operand is stored as a split bfloat16 pair (complement-basis split plans).
+template <bool TALL, bool SPLIT>
 __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -659,7 +704,7 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
     for (int half = 0; half < 2; half++) {
       stage_half(acc, ep, half);
       __syncthreads();
-      emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+      emit_operand<SPLIT>(ep, dst, hp, m0, n0, half, diag);
       if (!keep_f32) {
         if (diag && threadIdx.x < 128) dg += (double)ep[threadIdx.x * EP_LD + half * 128 + threadIdx.x];
         __syncthreads();
@@ -695,8 +740,11 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
-template <bool AGG>
+// SPLIT (complement basis): the operand is a split pair [D_hi | D_lo]; the product runs over
+// K = 3 hp as D_hi D_hi + D_hi D_lo + D_lo D_hi, and the next operand is written split.
+template <bool AGG, bool SPLIT = false>
 __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
+  static_assert(!(AGG && SPLIT), "split operands are a complement-basis option");
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
   const int level = a.level;
@@ -728,12 +776,17 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
     const int m0 = task.tm * BM, n0 = task.tn * BN;
     const bool diag = task.tm == task.tn;
     const int64_t hp = P.hp;
-    const uint32_t bytes = (uint32_t)(hp * hp * 2);
+    const int64_t ldo = SPLIT ? 2 * hp : hp;  // operand leading dimension
+    const uint32_t bytes = (uint32_t)(hp * ldo * 2);
     const void *srcp = AGG ? (const void *)((const char *)P.lv + (int64_t)(level - 1) * P.lv_stride)
                            : (const void *)P.opnd[(level - 1) & 1];
-    const Operand op = make_operand(srcp, bytes, (uint32_t)(hp * 2), P.hp);
+    const Operand op = make_operand(srcp, bytes, (uint32_t)(ldo * 2), P.hp);
     f32x16 acc[FM][FN];
-    mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
+    if constexpr (SPLIT)
+      mainloop<false, false, false, KMAP_HHL, KMAP_HLH>(acc, smem, op, m0, op, n0, uni(3 * P.hp), false, uni(P.hp),
+                                                       uni(2 * P.hp), uni(2 * P.hp));
+    else
+      mainloop<false, false>(acc, smem, op, m0, op, n0, uni(P.h), false);
     uint16_t *dst = AGG ? (uint16_t *)((char *)P.lv + (int64_t)level * P.lv_stride) : (uint16_t *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
@@ -796,7 +849,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
         }
       }
       __syncthreads();
-      emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+      emit_operand<SPLIT>(ep, dst, hp, m0, n0, half, diag);
       __syncthreads();
     }
     block_sum3w(lv, dg, unused, (double *)smem);
@@ -861,7 +914,8 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
 // ---------------------------------------------------------------------------------------------
 // product: Y = s (c0 A + P A) in M's orientation (IFNSO only)
 // ---------------------------------------------------------------------------------------------
-template <bool TRANS>
+// SPLIT: P is a split pair [P_hi | P_lo] and the product runs over K = 2 hp against M taken twice.
+template <bool TRANS, bool SPLIT = false>
 __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int out_bf16) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
@@ -906,7 +960,8 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
     // the output tile's row (tall, K-major) or column (wide, MN-major) index either way
     const uint32_t mbytes = (uint32_t)(((int64_t)(TRANS ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(TRANS ? P.h : P.w) * 2);
     const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
-    const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * hp * 2), (uint32_t)(hp * 2), P.hp);
+    const int64_t ldp = SPLIT ? 2 * hp : hp;
+    const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * ldp * 2), (uint32_t)(ldp * 2), P.hp);
     const int Kp = uni(P.h);
     f32x16 acc[FM][FN];
     const int rows_out = P.trans ? P.w : P.h, cols_out = P.trans ? P.h : P.w;
@@ -919,10 +974,17 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
           for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
     } else if constexpr (TRANS) {
       // Y_out[n][i] = sum_k M[n][k] P[i][k]
-      mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
+      if constexpr (SPLIT)
+        mainloop<false, false, false, KMAP_MOD, KMAP_ID>(acc, smem, Mo, m0, Po, n0, uni(2 * P.hp), false, uni(P.hp), Kp);
+      else
+        mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
     } else {
       // Y[i][n] = sum_k P[i][k] M[k][n]
-      mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
+      if constexpr (SPLIT)
+        mainloop<false, true, false, KMAP_ID, KMAP_MOD>(acc, smem, Po, m0, Mo, n0, uni(2 * P.hp), false, uni(P.hp), 0,
+                                                        Kp);
+      else
+        mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
     // each thread owns one 8-column chunk of RS rows apart; row offsets are uniform additions
     constexpr int RS = NT / 32, PER = 128 / RS;
@@ -1043,15 +1105,21 @@ hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
 
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
+  const bool split = a.split != 0;
   if (stage == kStageGram) {
-    if (trans) hipLaunchKernelGGL(fast::kf_gram<true>, dim3(grid), dim3(fast::NT), 0, s, a);
-    else hipLaunchKernelGGL(fast::kf_gram<false>, dim3(grid), dim3(fast::NT), 0, s, a);
+    if (trans && split) hipLaunchKernelGGL((fast::kf_gram<true, true>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else if (trans) hipLaunchKernelGGL((fast::kf_gram<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else if (split) hipLaunchKernelGGL((fast::kf_gram<false, true>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else hipLaunchKernelGGL((fast::kf_gram<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
   } else if (stage == kStageSquare) {
-    if (a.agg) hipLaunchKernelGGL(fast::kf_square<true>, dim3(grid), dim3(fast::NT), 0, s, a);
-    else hipLaunchKernelGGL(fast::kf_square<false>, dim3(grid), dim3(fast::NT), 0, s, a);
+    if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else if (split) hipLaunchKernelGGL((fast::kf_square<false, true>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
   } else {
-    if (trans) hipLaunchKernelGGL(fast::kf_product<true>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
-    else hipLaunchKernelGGL(fast::kf_product<false>, dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
+    if (trans && split) hipLaunchKernelGGL((fast::kf_product<true, true>), dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
+    else if (trans) hipLaunchKernelGGL((fast::kf_product<true, false>), dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
+    else if (split) hipLaunchKernelGGL((fast::kf_product<false, true>), dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
+    else hipLaunchKernelGGL((fast::kf_product<false, false>), dim3(grid), dim3(fast::NT), 0, s, a, out_bf16);
   }
   return hipGetLastError();
 }
@@ -1064,8 +1132,8 @@ hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t
 }
 
 hipError_t fast_occupancy(int stage, int *blocks_per_cu) {
-  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false>
-                 : stage == kStageSquare ? (const void *)fast::kf_square<true> : (const void *)fast::kf_product<false>;
+  const void *fn = stage == kStageGram ? (const void *)fast::kf_gram<false, false>
+                 : stage == kStageSquare ? (const void *)fast::kf_square<true, false> : (const void *)fast::kf_product<false, false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, fast::NT, 0);
 }
 

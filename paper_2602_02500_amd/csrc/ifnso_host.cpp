@@ -77,7 +77,7 @@ void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
 // Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
 // float32 D ping-pong; classical NS adds two h x w iterates.
 ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
-                          bool e4m3 = false) {
+                          bool e4m3 = false, bool split = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -102,8 +102,9 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.off_opnd[1] = L.off_lv;
     L.off_accf = L.off_lv;  // never written in the level layout
   } else {
-    L.off_opnd[0] = take(hh * op_size(op));
-    L.off_opnd[1] = take(hh * op_size(op));
+    // split operands: hp x 2hp, [X_hi | X_lo] per row
+    L.off_opnd[0] = take(hh * op_size(op) * (split ? 2 : 1));
+    L.off_opnd[1] = take(hh * op_size(op) * (split ? 2 : 1));
     L.off_accf = take(hh * 4);
   }
   if (complement) {
@@ -255,6 +256,7 @@ struct ifnso_plan_s {
   bool agg = false;   // level layout + aggregate stage (fast, Gram basis, J >= 1)
   bool learned = false;
   bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
+  bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
   int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
@@ -377,7 +379,12 @@ static ifnso_status validate_desc(const ifnso_poly_desc *d) {
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad compute %d", d->compute);
   if (d->coeff_mode != IFNSO_COEFF_FIXED && d->coeff_mode != IFNSO_COEFF_LEARNED)
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad coeff_mode %d", d->coeff_mode);
-  if (d->flags & ~(uint32_t)IFNSO_FLAG_ENFORCE_SUM_ONE) return fail(IFNSO_ERR_INVALID_ARGUMENT, "unknown flags");
+  if (d->flags & ~(uint32_t)(IFNSO_FLAG_ENFORCE_SUM_ONE | IFNSO_FLAG_SPLIT_BF16))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "unknown flags");
+  if ((d->flags & IFNSO_FLAG_SPLIT_BF16) &&
+      (d->compute != IFNSO_COMPUTE_BF16 || d->basis != IFNSO_BASIS_COMPLEMENT || d->coeff_mode != IFNSO_COEFF_FIXED))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "IFNSO_FLAG_SPLIT_BF16 needs bf16 compute, the complement basis and fixed "
+                                            "coefficients");
   if (d->flags & IFNSO_FLAG_ENFORCE_SUM_ONE) {
     double s = 0;
     for (int k = 0; k < d->num_terms; k++) s += d->coeffs[k];
@@ -478,13 +485,20 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->e4m3 = e4m3;
   p->agg = p->fast && p->basis == IFNSO_BASIS_GRAM && (p->J >= 1 || e4m3);
   p->learned = desc->coeff_mode == IFNSO_COEFF_LEARNED;
+  p->split = (desc->flags & IFNSO_FLAG_SPLIT_BF16) != 0;
+  if (p->split && !p->fast)
+    return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "split bf16 operands need the bf16 fast path (IFNSO_FAST != 0, "
+                                                        "h below 32512)"));
+  for (int i = 0; p->split && i < num_problems; i++)
+    if (round_up(std::min(rows[i], cols[i]), kPad) > 23040)  // hp x 2hp bf16 pairs below 2 GiB
+      return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "split bf16 operands need min(rows, cols) <= 23040"));
   if (p->learned && !p->agg)
     return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
   p->Jsq = p->learned ? p->J + 2 : p->J;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
-                                    p->agg, e4m3));
+                                    p->agg, e4m3, p->split));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -608,6 +622,7 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   a.p_empty = p->p_empty;
   a.learned = 0;
   a.agg = p->agg ? 1 : 0;
+  a.split = p->split ? 1 : 0;
   return a;
 }
 
@@ -815,6 +830,16 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
   for (int i = 0; i < p->num; i++) {
     ifnso_status st = check_matrix_args(p, i, M[i], ldm[i], Y[i], ldy[i]);
     if (st != IFNSO_OK) return st;
+    if (p->split) {  // only the 256-tile kernels know the split layout
+      ProbDev t{};
+      t.M = M[i];
+      t.ldm = ldm[i];
+      t.Y = Y[i];
+      t.ldy = ldy[i];
+      if (!fast_io_ok(p, t, p->lay[i]))
+        return fail(IFNSO_ERR_UNSUPPORTED, "problem %d: split bf16 plans need 16-byte aligned M and Y rows and a "
+                                           "multiple of 8 columns", i);
+    }
   }
   std::lock_guard<std::mutex> lock(p->mu);
   int prev = 0;

@@ -60,6 +60,16 @@ def test_sum_one_flag(L):
     assert st == 1 and b"sum" in L.ifnso_last_error()
 
 
+def test_split_flag_requirements(L):
+    """Split bf16 operands are a complement-basis, bf16-compute, fixed-coefficient option."""
+    split = ifn.FLAG_SPLIT_BF16
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=0, compute=1, flags=split)[0] == 1  # Gram basis
+    assert b"SPLIT" in L.ifnso_last_error()
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=0, flags=split)[0] == 1  # float32 compute
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=2, flags=split)[0] == 1  # e4m3 compute
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=1, flags=8)[0] == 1      # unknown bit
+
+
 def test_unsupported_combinations(L):
     assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_F32, ind=ifn.BF16)[0] == 2
     assert _plan(L, [0, 1], [1, 1], compute=ifn.COMPUTE_BF16, ind=ifn.F32)[0] == 2
