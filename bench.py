@@ -473,6 +473,64 @@ def run_tform(args, torch, dev, hip, log):
     print(json.dumps(line), flush=True)
 
 
+def run_muon(args, torch, dev, hip, log):
+    """One Muon optimizer step per timed step on the gradient set: float32 weights and momentum,
+    the bf16 gradients as G, Nesterov momentum 0.95, lr 0.02, weight decay 0.01, the fixed
+    Gram-basis coefficients as the orthogonalisation. Reports matrices/s of whole steps and the
+    time of the orthogonalisation alone on the same inputs."""
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs, gen
+    exps, coeffs = configs.load_coeffs("gform_v1")
+    Gs = make_d3(torch, dev, args.layers)
+    shapes = [tuple(g.shape) for g in Gs]
+    n = len(Gs)
+    Ws = [gen.gaussian_torch(r, c, 5000 + i, 0, 0.02, device=dev) for i, (r, c) in enumerate(shapes)]
+    Bs = [torch.zeros(s, dtype=torch.float32, device=dev) for s in shapes]
+    plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
+    ws = torch.empty(plan.muon_workspace_bytes, dtype=torch.uint8, device=dev)
+    log(f"muon workspace {plan.muon_workspace_bytes / 2**30:.1f} GiB")
+    hp = dict(lr=0.02, momentum=0.95, weight_decay=0.01, nesterov=True)
+    for _ in range(args.warmup):
+        plan.muon_step(Ws, Gs, Bs, ws, **hp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.muon_step(Ws, Gs, Bs, ws, **hp)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    Ys = [torch.empty_like(g) for g in Gs]
+    for _ in range(args.warmup):
+        plan.orthogonalize_batched(Gs, Ys, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.orthogonalize_batched(Gs, Ys, ws)
+    torch.cuda.synchronize()
+    dto = (time.perf_counter() - t0) / args.steps
+    elems = sum(r * c for r, c in shapes)
+    # elementwise bytes: momentum pass reads B, G and writes B, U; update pass reads W, Y, writes W
+    ew_bytes = elems * (4 + 2 + 4 + 2 + 4 + 2 + 4)
+    finite = all(bool(torch.isfinite(w).all()) for w in Ws)
+    line = {
+        "metric": "Muon optimizer steps on the 32-layer gradient set (momentum, IFNSO, weight update)",
+        "value": round(n / dt, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices as gradients; float32 weights "
+                               "N(0, 0.02^2) and momentum", "matrices": n, "coeffs": "gform_v1",
+                   "optimizer": hp},
+        "roofline": None, "cpu_baseline": None,
+        "orthogonalize_ms": round(dto * 1e3, 3),
+        "elementwise_ms": round((dt - dto) * 1e3, 3),
+        "elementwise_bytes": ew_bytes,
+        "elementwise_gbps": round(ew_bytes / max(dt - dto, 1e-9) / 1e9, 1),
+        "weights_finite": finite,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,11 +540,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform"], default="gradset",
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon"], default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
                          "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
                          "network on the GPU, then run the gradient set with learned and fixed coefficients; "
-                         "tform: the paper's complement-basis form (L = 14) on the gradient set")
+                         "tform: the paper's complement-basis form (L = 14) on the gradient set; muon: whole "
+                         "Muon optimizer steps on the gradient set")
     ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
     ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
@@ -527,6 +586,8 @@ def main():
         return run_learned(args, torch, dev, hip, log)
     if args.workload == "tform":
         return run_tform(args, torch, dev, hip, log)
+    if args.workload == "muon":
+        return run_muon(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()

@@ -188,6 +188,31 @@ ifnso_status ifnso_plan_set_config(ifnso_plan_t plan, int32_t stage, const ifnso
  * Errors: INVALID_ARGUMENT. */
 ifnso_status ifnso_plan_launch_events(ifnso_plan_t plan, void *const *events, int32_t count);
 
+/* One Muon optimizer step over the plan's problems, with the plan's polynomial as the
+ * orthogonalisation (the paper's setting: Muon orthogonalises momentum updates, Sec. 1; the
+ * paper does not restate Muon's update, so this is the reading used):
+ *   B <- momentum B + G
+ *   U <- G + momentum B   (nesterov = 1)   or   U <- B   (nesterov = 0)
+ *   O <- the plan's result for U (U rounded to the plan's input type)
+ *   W <- (1 - lr weight_decay) W - lr sqrt(max(1, rows / cols)) O
+ * W (weights) and B (momentum) are device float32 matrices of each problem's shape, updated in
+ * place; G (gradients) is in the plan's input type. Leading dimensions >= cols. W, B and G must
+ * not overlap. The workspace (ifnso_muon_workspace_bytes, 256-byte aligned) holds the plan's
+ * workspace followed by U, O and a problem table; concurrent steps need their own workspaces.
+ * Enqueued on `stream`; the call returns when the work is queued.
+ * Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, UNSUPPORTED (as for the plan's calls), HIP. */
+typedef struct {
+  double lr;            /* learning rate */
+  double momentum;      /* momentum coefficient */
+  double weight_decay;  /* decoupled weight decay */
+  int32_t nesterov;     /* 0 or 1 */
+} ifnso_muon_params;
+
+ifnso_status ifnso_muon_workspace_bytes(ifnso_plan_t plan, size_t *bytes);
+ifnso_status ifnso_muon_step(ifnso_plan_t plan, const ifnso_muon_params *params, float *const *W,
+                             const int64_t *ldw, const void *const *G, const int64_t *ldg, float *const *B,
+                             const int64_t *ldb, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Classical Newton-Schulz with one odd quintic per step, Eq. (iteration_jordan):
  *   X_0 = A / ||A||_F,  X_{k+1} = a X_k + (b G_k + c G_k^2) X_k,  G_k = X_k X_k^T,
  * for `steps` steps (abc = {a, b, c}; {1.5, -0.5, 0} is the cubic of

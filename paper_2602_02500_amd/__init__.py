@@ -19,6 +19,7 @@ __all__ = [
     "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
     "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes", "StageConfig",
     "quantize_e4m3", "quantize_e4m3_workspace_bytes", "STAGE_GRAM", "STAGE_SQUARE", "STAGE_PRODUCT",
+    "MuonParams",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +49,12 @@ class IfnsoError(RuntimeError):
 
 
 STAGE_GRAM, STAGE_SQUARE, STAGE_PRODUCT = 0, 1, 2
+
+
+class MuonParams(ctypes.Structure):
+    """Hyper-parameters of one Muon step (see ifnso_muon_params)."""
+    _fields_ = [("lr", ctypes.c_double), ("momentum", ctypes.c_double), ("weight_decay", ctypes.c_double),
+                ("nesterov", ctypes.c_int32)]
 
 
 class StageConfig(ctypes.Structure):
@@ -92,6 +99,9 @@ def load() -> ctypes.CDLL:
     L.ifnso_plan_destroy.argtypes = [vp]
     L.ifnso_orthogonalize.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp]
     L.ifnso_orthogonalize_batched.argtypes = [vp, ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64, vp, sz, vp]
+    L.ifnso_muon_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ifnso_muon_step.argtypes = [vp, ctypes.POINTER(MuonParams), ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64,
+                                  ctypes.POINTER(vp), P64, vp, sz, vp]
     L.ifnso_classical_ns.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, ctypes.POINTER(ctypes.c_double), i32,
                                      vp, sz, vp]
     L.ifnso_classical_ns_workspace_bytes.argtypes = [i64, i64, i32]
@@ -199,6 +209,8 @@ class Plan:
         b = ctypes.c_size_t()
         _check(L.ifnso_plan_workspace_bytes(h, ctypes.byref(b)))
         self.workspace_bytes = b.value
+        _check(L.ifnso_muon_workspace_bytes(h, ctypes.byref(b)))
+        self.muon_workspace_bytes = b.value
 
     def orthogonalize(self, M, Y, workspace, stream=None):
         ws = _ptr(workspace)
@@ -214,6 +226,21 @@ class Plan:
         ldy = (ctypes.c_int64 * n)(*[int(y.stride(0)) for y in Ys])
         nb = self.workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
         _check(self._L.ifnso_orthogonalize_batched(self._h, mp, ldm, yp, ldy, _ptr(workspace), nb, _stream(stream)))
+
+    def muon_step(self, Ws, Gs, Bs, workspace, lr, momentum, weight_decay=0.0, nesterov=True, stream=None):
+        """One Muon step (ifnso_muon_step): Ws, Bs float32 weights and momentum (updated in place),
+        Gs gradients in the plan's input type, workspace of muon_workspace_bytes."""
+        n = len(Ws)
+        wp = (ctypes.c_void_p * n)(*[_ptr(w) for w in Ws])
+        gp = (ctypes.c_void_p * n)(*[_ptr(g) for g in Gs])
+        bp = (ctypes.c_void_p * n)(*[_ptr(b) for b in Bs])
+        ldw = (ctypes.c_int64 * n)(*[int(w.stride(0)) for w in Ws])
+        ldg = (ctypes.c_int64 * n)(*[int(g.stride(0)) for g in Gs])
+        ldb = (ctypes.c_int64 * n)(*[int(b.stride(0)) for b in Bs])
+        hp = MuonParams(float(lr), float(momentum), float(weight_decay), 1 if nesterov else 0)
+        nb = self.muon_workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
+        _check(self._L.ifnso_muon_step(self._h, ctypes.byref(hp), wp, ldw, gp, ldg, bp, ldb, _ptr(workspace), nb,
+                                       _stream(stream)))
 
     @property
     def num_launches(self) -> int:

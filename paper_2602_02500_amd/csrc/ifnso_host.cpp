@@ -283,6 +283,11 @@ struct ifnso_plan_s {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2 * kSlotsRing] = {};  // per table slot, generic / fast I/O
   std::vector<hipEvent_t> stage_events;  // pending measurement request (one call)
+  // Muon steps: pinned staging of the problem table (allocated on first use) and the event of
+  // the last step that read it
+  MuonProb *h_muon = nullptr;
+  hipEvent_t ev_muon = nullptr;
+  bool ev_muon_used = false;
   std::mutex mu;
 };
 
@@ -598,6 +603,11 @@ extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
     if (p->d_table[s]) (void)hipFree(p->d_table[s]);
     if (p->h_table[s]) (void)hipHostFree(p->h_table[s]);
   }
+  if (p->ev_muon) {
+    (void)hipEventSynchronize(p->ev_muon);
+    (void)hipEventDestroy(p->ev_muon);
+  }
+  if (p->h_muon) (void)hipHostFree(p->h_muon);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_coef) (void)hipFree(p->d_coef);
@@ -995,6 +1005,140 @@ extern "C" ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t p, const void *
   if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (!M || !ldm || !Y || !ldy) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL pointer array");
   return run_batched(p, M, ldm, Y, ldy, workspace, workspace_bytes, (hipStream_t)stream, false);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Muon step
+// ---------------------------------------------------------------------------------------------
+// Workspace of a Muon step: the plan's own, then per problem the orthogonalisation input U and
+// output Y (rows x round_up(cols, 8), the plan's input and output types), then the device table.
+struct MuonLayout {
+  std::vector<size_t> off_u, off_y;
+  std::vector<int64_t> ld;
+  size_t off_table = 0, bytes = 0;
+};
+
+static MuonLayout muon_layout(const ifnso_plan_s *p) {
+  MuonLayout m;
+  size_t o = align_up(p->ws_bytes, kAlign);
+  const size_t ies = p->in_dtype == IFNSO_F32 ? 4 : 2, oes = p->out_dtype == IFNSO_F32 ? 4 : 2;
+  for (int i = 0; i < p->num; i++) {
+    const ProbLayout &L = p->lay[i];
+    const int64_t ld = round_up(L.cols, 8);
+    m.ld.push_back(ld);
+    m.off_u.push_back(o);
+    o = align_up(o + (size_t)L.rows * ld * ies, kAlign);
+    m.off_y.push_back(o);
+    o = align_up(o + (size_t)L.rows * ld * oes, kAlign);
+  }
+  m.off_table = o;
+  m.bytes = align_up(o + (size_t)p->num * sizeof(MuonProb), kAlign);
+  return m;
+}
+
+extern "C" ifnso_status ifnso_muon_workspace_bytes(ifnso_plan_t p, size_t *bytes) {
+  if (!p || !bytes) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = muon_layout(p).bytes;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_muon_step(ifnso_plan_t p, const ifnso_muon_params *hp, float *const *W,
+                                        const int64_t *ldw, const void *const *G, const int64_t *ldg,
+                                        float *const *B, const int64_t *ldb, void *workspace,
+                                        size_t workspace_bytes, void *stream) {
+  if (!p || !hp) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!W || !ldw || !G || !ldg || !B || !ldb) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL pointer array");
+  if (!std::isfinite(hp->lr) || !std::isfinite(hp->momentum) || !std::isfinite(hp->weight_decay) ||
+      (hp->nesterov != 0 && hp->nesterov != 1))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "Muon parameters must be finite, nesterov 0 or 1");
+  const MuonLayout m = muon_layout(p);
+  if (!workspace) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < m.bytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, a Muon step needs %zu", workspace_bytes,
+                m.bytes);
+  if ((uintptr_t)workspace % kAlign) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace must be %zu-byte aligned", kAlign);
+  const size_t ies = p->in_dtype == IFNSO_F32 ? 4 : 2;
+  for (int i = 0; i < p->num; i++) {
+    const ProbLayout &L = p->lay[i];
+    if (!W[i] || !G[i] || !B[i]) return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: NULL matrix pointer", i);
+    if (ldw[i] < L.cols || ldg[i] < L.cols || ldb[i] < L.cols)
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: leading dimension smaller than cols (%lld)", i,
+                  (long long)L.cols);
+    const size_t wb = matrix_bytes(L.rows, ldw[i], L.cols, 4), bb = matrix_bytes(L.rows, ldb[i], L.cols, 4),
+                 gb = matrix_bytes(L.rows, ldg[i], L.cols, ies);
+    if (ranges_overlap(W[i], wb, B[i], bb) || ranges_overlap(W[i], wb, G[i], gb) || ranges_overlap(B[i], bb, G[i], gb))
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: W, G and the momentum buffer must not overlap", i);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char *base = (char *)workspace;
+  std::vector<const void *> U(p->num);
+  std::vector<void *> Y(p->num);
+  struct DeviceGuard {  // makes the plan's device current for a scope
+    int prev = 0, dev;
+    hipError_t e;
+    explicit DeviceGuard(int d) : dev(d) {
+      e = hipGetDevice(&prev);
+      if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+      if (prev != dev) (void)hipSetDevice(prev);
+    }
+  };
+  MuonArgs a;
+  int per = 1;
+  {
+    std::lock_guard<std::mutex> lock(p->mu);  // the staging table is the plan's
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.e);
+    if (!p->h_muon) {
+      HIP_TRY(hipHostMalloc((void **)&p->h_muon, (size_t)p->num * sizeof(MuonProb), 0));
+      HIP_TRY(hipEventCreateWithFlags(&p->ev_muon, hipEventDisableTiming));
+    }
+    if (p->ev_muon_used) HIP_TRY(hipEventSynchronize(p->ev_muon));  // staging free again
+    const double lr = hp->lr;
+    for (int i = 0; i < p->num; i++) {
+      const ProbLayout &L = p->lay[i];
+      MuonProb &q = p->h_muon[i];
+      q.W = W[i];
+      q.G = G[i];
+      q.B = B[i];
+      q.U = base + m.off_u[i];
+      q.Y = base + m.off_y[i];
+      q.rows = L.rows;
+      q.cols = L.cols;
+      q.ldw = ldw[i];
+      q.ldg = ldg[i];
+      q.ldb = ldb[i];
+      q.ldu = m.ld[i];
+      q.ldy = m.ld[i];
+      q.step = (float)(lr * std::sqrt(std::max(1.0, (double)L.rows / (double)L.cols)));
+      const bool a16 = ((uintptr_t)W[i] % 16) == 0 && ((uintptr_t)B[i] % 16) == 0 && ((uintptr_t)G[i] % (4 * ies)) == 0;
+      q.vec = (L.cols % 4 == 0 && ldw[i] % 4 == 0 && ldb[i] % 4 == 0 && ldg[i] % 4 == 0 && a16) ? 1 : 0;
+      U[i] = q.U;
+      Y[i] = const_cast<void *>(q.Y);
+    }
+    MuonProb *d_table = (MuonProb *)(base + m.off_table);
+    HIP_TRY(hipMemcpyAsync(d_table, p->h_muon, (size_t)p->num * sizeof(MuonProb), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(p->ev_muon, s));
+    p->ev_muon_used = true;
+    a.probs = d_table;
+    a.momentum = hp->momentum;
+    a.decay = (float)(1.0 - lr * hp->weight_decay);
+    a.nesterov = hp->nesterov;
+    a.in_bf16 = p->in_dtype == IFNSO_BF16;
+    a.out_bf16 = p->out_dtype == IFNSO_BF16;
+    int64_t most = 1;
+    for (const ProbLayout &L : p->lay) most = std::max<int64_t>(most, L.rows * L.cols);
+    per = (int)std::max<int64_t>(1, std::min<int64_t>((most / 4 + kThreads - 1) / kThreads,
+                                                      std::max(1, 8 * p->cus / p->num)));
+    HIP_TRY(launch_muon_pre(a, p->num, per, s));
+  }
+  ifnso_status st = run_batched(p, U.data(), m.ld.data(), Y.data(), m.ld.data(), workspace, p->ws_bytes, s, false);
+  if (st != IFNSO_OK) return st;
+  DeviceGuard dg(p->device);
+  HIP_TRY(dg.e);
+  HIP_TRY(launch_muon_post(a, p->num, per, s));
+  return IFNSO_OK;
 }
 
 // ---------------------------------------------------------------------------------------------

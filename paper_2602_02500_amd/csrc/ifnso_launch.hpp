@@ -52,4 +52,30 @@ hipError_t launch_learned(const StageArgs &a, int nprob, const float *params, co
 
 hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
 
+// Muon step around a batched orthogonalisation (ifnso_muon.hip)
+struct MuonProb {
+  float *W;         // rows x cols float32, leading dimension ldw
+  const void *G;    // gradient, the plan's input type, ldg
+  float *B;         // momentum, float32, ldb
+  void *U;          // orthogonalisation input (plan's input type), ldu
+  const void *Y;    // orthogonalised update (plan's output type), ldy
+  int64_t rows, cols, ldw, ldg, ldb, ldu, ldy;
+  float step;       // lr * sqrt(max(1, rows / cols))
+  int32_t vec;      // cols % 4 == 0, every leading dimension % 4 == 0 and 16-byte aligned bases
+};
+
+struct MuonArgs {
+  const MuonProb *probs;  // device table
+  float momentum;
+  float decay;            // 1 - lr * weight_decay
+  int32_t nesterov;
+  int32_t in_bf16;        // G and U are bfloat16 (else float32)
+  int32_t out_bf16;       // Y is bfloat16 (else float32)
+};
+
+// B = momentum B + G; U = Nesterov ? G + momentum B : B (one grid row per problem)
+hipError_t launch_muon_pre(const MuonArgs &a, int nprob, int per_problem, hipStream_t s);
+// W = decay W - step Y
+hipError_t launch_muon_post(const MuonArgs &a, int nprob, int per_problem, hipStream_t s);
+
 }  // namespace ifnso
