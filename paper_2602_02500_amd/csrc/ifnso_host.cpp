@@ -1127,10 +1127,11 @@ extern "C" ifnso_status ifnso_muon_step(ifnso_plan_t p, const ifnso_muon_params 
     a.nesterov = hp->nesterov;
     a.in_bf16 = p->in_dtype == IFNSO_BF16;
     a.out_bf16 = p->out_dtype == IFNSO_BF16;
+    // one grid row per problem, sized for the largest (workgroups of smaller problems run out
+    // of work and exit): about 8 resident workgroups per CU over the largest problem's span
     int64_t most = 1;
     for (const ProbLayout &L : p->lay) most = std::max<int64_t>(most, L.rows * L.cols);
-    per = (int)std::max<int64_t>(1, std::min<int64_t>((most / 4 + kThreads - 1) / kThreads,
-                                                      std::max(1, 8 * p->cus / p->num)));
+    per = (int)std::max<int64_t>(1, std::min<int64_t>((most / 4 + kThreads - 1) / kThreads, 8 * p->cus));
     HIP_TRY(launch_muon_pre(a, p->num, per, s));
   }
   ifnso_status st = run_batched(p, U.data(), m.ld.data(), Y.data(), m.ld.data(), workspace, p->ws_bytes, s, false);
