@@ -7,7 +7,7 @@ namespace ifnso {
 constexpr int kMaxTerms = 16;
 constexpr int kSlots = 17;       // coefficient slot 0: exponent 0; slot 1 + j: exponent 2^j
 constexpr int kMaxLevels = 18;   // levels 1..17 (level l holds B^(2^(l-1)))
-constexpr int kThreads = 256;    // every GEMM workgroup: 4 waves of 64
+constexpr int kThreads = 256;    // generic 128-tile GEMMs and the memory-bound passes: 4 waves of 64
 constexpr int kFeat = 8;         // learned mode: traces tr(G^(2^j)), j = 0..7
 
 enum Basis : int32_t { kGram = 0, kComplement = 1 };

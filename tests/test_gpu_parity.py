@@ -248,7 +248,8 @@ def test_orth_error_float64(torch_dev):
 
 # shapes whose rows are 16-byte aligned (cols % 8 == 0): the bfloat16 plans route the Gram and
 # the product through the 256-tile kernels; ragged 256-tile edges in both orientations
-FAST_SHAPES = [(512, 1536), (1536, 512), (264, 776), (776, 264), (8, 4096), (4096, 8), (256, 256)]
+FAST_SHAPES = [(512, 1536), (1536, 512), (264, 776), (776, 264), (8, 4096), (4096, 8), (256, 256), (1001, 264),
+               (203, 520)]
 
 
 @pytest.mark.parametrize("shape", FAST_SHAPES)
