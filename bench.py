@@ -99,7 +99,8 @@ def stage_flops(shapes, J):
 
 
 # kernel of a bench launch name -> its name in the rocprofv3 traffic summary
-PROFILE_KERNEL = {"square": "kf_square<true, false>", "gram_wide": "kf_gram<false, false>",
+PROFILE_KERNEL = {"square": "kf_square<true, false, false>", "square_last": "kf_square<true, false, true>",
+                  "gram_wide": "kf_gram<false, false>",
                   "gram_tall": "kf_gram<true, false>", "product_wide": "kf_product<false, false>",
                   "product_tall": "kf_product<true, false>",
                   "aggregate": "kf_aggregate"}
@@ -603,8 +604,10 @@ def main():
     nl = plan.num_launches
     J = nl - 6
     fl = stage_flops(shapes, J)
-    # kernel of each launch slot (squaring levels share one kernel)
-    names = ["prep"] + ["gram_wide", "gram_tall"] + ["square"] * J + ["aggregate", "product_wide", "product_tall"]
+    # kernel of each launch slot (squaring levels share one kernel; the last one forms P, the
+    # aggregation folded into its epilogue, and leaves the aggregate slot empty)
+    names = ["prep"] + ["gram_wide", "gram_tall"] + ["square"] * (J - 1) + ["square_last"] + \
+        ["aggregate", "product_wide", "product_tall"]
 
     t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
     kern, elapsed, graph_ms = t["kern"], t["elapsed"], t["graph_ms"]

@@ -77,6 +77,8 @@ struct StageArgs {
   int32_t xcd_cnt[8];
   int32_t wg_per_xcd;  // host only: workgroups per XCD of a fast launch
   int32_t split;       // complement basis, fast path: operands stored as split bf16 pairs
+  int32_t fuse_agg;    // level layout: the last squaring forms P (no separate aggregate stage)
+  int32_t p_slot;      // level layout: the level slot that holds P for the product
   ProbDev one;         // the problem of a single-problem launch
 };
 

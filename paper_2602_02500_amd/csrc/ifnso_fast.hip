@@ -737,17 +737,81 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   }
 }
 
+// Last squaring with the aggregation folded in (level layout): instead of storing level J + 1,
+// the tile of P = c_{J+1} S_{J+1} L_{J+1} + sum_{l <= J} c_l S_l L_l is formed from the float32
+// accumulators (c_last = c_{J+1} S_J^2 times acc is the first term; the stored level would be
+// F_J acc with S_{J+1} = S_J^2 / F_J) and the same tile of each stored level (symmetric, so the
+// upper tile gives the mirror too), and stored, tile and mirror, in level slot J + 1. wl[l]
+// holds c_l S_l (shared memory).
+__device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char *smem, const float *wl,
+                                              const ProbDev &P, int J, const Task &task, float c_last) {
+  float *ep = (float *)smem;
+  const int m0 = task.tm * BM, n0 = task.tn * BN;
+  const bool diag = task.tm == task.tn;
+  const int64_t hp = P.hp;
+  uint16_t *dst = (uint16_t *)((char *)P.lv + (int64_t)J * P.lv_stride);
+  constexpr int RS = NT / 64;  // rows per iteration; a wave reads one staged row
+  const int row0 = threadIdx.x >> 6, c4 = (threadIdx.x & 63) * 4;
+  for (int half = 0; half < 2; half++) {
+    stage_half(acc, ep, half);
+    __syncthreads();
+    float *src = ep + row0 * EP_LD + c4;
+    const char *lb = (const char *)P.lv + ((int64_t)(m0 + half * 128 + row0) * hp + n0 + c4) * 2;
+    // two row groups per pass, levels four at a time: up to eight 8-byte loads in flight
+    constexpr int UR = 2, UL = 4;
+    for (int it = 0; it < 128 / RS; it += UR) {
+      float4 v[UR];
+#pragma unroll
+      for (int u = 0; u < UR; u++) {
+        v[u] = *(const float4 *)(src + (it + u) * RS * EP_LD);
+        v[u] = make_float4(c_last * v[u].x, c_last * v[u].y, c_last * v[u].z, c_last * v[u].w);
+      }
+      for (int l0 = 1; l0 <= J; l0 += UL) {
+        uint2 q[UR][UL];
+#pragma unroll
+        for (int u = 0; u < UR; u++)
+#pragma unroll
+          for (int k = 0; k < UL; k++)
+            q[u][k] = l0 + k <= J ? *(const uint2 *)(lb + (int64_t)uni((it + u) * RS) * hp * 2 +
+                                                     (int64_t)(l0 + k - 1) * P.lv_stride)
+                                  : make_uint2(0, 0);
+#pragma unroll
+        for (int k = 0; k < UL; k++) {
+          const float w = l0 + k <= J ? wl[l0 + k] : 0.f;
+#pragma unroll
+          for (int u = 0; u < UR; u++) {
+            v[u].x += w * __uint_as_float(q[u][k].x << 16);
+            v[u].y += w * __uint_as_float(q[u][k].x & 0xffff0000u);
+            v[u].z += w * __uint_as_float(q[u][k].y << 16);
+            v[u].w += w * __uint_as_float(q[u][k].y & 0xffff0000u);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UR; u++) *(float4 *)(src + (it + u) * RS * EP_LD) = v[u];
+    }
+    __syncthreads();
+    emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
 // SPLIT (complement basis): the operand is a split pair [D_hi | D_lo]; the product runs over
 // K = 3 hp as D_hi D_hi + D_hi D_lo + D_lo D_hi, and the next operand is written split.
-template <bool AGG, bool SPLIT = false>
+// FUSE (level layout, last squaring only): the aggregation is folded into the epilogue
+// (store_p_fused) instead of storing the last level.
+template <bool AGG, bool SPLIT = false, bool FUSE = false>
 __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
   static_assert(!(AGG && SPLIT), "split operands are a complement-basis option");
+  static_assert(!FUSE || AGG, "the aggregation folds into level-layout squarings");
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  __shared__ float wl[kMaxLevels];  // fused aggregation: c_l S_l of the stored levels
   float *ep = (float *)smem;
   const int level = a.level;
+  constexpr bool fuse = FUSE;
   int cur_p = -1;
   float f_out = 1.f, c_acc = 0.f, c_first = 0.f, alpha = 1.f, c_next = 0.f, dscale = 1.f;
   const TaskRange tr = task_range(a);
@@ -766,6 +830,13 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
         f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt));
         c_acc = (float)(P.coef[level + 1] * S * S);
         c_first = (float)(P.coef[1] * sc.sg);
+        if constexpr (fuse) {  // weights of the stored levels 1..J (the same recursion as level_scale)
+          double Sl = sc.sg;
+          for (int l = 1; l <= level; l++) {
+            if (threadIdx.x == 0) wl[l] = (float)(P.coef[l] * Sl);
+            Sl = Sl * Sl / pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+          }
+        }
       } else {
         alpha = (float)(level == 1 ? sc.sg * sc.sg : 1.0);
         dscale = (float)(-sc.sg);
@@ -791,7 +862,8 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
     if constexpr (AGG) {
-      store_level<false>(acc, smem, P, level + 1, task, f_out);
+      if constexpr (fuse) store_p_fused(acc, smem, wl, P, level, task, c_acc);  // wl written before the mainloop
+      else store_level<false>(acc, smem, P, level + 1, task, f_out);
       continue;
     } else {
     for (int half = 0; half < 2; half++) {
@@ -961,7 +1033,8 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
     const uint32_t mbytes = (uint32_t)(((int64_t)(TRANS ? P.w : P.h) - 1) * P.ldm * 2 + (int64_t)(TRANS ? P.h : P.w) * 2);
     const Operand Mo = make_operand(P.M, mbytes, (uint32_t)(P.ldm * 2), P.w);
     const int64_t ldp = SPLIT ? 2 * hp : hp;
-    const Operand Po = make_operand(a.agg ? P.lv : P.opnd[a.J & 1], (uint32_t)(hp * ldp * 2), (uint32_t)(ldp * 2), P.hp);
+    const void *pp = a.agg ? (const void *)((const char *)P.lv + (int64_t)a.p_slot * P.lv_stride) : P.opnd[a.J & 1];
+    const Operand Po = make_operand(pp, (uint32_t)(hp * ldp * 2), (uint32_t)(ldp * 2), P.hp);
     const int Kp = uni(P.h);
     f32x16 acc[FM][FN];
     const int rows_out = P.trans ? P.w : P.h, cols_out = P.trans ? P.h : P.w;
@@ -1112,7 +1185,9 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
     else if (split) hipLaunchKernelGGL((fast::kf_gram<false, true>), dim3(grid), dim3(fast::NT), 0, s, a);
     else hipLaunchKernelGGL((fast::kf_gram<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
   } else if (stage == kStageSquare) {
-    if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
+    if (a.agg && a.fuse_agg && a.last)
+      hipLaunchKernelGGL((fast::kf_square<true, false, true>), dim3(grid), dim3(fast::NT), 0, s, a);
+    else if (a.agg) hipLaunchKernelGGL((fast::kf_square<true, false>), dim3(grid), dim3(fast::NT), 0, s, a);
     else if (split) hipLaunchKernelGGL((fast::kf_square<false, true>), dim3(grid), dim3(fast::NT), 0, s, a);
     else hipLaunchKernelGGL((fast::kf_square<false, false>), dim3(grid), dim3(fast::NT), 0, s, a);
   } else {

@@ -257,6 +257,7 @@ struct ifnso_plan_s {
   bool learned = false;
   bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
   bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
+  bool fuse_agg = false;  // level layout, fixed coefficients, bf16: the last squaring forms P
   int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
@@ -500,6 +501,9 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (p->learned && !p->agg)
     return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
   p->Jsq = p->learned ? p->J + 2 : p->J;
+  // the aggregation needs the coefficients before the last squaring: not in learned mode (the
+  // network reads the last levels), and the e4m3 squarings keep their own epilogue
+  p->fuse_agg = p->agg && !p->learned && !p->e4m3 && p->J >= 1;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
@@ -633,6 +637,8 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   a.learned = 0;
   a.agg = p->agg ? 1 : 0;
   a.split = p->split ? 1 : 0;
+  a.fuse_agg = p->fuse_agg ? 1 : 0;
+  a.p_slot = p->fuse_agg ? p->J : 0;  // P lands in level slot J + 1 (index J), else in level 1
   return a;
 }
 
@@ -776,7 +782,7 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     e = launch_learned(b, p->num, p->d_params, p->d_fixed, s);
     if (e != hipSuccess) return e;
   }
-  if (p->agg) {
+  if (p->agg && !p->fuse_agg) {
     a.ntasks = one ? (int)(((int64_t)L0->hp * L0->hp + kAggChunk - 1) / kAggChunk) : p->n_agg;
     if (!one) a.tasks = p->d_tasks + p->off_agg;
     e = launch_aggregate(a, std::max(1, std::min(a.ntasks, 8 * cus)), s);

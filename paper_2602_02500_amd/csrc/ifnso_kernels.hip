@@ -313,7 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
       sc0 = (float)(sout * c0);
       sps = (float)(sout * ps);
     }
-    const T *Pb = (const T *)(a.agg ? P.lv : P.opnd[a.J & 1]);
+    const T *Pb = (const T *)(a.agg ? (const void *)((const char *)P.lv + (int64_t)a.p_slot * P.lv_stride)
+                                    : P.opnd[a.J & 1]);
     const int64_t hp = P.hp;
     // geometry: source X_k, destination, orientation of the computed tile
     const bool ns = a.ns_step >= 0;
