@@ -742,9 +742,12 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
 // accumulators (c_last = c_{J+1} S_J^2 times acc is the first term; the stored level would be
 // F_J acc with S_{J+1} = S_J^2 / F_J) and the same tile of each stored level (symmetric, so the
 // upper tile gives the mirror too), and stored, tile and mirror, in level slot J + 1. wl[l]
-// holds c_l S_l (shared memory).
+// holds c_l S_l (shared memory). ROUND (e4m3 plans, whose levels are all stored in bf16): the
+// last level enters as w_last bf16(f_store acc), exactly as a stored level J + 1 would.
+template <bool ROUND = false>
 __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char *smem, const float *wl,
-                                              const ProbDev &P, int J, const Task &task, float c_last) {
+                                              const ProbDev &P, int J, const Task &task, float c_last,
+                                              float f_store = 1.f) {
   float *ep = (float *)smem;
   const int m0 = task.tm * BM, n0 = task.tn * BN;
   const bool diag = task.tm == task.tn;
@@ -764,7 +767,11 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
 #pragma unroll
       for (int u = 0; u < UR; u++) {
         v[u] = *(const float4 *)(src + (it + u) * RS * EP_LD);
-        v[u] = make_float4(c_last * v[u].x, c_last * v[u].y, c_last * v[u].z, c_last * v[u].w);
+        if constexpr (ROUND)
+          v[u] = make_float4(c_last * bf16_value(f_store * v[u].x), c_last * bf16_value(f_store * v[u].y),
+                             c_last * bf16_value(f_store * v[u].z), c_last * bf16_value(f_store * v[u].w));
+        else
+          v[u] = make_float4(c_last * v[u].x, c_last * v[u].y, c_last * v[u].z, c_last * v[u].w);
       }
       for (int l0 = 1; l0 <= J; l0 += UL) {
         uint2 q[UR][UL];
@@ -862,7 +869,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
     if constexpr (AGG) {
-      if constexpr (fuse) store_p_fused(acc, smem, wl, P, level, task, c_acc);  // wl written before the mainloop
+      if constexpr (fuse) store_p_fused<false>(acc, smem, wl, P, level, task, c_acc);  // wl written before the mainloop
       else store_level<false>(acc, smem, P, level + 1, task, f_out);
       continue;
     } else {
@@ -957,11 +964,15 @@ __global__ __launch_bounds__(NT, 1) void kf_gram8(const StageArgs a) {
   }
 }
 
+// FUSE: last squaring with the aggregation folded in (store_p_fused, the last level rounded to
+// bf16 as a stored level would be).
+template <bool FUSE = false>
 __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
+  __shared__ float wl[kMaxLevels];
   const int level = a.level;
   int cur_p = -1;
-  float f_out = 1.f;
+  float f_out = 1.f, w_last = 0.f;
   const TaskRange tr = task_range(a);
   for (int t = tr.start; t < tr.end; t += tr.stride) {
     Task task = fetch(a, tr.base + t, kStageSquare);
@@ -974,12 +985,25 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
       const int64_t nt2 = (int64_t)P.nt * P.nt;
       f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt)) *
               inv_square(P.q_scale[2 * level]);
+      if constexpr (FUSE) {  // c_l S_l of the stored levels 1..J, and c_{J+1} S_{J+1}
+        double Sl = scalars(P, a.norm).sg;
+        for (int l = 1; l <= level + 1; l++) {
+          const float w = (float)(P.coef[l] * Sl);
+          if (l <= level) {
+            if (threadIdx.x == 0) wl[l] = w;
+            Sl = Sl * Sl / pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+          } else {
+            w_last = w;
+          }
+        }
+      }
     }
     const int64_t hp = P.hp;
     const Operand op = make_operand(P.q8, (uint32_t)(hp * hp), (uint32_t)hp, P.hp);
     f32x16 acc[FM][FN];
     mainloop<false, false, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, uni(P.h), false);
-    store_level<true>(acc, smem, P, level + 1, task, f_out);
+    if constexpr (FUSE) store_p_fused<true>(acc, smem, wl, P, level, task, w_last, f_out);
+    else store_level<true>(acc, smem, P, level + 1, task, f_out);
   }
 }
 
@@ -1202,7 +1226,8 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
 hipError_t launch_e4m3_gemm(int stage, const StageArgs &a, int grid, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   if (stage == kStageGram) hipLaunchKernelGGL(fast::kf_gram8, dim3(grid), dim3(fast::NT), 0, s, a);
-  else hipLaunchKernelGGL(fast::kf_square8, dim3(grid), dim3(fast::NT), 0, s, a);
+  else if (a.fuse_agg && a.last) hipLaunchKernelGGL(fast::kf_square8<true>, dim3(grid), dim3(fast::NT), 0, s, a);
+  else hipLaunchKernelGGL(fast::kf_square8<false>, dim3(grid), dim3(fast::NT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -257,7 +257,7 @@ struct ifnso_plan_s {
   bool learned = false;
   bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
   bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
-  bool fuse_agg = false;  // level layout, fixed coefficients, bf16: the last squaring forms P
+  bool fuse_agg = false;  // level layout with fixed coefficients: the last squaring forms P
   int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
@@ -502,8 +502,8 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
     return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
   p->Jsq = p->learned ? p->J + 2 : p->J;
   // the aggregation needs the coefficients before the last squaring: not in learned mode (the
-  // network reads the last levels), and the e4m3 squarings keep their own epilogue
-  p->fuse_agg = p->agg && !p->learned && !p->e4m3 && p->J >= 1;
+  // network reads the last levels)
+  p->fuse_agg = p->agg && !p->learned && p->J >= 1;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
