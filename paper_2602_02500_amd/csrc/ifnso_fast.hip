@@ -57,11 +57,8 @@ __device__ __forceinline__ const void *uni(const void *p) {
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(uni(p)), (short)0, (int)uni(bytes), 0x00020000);
-}
-
-// The same descriptor as four scalar words (base, stride 0, record count, gfx9 format word).
+// Buffer resource descriptor of `bytes` bytes at p, as four scalar words (base, stride 0,
+// record count, gfx9 format word): offsets at or beyond the record count read as zero.
 __device__ __forceinline__ i32x4 rsrc_words(const void *p, uint32_t bytes) {
   const uint64_t a = (uint64_t)uni(p);
   i32x4 r;
@@ -117,15 +114,13 @@ __device__ __forceinline__ void wait_vmcnt() {
 // the 256 x 256 mainloop: acc = Aop[am0.., :K] * Bop[bn0.., :K]^T
 // ---------------------------------------------------------------------------------------------
 struct Operand {
-  __amdgpu_buffer_rsrc_t r;
-  i32x4 w;           // the same descriptor as words, for the LDS-DMA loads
+  i32x4 w;           // buffer descriptor words, for the LDS-DMA loads
   uint32_t ld_bytes;
   int lim;           // rows (M/N index) in range
 };
 
 __device__ __forceinline__ Operand make_operand(const void *p, uint32_t bytes, uint32_t ld_bytes, int lim) {
   Operand o;
-  o.r = rsrc(p, bytes);
   o.w = rsrc_words(p, bytes);
   o.ld_bytes = uni(ld_bytes);
   o.lim = uni(lim);
