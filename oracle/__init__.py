@@ -9,3 +9,4 @@ from .coeffs import *  # noqa: F401,F403
 from .mlp import *  # noqa: F401,F403
 from . import fp8  # noqa: F401
 from .muon import *  # noqa: F401,F403
+from . import baselines  # noqa: F401

@@ -23,7 +23,7 @@ from .gen import uniform_np
 __all__ = [
     "MUON_ABC", "CUBIC_ABC", "D1_EXPONENTS", "D2_EXPONENTS", "d1_coeffs", "LAYER_SHAPES",
     "d3_shapes", "d3_seed", "load_coeffs", "D4_SHAPE", "D4_BATCH", "d4_seed", "d4_sigma", "d2_sigma_np",
-    "PAPER_L",
+    "PAPER_L", "load_schedule",
 ]
 
 # Muon's quintic coefficients, Eq. (iteration_jordan).
@@ -81,3 +81,12 @@ def load_coeffs(name: str = "gform_v1"):
     with open(path) as f:
         d = json.load(f)[name]
     return tuple(d["exponents"]), np.array(d["coeffs"], dtype=np.float64)
+
+
+def load_schedule(name: str):
+    """Newton-Schulz step schedules stored next to this module (written by the oracle's
+    script). Returns (list of (a, b, c) per step, gelfand_q)."""
+    path = os.path.join(os.path.dirname(__file__), "coeffs.json")
+    with open(path) as f:
+        d = json.load(f)[name]
+    return [tuple(float(v) for v in abc) for abc in d["schedule"]], int(d["gelfand_q"])
