@@ -16,7 +16,9 @@ U diag(sigma) V^T with Haar factors and sigma_i = i^-1.5 (seed 3), e4m3 Gram and
 with per-tensor scales, bfloat16 aggregation and product; it reports the error of the
 e4m3 and bfloat16 modes against the FP64 oracle on a sample of the batch. `--workload
 learned` trains the coefficient network and runs the set with it; `--workload tform` runs
-the paper's complement-basis form (depth 14) on the set in bfloat16.
+the paper's complement-basis form (depth 14) on the set in bfloat16; `--workload muon` runs
+whole Muon optimizer steps on the set; `--workload table1` reproduces the paper's Table 1
+comparison (five methods, three sizes) on the device.
 """
 from __future__ import annotations
 
@@ -141,6 +143,48 @@ def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
     return {"value": len(Ms_host) / dt, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
             "sample": f"layer 0 of the set ({len(Ms_host)} matrices: 2x 4096x4096, 2x 1024x4096, "
                       f"2x 14336x4096, 1x 4096x14336), float64 numpy, {dt:.1f} s"}, rel, orth
+
+
+def _oracle_threads():
+    from threadpoolctl import threadpool_info
+    return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+
+
+def cpu_baseline_learned(theta, coeffs, held):
+    """The FP64 oracle on the coefficient-network part of the learned workload: features,
+    network and polar distance^2 / h of the learned and the fixed polynomial for each held-out
+    spectrum."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    ll, lf = [], []
+    for _, _, sgm in held:
+        c, _ = oracle.mlp_forward(np.asarray(theta, dtype=np.float64), oracle.features_from_spectrum(sgm))
+        ll.append(oracle.spectral_loss(c, sgm)[0])
+        lf.append(oracle.spectral_loss(coeffs, sgm)[0])
+    dt = time.perf_counter() - t0
+    cpu = {"value": len(held) / dt, "unit": "spectra/s", "cores": _oracle_threads(), "kind": "oracle",
+           "sample": f"{len(held)} held-out spectra: features, network, polar distance of the learned and "
+                     f"fixed polynomials, float64 numpy, {dt:.1f} s"}
+    return cpu, {"learned": float(np.mean(ll)), "fixed": float(np.mean(lf)), "spectra": len(held)}
+
+
+def cpu_baseline_tform(Mh, Yd, exps, coeffs):
+    """The FP64 oracle of the complement-basis form on a bounded sample (host matrices `Mh`),
+    with the relative distance of the device results `Yd` and the oracle's orthogonality error."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    outs = [oracle.ifnso(M, exps, coeffs, "complement", "gram_frobenius") for M in Mh]
+    dt = time.perf_counter() - t0
+    rel = [float(np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)) for Y, Yo in zip(Yd, outs)]
+    orth = [float(oracle.orth_error(Yo) / np.sqrt(min(Yo.shape))) for Yo in outs]
+    cpu = {"value": len(Mh) / dt, "unit": "matrices/s", "cores": _oracle_threads(), "kind": "oracle",
+           "sample": f"layer 0's {len(Mh)} matrices of 1024x4096, complement basis, depth 14, float64 numpy, "
+                     f"{dt:.1f} s"}
+    return cpu, rel, orth
 
 
 def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
@@ -311,15 +355,14 @@ def run_learned(args, torch, dev, hip, log):
 
     import paper_2602_02500_amd as ifn
     from paper_2602_02500_amd import learn
-    from workloads import configs, spectra
-    import oracle
+    from workloads import configs, gen, spectra
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()
     samples = spectra.spectral_mixture(args.train_samples, seed=5)
     sig, nsig = spectra.pad_spectra(samples)
     sig_d, nsig_d = torch.from_numpy(sig).to(dev), torch.from_numpy(nsig).to(dev)
     log(f"generated {len(samples)} training spectra in {time.perf_counter() - t0:.1f} s")
-    params = torch.from_numpy(oracle.mlp_init(0).astype(np.float32)).to(dev)
+    params = torch.from_numpy(gen.fan_in_uniform_np(0, learn.PARAM_LAYOUT).astype(np.float32)).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = []
@@ -331,13 +374,10 @@ def run_learned(args, torch, dev, hip, log):
     last = float(torch.stack(losses[-50:]).mean())
     theta = params.cpu().numpy()
     log(f"trained {steps} steps in {train_s:.2f} s: loss {first:.4f} -> {last:.4f}")
-    # held-out spectra: mean polar distance^2 / h of learned vs fixed coefficients
-    held = spectra.spectral_mixture(1000, seed=6)
-    ll, lf = [], []
-    for _, _, sgm in held:
-        c, _ = oracle.mlp_forward(theta.astype(np.float64), oracle.features_from_spectrum(sgm))
-        ll.append(oracle.spectral_loss(c, sgm)[0])
-        lf.append(oracle.spectral_loss(coeffs, sgm)[0])
+    held_out, cpu = None, None
+    if not args.no_cpu:
+        log("running the CPU oracle on the held-out spectra ...")
+        cpu, held_out = cpu_baseline_learned(theta, coeffs, spectra.spectral_mixture(1000, seed=6))
     Ms = make_d3(torch, dev, args.layers)
     shapes = [tuple(m.shape) for m in Ms]
     n = len(Ms)
@@ -380,10 +420,9 @@ def run_learned(args, torch, dev, hip, log):
                    "exponents": list(exps), "fallback_coeffs": "gform_v1"},
         "training": {"samples": len(samples), "epochs": args.epochs, "batch": 256, "steps": steps,
                      "seconds": round(train_s, 3), "loss_first50": first, "loss_last50": last},
-        "held_out_polar_dist2_over_h": {"learned": float(np.mean(ll)), "fixed": float(np.mean(lf)),
-                                        "spectra": len(held)},
+        "held_out_polar_dist2_over_h": held_out,
         "gradset": res,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -399,7 +438,6 @@ def run_tform(args, torch, dev, hip, log):
 
     import paper_2602_02500_amd as ifn
     from workloads import configs
-    import oracle
     exps, coeffs = configs.load_coeffs("paper_L14")
     Ms = make_d3(torch, dev, args.layers)
     shapes = [tuple(m.shape) for m in Ms]
@@ -432,16 +470,14 @@ def run_tform(args, torch, dev, hip, log):
         return {"mean": float(oe.mean()), "max": float(oe.max()), "per_shape": per}
 
     err_t = orth(Ys)
-    # layer 0's Wk, Wv against the float64 oracle (13 squarings of 1024^2 in numpy)
-    rel, orth_o = [], []
-    for i in range(min(n, 7)):
-        if shapes[i] != (1024, 4096):
-            continue
-        Mh = Ms[i].float().cpu().numpy().astype(np.float64)
-        Yo = oracle.ifnso(Mh, exps, coeffs, "complement", "gram_frobenius")
-        Yg = Ys[i].float().cpu().numpy().astype(np.float64)
-        rel.append(float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)))
-        orth_o.append(float(oracle.orth_error(Yo) / np.sqrt(1024)))
+    # CPU leg: layer 0's Wk, Wv through the float64 oracle (13 squarings of 1024^2 in numpy)
+    cpu, rel, orth_o = None, None, None
+    if not args.no_cpu:
+        sel = [i for i in range(min(n, 7)) if shapes[i] == (1024, 4096)]
+        log("running the CPU oracle on layer 0's 1024x4096 matrices ...")
+        cpu, rel, orth_o = cpu_baseline_tform([Ms[i].float().cpu().numpy().astype(np.float64) for i in sel],
+                                              [Ys[i].float().cpu().numpy().astype(np.float64) for i in sel],
+                                              exps, coeffs)
     del ws, plan
     eg, cg = configs.load_coeffs("gform_v1")
     plan_g = ifn.Plan(eg, cg, shapes, compute="bf16")
@@ -462,7 +498,7 @@ def run_tform(args, torch, dev, hip, log):
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                      "avg_launch_ms": round(dur_ms, 3)},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
         "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
                         "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
                     for k, v in kern.items()},
@@ -532,6 +568,113 @@ def run_muon(args, torch, dev, hip, log):
     print(json.dumps(line), flush=True)
 
 
+TABLE1_SHAPES = ((128, 128), (128, 512), (128, 1024))
+
+
+def cpu_baseline_table1(methods, inputs):
+    """The FP64 oracle of every Table 1 method on the three inputs; its ||YY^T - I||_F."""
+    import numpy as np
+
+    import oracle
+    from oracle import baselines as BL
+    t0 = time.perf_counter()
+    errs = {}
+    for name, m in methods.items():
+        for shape, Mh in inputs.items():
+            if m["kind"] == "schedule":
+                Yo = BL.ns_schedule(Mh, m["schedule"], m["q"])
+            else:
+                Yo = oracle.ifnso(Mh, m["exps"], m["coeffs"], m["basis"], m["norm"])
+            errs[(name, shape)] = float(oracle.orth_error(Yo))
+    dt = time.perf_counter() - t0
+    calls = len(methods) * len(inputs)
+    cpu = {"value": calls / dt, "unit": "matrices/s", "cores": _oracle_threads(), "kind": "oracle",
+           "sample": f"all {calls} method x size cases of the table, float64 numpy, {dt:.2f} s"}
+    return cpu, errs
+
+
+def run_table1(args, torch, dev, hip, log):
+    """Table 1 of the paper on one MI355X: the orthogonality error ||YY^T - I||_F and the time
+    per call of Newton-Schulz with the cubic (8 steps), Muon's quintic (5 steps), Cesista-form
+    quintics (5 steps), CANS minimax quintics with Gelfand q = 2 (5 steps), and IFNSO in the
+    paper's form (complement basis, depth 14) and in the Gram basis (exponents up to 16), on
+    N(0,1) matrices 128x128, 128x512 and 128x1024 (seed 0), float32. FLOPs follow the paper's
+    dense count. The paper's own values, measured on other inputs, are printed beside them."""
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs, gen
+    methods = {}
+    for name in ("original_ns8", "muon_ns5", "cesista_ns5", "cans_ns5_q2"):
+        sched, q = configs.load_schedule(name)
+        methods[name] = {"kind": "schedule", "schedule": sched, "q": q}
+    e, c = configs.load_coeffs("paper_L14")
+    methods["ifnso_paper_L14"] = {"kind": "plan", "exps": e, "coeffs": c, "basis": "complement",
+                                  "norm": "gram_frobenius"}
+    e, c = configs.load_coeffs("gform_v1")
+    methods["ifnso_gform_v1"] = {"kind": "plan", "exps": e, "coeffs": c, "basis": "gram", "norm": "frobenius"}
+    paper_name = {"original_ns8": "original_ns", "muon_ns5": "muon_ns", "cesista_ns5": "cesista_ns",
+                  "cans_ns5_q2": "cans", "ifnso_paper_L14": "ifnso"}
+    with open(os.path.join(ROOT, "tests", "golden", "table1.json")) as f:
+        printed = {(r["method"], r["h"], r["w"]): r for r in json.load(f)["rows"]}
+    inputs = {s: gen.gaussian_np(*s, seed=0).astype(np.float32).astype(np.float64) for s in TABLE1_SHAPES}
+    reps = max(args.steps, 20)
+    rows, times = [], {}
+    for shape, Mh in inputs.items():
+        h, w = shape
+        Mt = torch.from_numpy(Mh.astype(np.float32)).to(dev)
+        Y = torch.empty_like(Mt)
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+        ows = torch.empty(ifn.orth_error_workspace_bytes(1), dtype=torch.uint8, device=dev)
+        for name, m in methods.items():
+            if m["kind"] == "schedule":
+                ws = torch.empty(ifn.classical_ns_workspace_bytes(h, w, "f32"), dtype=torch.uint8, device=dev)
+                call = lambda: ifn.ns_schedule(Mt, Y, m["schedule"], m["q"], "f32", ws)  # noqa: E731
+                steps = len(m["schedule"])
+                longp = 2 if name == "original_ns8" else 3
+                flops = steps * longp * 2.0 * h * h * w
+            else:
+                plan = ifn.Plan(m["exps"], m["coeffs"], [shape], basis=m["basis"], norm=m["norm"], compute="f32")
+                ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+                call = lambda: plan.orthogonalize(Mt, Y, ws)  # noqa: E731
+                sq = len(m["exps"]) - 2
+                flops = 4.0 * h * h * w + 2.0 * sq * h ** 3
+            for _ in range(args.warmup):
+                call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            ifn.orth_error([Y], out, ows)
+            err = float(out.item())
+            pr = printed.get((paper_name.get(name, ""), h, w))
+            rows.append({"method": name, "h": h, "w": w, "error": round(err, 4), "ms": round(dt * 1e3, 4),
+                         "flops_dense": flops, "paper_error": pr["error"] if pr else None,
+                         "paper_flops": pr["flops"] if pr else None})
+            times[(name, shape)] = dt
+            del ws
+    cpu = None
+    if not args.no_cpu:
+        log("running the CPU oracle on every case ...")
+        cpu, errs = cpu_baseline_table1(methods, inputs)
+        for r in rows:
+            r["oracle_error"] = round(errs[(r["method"], (r["h"], r["w"]))], 4)
+    value = 1.0 / times[("ifnso_paper_L14", (128, 1024))]
+    line = {
+        "metric": "Table 1 on MI355X: ||YY^T - I||_F and time per call of five orthogonalisation methods",
+        "value": round(value, 3), "unit": "matrices/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 / value, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "N(0,1) 128x128, 128x512, 128x1024 (seed 0), float32; value: IFNSO paper form on "
+                               "128x1024, one call at a time", "methods": list(methods)},
+        "roofline": None, "cpu_baseline": cpu,
+        "table": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,7 +684,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon"], default="gradset",
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon", "table1"],
+                    default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
                          "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
                          "network on the GPU, then run the gradient set with learned and fixed coefficients; "
@@ -589,6 +733,8 @@ def main():
         return run_tform(args, torch, dev, hip, log)
     if args.workload == "muon":
         return run_muon(args, torch, dev, hip, log)
+    if args.workload == "table1":
+        return run_table1(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()

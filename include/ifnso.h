@@ -226,6 +226,27 @@ ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64
 /* Workspace bytes for ifnso_classical_ns with these dimensions (0 on bad arguments). */
 size_t ifnso_classical_ns_workspace_bytes(int64_t rows, int64_t cols, int32_t compute);
 
+/* Most steps of one ifnso_ns_schedule call. */
+#define IFNSO_NS_MAX_STEPS 16
+
+/* Newton-Schulz with its own odd quintic at every step: the iterations the paper compares
+ * against in Sec. 2 (Cesista's iteration-specific coefficients, CANS' minimax polynomials),
+ * in the form of Eq. (iteration_jordan):
+ *   X_0 = A / s,  X_{k+1} = a_k X_k + (b_k G_k + c_k G_k^2) X_k,  G_k = X_k X_k^T,
+ * with A oriented as in Sec. 1 (h <= w) and the result returned in M's orientation.
+ * s = ||A||_F (gelfand_q = 0, Eq. (constraint)), or Gelfand's bound of Eq. (gelfand_formula)
+ * and Eq. (scale_formula_function), s = ||(A A^T)^q||_F^(1/(2q)), for q = gelfand_q = 1 or 2
+ * (q = 2 adds one h x h squaring of the raw Gram at the first step, for its norm only).
+ * abc: host array of `steps` triples {a_k, b_k, c_k}, read during the call; 1 <= steps <=
+ * IFNSO_NS_MAX_STEPS. M, Y, dtype, compute, workspace (ifnso_classical_ns_workspace_bytes
+ * bytes) and stream as for ifnso_classical_ns; a zero input gives a zero output.
+ * Errors: INVALID_ARGUMENT (NULL pointers, bad shapes, steps out of range, gelfand_q < 0,
+ * non-finite coefficients, Y overlapping M), UNSUPPORTED (gelfand_q > 2, dtype/compute
+ * pairs other than F32/F32 and BF16/BF16), WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_ns_schedule(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype, void *Y,
+                               int64_t ldy, int32_t steps, const double *abc, int32_t gelfand_q, int32_t compute,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
 /* The input side of the FP8_E4M3 mode on its own: A (= M, or M^T when rows > cols; h x w,
  * h <= w) quantised to OCP e4m3 with the per-tensor power-of-two scale of ifnso_compute,
  * Q[i][k] = e4m3(s A[i][k]) for k < w and 0 for w <= k < round_up(w, 16): the K-major operand

@@ -17,8 +17,9 @@ readings used here:
   for its own coefficients, experiment section), the expectation taken by Gauss-Legendre
   quadrature, by L-BFGS started from Muon's quintic on every step.
 * CANS: step k applies the odd polynomial of degree 3 or 5 that minimises max |1 - p(x)| over
-  the interval [lo_k, hi_k] known to hold the singular values (Remez exchange); the interval
-  starts at [delta, 1] and becomes [1 - E_k, 1 + E_k] after a step with minimax error E_k.
+  the interval [lo_k, hi_k] known to hold the singular values (Remez exchange), widened at the
+  top by a 2 % margin for rounding; the interval starts at [delta, 1] and becomes
+  [1 - E_k, 1 + E_k] after a step with minimax error E_k.
 
 Matrix iterations: X_{k+1} = a_k X_k + b_k (X_k X_k^T) X_k + c_k (X_k X_k^T)^2 X_k with
 numpy's matmul as the only library step. Only the tests, the smoke check and the
@@ -149,15 +150,18 @@ def minimax_odd(lo: float, hi: float, degree: int = 5, iters: int = 100, tol: fl
     return tuple(out), float(abs(E))
 
 
-def cans_schedule(steps: int, delta: float, degree: int = 5):
+def cans_schedule(steps: int, delta: float, degree: int = 5, margin: float = 0.02):
     """Per-step minimax polynomials for singular values starting in [delta, 1]; returns
-    (schedule [steps][3], intervals [steps + 1][2]). Each step maps its interval onto
-    [1 - E, 1 + E]."""
+    (schedule [steps][3], intervals [steps + 1][2]). Step k's polynomial is the minimax one
+    on [lo_k, (1 + margin) hi_k] and maps it onto [lo_{k+1}, hi_{k+1}] = [1 - E, 1 + E]. The
+    margin keeps a singular value that rounding has pushed just past hi_k inside the range
+    the polynomial was built for: each polynomial rises steeply at the top of its interval,
+    and without the margin the next one would amplify such an excess at every step."""
     lo, hi = float(delta), 1.0
     sched: List[Tuple[float, float, float]] = []
     iv = [(lo, hi)]
     for _ in range(steps):
-        abc, E = minimax_odd(lo, hi, degree)
+        abc, E = minimax_odd(lo, hi * (1.0 + margin), degree)
         sched.append(abc)
         lo, hi = 1.0 - E, 1.0 + E
         iv.append((lo, hi))

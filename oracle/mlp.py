@@ -50,17 +50,10 @@ def unpack_params(theta):
 
 
 def mlp_init(seed: int = 0) -> np.ndarray:
-    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases (float64)."""
-    from workloads.gen import uniform_np
-    parts = []
-    for i, (name, shape) in enumerate(_SHAPES):
-        n = int(np.prod(shape))
-        if name.startswith("W"):
-            bound = 1.0 / math.sqrt(shape[1])
-            parts.append((2.0 * uniform_np(seed, 100 + i, n) - 1.0) * bound)
-        else:
-            parts.append(np.zeros(n))
-    return np.concatenate(parts)
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases (float64), from the
+    seeded input generators."""
+    from workloads.gen import fan_in_uniform_np
+    return fan_in_uniform_np(seed, _SHAPES)
 
 
 def features_from_spectrum(sigma) -> np.ndarray:

@@ -19,7 +19,8 @@ q >= 1 for Gelfand's bound ||(AA^T)^q||_F^(1/(2q))):
 * original_ns8  the cubic of Eq. (one_iteration_matrix), eight steps.
 * muon_ns5      Muon's quintic of Eq. (iteration_jordan), five steps.
 * cesista_ns5   five quintics in Cesista's (gamma, r, u) form, fitted by the oracle.
-* cans_ns5_q2   five minimax quintics for singular values in [1e-3, 1], Gelfand q = 2.
+* cans_ns5_q2   five minimax quintics for singular values in [1e-3, 1] (2 % margin at the top of
+                each interval), Gelfand q = 2.
 """
 import json
 import os

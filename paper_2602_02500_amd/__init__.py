@@ -12,7 +12,7 @@ import re
 from typing import Optional, Sequence
 
 __all__ = [
-    "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes",
+    "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes", "ns_schedule",
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
     "FLAG_SPLIT_BF16",
@@ -104,6 +104,8 @@ def load() -> ctypes.CDLL:
                                   ctypes.POINTER(vp), P64, vp, sz, vp]
     L.ifnso_classical_ns.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, ctypes.POINTER(ctypes.c_double), i32,
                                      vp, sz, vp]
+    L.ifnso_ns_schedule.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, ctypes.POINTER(ctypes.c_double), i32, i32,
+                                    vp, sz, vp]
     L.ifnso_classical_ns_workspace_bytes.argtypes = [i64, i64, i32]
     L.ifnso_classical_ns_workspace_bytes.restype = sz
     L.ifnso_orth_error.argtypes = [i32, ctypes.POINTER(vp), P64, P64, P64, i32, vp, vp, sz, vp]
@@ -299,6 +301,22 @@ def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=N
     nb = workspace.numel() * workspace.element_size()
     _check(L.ifnso_classical_ns(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
                                 int(steps), abc_c, comp, _ptr(workspace), nb, _stream(stream)))
+
+
+def ns_schedule(M, Y, schedule, gelfand_q: int = 0, compute="bf16", workspace=None, stream=None):
+    """Newton-Schulz with one (a, b, c) per step (``schedule``: a sequence of triples) and the
+    input scaled by ||A||_F (gelfand_q = 0) or by ||(AA^T)^q||_F^(1/(2q)) (q = 1, 2).
+    Workspace: classical_ns_workspace_bytes(rows, cols, compute) bytes."""
+    L = load()
+    comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    rows, cols = M.shape
+    flat = [float(x) for abc in schedule for x in abc]
+    if len(flat) != 3 * len(schedule):
+        raise ValueError("schedule entries must be (a, b, c) triples")
+    abc_c = (ctypes.c_double * max(len(flat), 3))(*flat)
+    nb = workspace.numel() * workspace.element_size()
+    _check(L.ifnso_ns_schedule(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
+                               len(schedule), abc_c, int(gelfand_q), comp, _ptr(workspace), nb, _stream(stream)))
 
 
 def quantize_e4m3_workspace_bytes(rows: int, cols: int) -> int:

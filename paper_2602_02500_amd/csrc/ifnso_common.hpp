@@ -9,9 +9,12 @@ constexpr int kSlots = 17;       // coefficient slot 0: exponent 0; slot 1 + j: 
 constexpr int kMaxLevels = 18;   // levels 1..17 (level l holds B^(2^(l-1)))
 constexpr int kThreads = 256;    // generic 128-tile GEMMs and the memory-bound passes: 4 waves of 64
 constexpr int kFeat = 8;         // learned mode: traces tr(G^(2^j)), j = 0..7
+constexpr int kMaxNsSteps = 16;  // Newton-Schulz step schedules: at most this many (a, b, c)
 
 enum Basis : int32_t { kGram = 0, kComplement = 1 };
-enum Norm : int32_t { kFrob = 0, kGramFrob = 1, kNone = 2 };
+// kGelfand2 (Newton-Schulz schedules only): s = ||(A A^T)^2||_F^(1/4), from the partials of a
+// norm-only squaring of the raw Gram
+enum Norm : int32_t { kFrob = 0, kGramFrob = 1, kNone = 2, kGelfand2 = 3 };
 enum OpType : int32_t { kOpF32 = 0, kOpBF16 = 1, kOpFP8 = 2 };
 
 // One problem of a call, rebuilt by the host for every call (pointers move between calls).
@@ -65,9 +68,12 @@ struct StageArgs {
   int32_t learned;     // learned mode: keep levels, defer aggregation
   int32_t ns_step;     // classical NS: step index (-1 for IFNSO)
   int32_t ns_last;     // classical NS: last step
-  double ns_abc[3];
+  double ns_abc[3];    // classical NS: (a, b, c) of the current step
   int32_t p_empty;     // product: no terms with exponent >= 1
   int32_t ns_steps;    // classical NS: total steps (used by the h == 1 scalar path)
+  int32_t ns_nsched;   // classical NS: entries of ns_sched; step k uses entry min(k, ns_nsched - 1)
+  int32_t ns_norm_pass;  // squaring stage: only the float64 partials of ||G_raw^2||_F^2 (slot 2)
+  double ns_sched[kMaxNsSteps][3];  // classical NS: the whole schedule (h == 1 scalar path)
   // XCD-aware schedule (fast kernels): workgroup b runs on XCD b % 8 and works through that
   // XCD's task queue tasks[xcd_off[x] .. + xcd_cnt[x]) with stride gridDim.x / 8
   int32_t agg;         // level layout (Gram basis, fast path): levels kept, P formed by the

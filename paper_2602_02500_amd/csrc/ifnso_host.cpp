@@ -1164,18 +1164,22 @@ extern "C" size_t ifnso_classical_ns_workspace_bytes(int64_t rows, int64_t cols,
   return layout_problem(rows, cols, op, 1, false, true).bytes;
 }
 
-extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
-                                           void *Y, int64_t ldy, int32_t steps, const double abc[3],
-                                           int32_t compute, void *workspace, size_t workspace_bytes, void *stream) {
-  if (!M || !Y || !abc) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+// Shared by ifnso_classical_ns (one (a, b, c) for every step) and ifnso_ns_schedule (one per
+// step): step k uses sched[min(k, nsched - 1)].
+static ifnso_status run_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype, void *Y,
+                           int64_t ldy, int32_t steps, const double *sched, int32_t nsched, int32_t gelfand_q,
+                           int32_t compute, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!M || !Y || !sched) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
   if (rows < 1 || cols < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad shape");
   if (ldm < cols || ldy < cols) return fail(IFNSO_ERR_INVALID_ARGUMENT, "leading dimension smaller than cols");
   if (steps < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "steps must be >= 1");
   if (dtype != IFNSO_F32 && dtype != IFNSO_BF16) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad dtype");
   if (compute < IFNSO_COMPUTE_F32 || compute > IFNSO_COMPUTE_FP8_E4M3)
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad compute");
-  for (int i = 0; i < 3; i++)
-    if (!std::isfinite(abc[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficient not finite");
+  if (gelfand_q < 0) return fail(IFNSO_ERR_INVALID_ARGUMENT, "gelfand_q must be >= 0");
+  for (int i = 0; i < 3 * nsched; i++)
+    if (!std::isfinite(sched[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficient not finite");
+  if (gelfand_q > 2) return fail(IFNSO_ERR_UNSUPPORTED, "gelfand_q above 2 is not built");
   const int op = ns_op(compute, dtype);
   if (op < 0) return fail(IFNSO_ERR_UNSUPPORTED, "classical NS supports F32/F32 and BF16/BF16 (dtype/compute)");
   if (std::min(rows, cols) > 65536) return fail(IFNSO_ERR_UNSUPPORTED, "matrix too large");
@@ -1195,20 +1199,30 @@ extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t 
   fill_dev(a.one, L, (char *)workspace, M, ldm, Y, ldy, op, nullptr, nullptr);
   a.J = 1;
   a.basis = kGram;
-  a.norm = kFrob;
-  for (int i = 0; i < 3; i++) a.ns_abc[i] = abc[i];
+  a.norm = gelfand_q == 0 ? kFrob : gelfand_q == 1 ? kGramFrob : kGelfand2;
+  a.ns_nsched = nsched;
+  for (int k = 0; k < nsched; k++)
+    for (int i = 0; i < 3; i++) a.ns_sched[k][i] = sched[3 * k + i];
   const int nsym = L.nt * (L.nt + 1) / 2;
   hipStream_t s = (hipStream_t)stream;
   a.ns_steps = steps;
   // h == 1: the product kernel runs the scalar recursion from the float64 norm in one pass
   const int passes = L.h == 1 ? 1 : steps;
   for (int k = 0; k < passes; k++) {
+    const double *abc = sched + 3 * std::min(k, nsched - 1);
+    for (int i = 0; i < 3; i++) a.ns_abc[i] = abc[i];
     a.ns_step = k;
     a.ns_last = k == passes - 1;
     a.ntasks = nsym;
     a.level = 1;
     a.last = 1;
     HIP_TRY(launch_stage(op, kTS, kStageGram, a, grid_for(op, kStageGram, nsym, cus), 0, s));
+    if (L.h > 1 && k == 0 && gelfand_q == 2) {
+      // ||G_raw^2||_F^2 into level slot 2 before any consumer of the scale runs
+      a.ns_norm_pass = 1;
+      HIP_TRY(launch_stage(op, kTS, kStageSquare, a, grid_for(op, kStageSquare, nsym, cus), 0, s));
+      a.ns_norm_pass = 0;
+    }
     if (L.h > 1) HIP_TRY(launch_stage(op, kTS, kStageSquare, a, grid_for(op, kStageSquare, nsym, cus), 0, s));
     const bool tall_map = k == 0 && L.trans;
     const int rt = ((tall_map ? L.w : L.h) + kTS - 1) / kTS, ct = ((tall_map ? L.h : L.w) + kTS - 1) / kTS;
@@ -1219,6 +1233,22 @@ extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t 
                          dtype == IFNSO_BF16, s));
   }
   return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
+                                           void *Y, int64_t ldy, int32_t steps, const double abc[3],
+                                           int32_t compute, void *workspace, size_t workspace_bytes, void *stream) {
+  return run_ns(M, rows, cols, ldm, dtype, Y, ldy, steps, abc, 1, 0, compute, workspace, workspace_bytes, stream);
+}
+
+extern "C" ifnso_status ifnso_ns_schedule(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
+                                          void *Y, int64_t ldy, int32_t steps, const double *abc, int32_t gelfand_q,
+                                          int32_t compute, void *workspace, size_t workspace_bytes, void *stream) {
+  static_assert(IFNSO_NS_MAX_STEPS == kMaxNsSteps, "schedule bound of the header and the kernels");
+  if (steps > kMaxNsSteps)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "a schedule holds at most %d steps", kMaxNsSteps);
+  return run_ns(M, rows, cols, ldm, dtype, Y, ldy, steps, abc, std::max(steps, 1), gelfand_q, compute, workspace,
+                workspace_bytes, stream);
 }
 
 // ---------------------------------------------------------------------------------------------

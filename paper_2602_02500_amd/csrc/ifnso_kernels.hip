@@ -51,6 +51,11 @@ __device__ __forceinline__ Scalars problem_scalars(const ProbDev &P, int norm) {
     const double o = sqrt(s.g2);
     s.sg = s.zero ? 0.0 : 1.0 / o;
     s.sout = s.zero ? 0.0 : 1.0 / sqrt(o);
+  } else if (norm == kGelfand2) {
+    // s^2 = ||G_raw^2||_F^(1/2); slot 2 holds the partials of ||G_raw^2||_F^2
+    const double o = sqrt(sqrt(wave_sum_upper(P.lvl_part + (int64_t)2 * P.nt * P.nt, P.nt)));
+    s.sg = s.zero ? 0.0 : 1.0 / o;
+    s.sout = s.zero ? 0.0 : 1.0 / sqrt(o);
   } else {
     s.sg = 1.0;
     s.sout = 1.0;
@@ -221,6 +226,12 @@ __global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
           const int i = m0 + TL::row_of(fm, r), j = n0 + TL::col_of(fn);
           const int64_t ij = i * hp + j;
           const float acc = tile.acc[fm][fn][r];
+          if (a.ns_norm_pass) {
+            // Gelfand q = 2: the sum of squares of G_raw^2 only; nothing is stored
+            const double dv = (double)acc;
+            lv = fma(dv, diag ? dv : 2.0 * dv, lv);
+            continue;
+          }
           float out, pv;
           if (a.ns_step >= 0) {
             // classical NS: B = b G + c G^2 (G = s G_raw at the first step)
@@ -244,10 +255,10 @@ __global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
           if (i == j) dg += dv;
         }
     block_sum3(lv, dg, unused, (double *)smem);
-    if (threadIdx.x == 0 && a.ns_step < 0) {
+    if (threadIdx.x == 0 && (a.ns_step < 0 || a.ns_norm_pass)) {
       const int nt = P.nt;
       P.lvl_part[(int64_t)(level + 1) * nt * nt + task.tm * nt + task.tn] = lv;
-      if (diag) P.diag_part[(level + 1) * nt + task.tm] = dg;
+      if (diag && !a.ns_norm_pass) P.diag_part[(level + 1) * nt + task.tm] = dg;
     }
     __syncthreads();
   }
@@ -282,7 +293,10 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
         double v = 0.0;
         if (a.ns_step >= 0) {
           double x = 1.0;
-          for (int k = 0; k < a.ns_steps; k++) x = x * (a.ns_abc[0] + x * x * (a.ns_abc[1] + a.ns_abc[2] * x * x));
+          for (int k = 0; k < a.ns_steps; k++) {
+            const double *c = a.ns_sched[k < a.ns_nsched ? k : a.ns_nsched - 1];
+            x = x * (c[0] + x * x * (c[1] + c[2] * x * x));
+          }
           v = x;
         } else {
           const double b = (a.basis == kGram) ? g : 1.0 - g;

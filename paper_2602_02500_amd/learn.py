@@ -8,7 +8,10 @@ from __future__ import annotations
 
 from . import mlp_features, mlp_train_step, mlp_train_workspace_bytes
 
-__all__ = ["train"]
+__all__ = ["train", "PARAM_LAYOUT"]
+
+# Parameter layout of the network (float32, flattened in this order; weights output-major).
+PARAM_LAYOUT = (("W1", (64, 8)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (6, 64)), ("b3", (6,)))
 
 
 def train(sig, nsig, params, epochs: int = 1, batch: int = 256, lr: float = 1e-3, betas=(0.9, 0.999),

@@ -162,6 +162,25 @@ def test_classical_ns_argument_checks(L):
     assert L.ifnso_classical_ns_workspace_bytes(0, 8, 0) == 0
 
 
+def test_ns_schedule_argument_checks(L):
+    n = 17
+    abc = (ctypes.c_double * (3 * n))(*([3.4445, -4.775, 2.0315] * n))
+    need = L.ifnso_classical_ns_workspace_bytes(4, 8, 0)
+    args = lambda steps, q, ws=need: (1024, 4, 8, 8, 0, 1 << 30, 8, steps, abc, q, 0, 256, ws, None)
+    assert L.ifnso_ns_schedule(*args(0, 0)) == 1  # no steps
+    assert L.ifnso_ns_schedule(*args(17, 0)) == 1  # more than IFNSO_NS_MAX_STEPS
+    assert L.ifnso_ns_schedule(*args(3, -1)) == 1  # negative q
+    assert L.ifnso_ns_schedule(*args(3, 3)) == 2  # q above 2 not built
+    assert L.ifnso_ns_schedule(*args(3, 2, need - 1)) == 3
+    assert L.ifnso_ns_schedule(1024, 4, 8, 8, 0, 1 << 30, 8, 3, None, 0, 0, 256, need, None) == 1
+    bad = (ctypes.c_double * 6)(1.0, 0.0, 0.0, float("nan"), 0.0, 0.0)
+    assert L.ifnso_ns_schedule(1024, 4, 8, 8, 0, 1 << 30, 8, 2, bad, 0, 0, 256, need, None) == 1
+    assert b"finite" in L.ifnso_last_error()
+    # the header's step bound
+    with open(ifn.HEADER_PATH) as f:
+        assert "#define IFNSO_NS_MAX_STEPS 16" in f.read()
+
+
 def test_workspace_sizes_grow_with_shape(L):
     a = L.ifnso_classical_ns_workspace_bytes(256, 512, 1)
     b = L.ifnso_classical_ns_workspace_bytes(1024, 4096, 1)

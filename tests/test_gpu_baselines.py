@@ -1,0 +1,137 @@
+"""Newton-Schulz step schedules on the GPU (ifnso_ns_schedule) against the FP64 oracle: the
+baselines of the paper's comparison (Sec. 2; Table 1's methods) through the library's
+generic kernels.
+
+Tolerances (relative Frobenius distance to the oracle on the same input bytes):
+* float32: 1e-4. A float32 numpy run of the same iterations stays below 1.2e-5 on these
+  shapes for every schedule.
+* bfloat16: three times what a float64 model of the bf16 storage points (X_k, the Gram
+  operand, B_k = b G + c G^2 rounded to bf16) gives on these shapes: the schedules differ
+  widely in gain. The model gives 0.5 % (cubic, 8 steps), 1.8 % (Muon), 0.8 % (Cesista form)
+  and 5.5 % (CANS, whose first quintic has coefficients up to 25).
+"""
+import numpy as np
+import pytest
+
+from oracle import baselines as BL
+import oracle
+from workloads import configs, gen
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = ["original_ns8", "muon_ns5", "cesista_ns5", "cans_ns5_q2"]
+TOL_F32 = 1e-4
+TOL_BF16 = {"original_ns8": 1.5e-2, "muon_ns5": 6e-2, "cesista_ns5": 3e-2, "cans_ns5_q2": 0.17}
+
+
+@pytest.fixture(scope="module")
+def tdev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02500_amd as ifn
+    ifn.load()
+    return torch, torch.device("cuda:0")
+
+
+def _dev(torch, dev, M64, compute):
+    if compute == "f32":
+        v = M64.astype(np.float32)
+        return torch.from_numpy(v).to(dev), v.astype(np.float64)
+    v = gen.round_to_bf16_np(M64)
+    return torch.from_numpy(v.astype(np.float32)).to(dev).to(torch.bfloat16), v
+
+
+def _run(torch, dev, Mt, sched, q, compute):
+    import paper_2602_02500_amd as ifn
+    rows, cols = Mt.shape
+    Y = torch.full_like(Mt, float("nan"))
+    ws = torch.empty(ifn.classical_ns_workspace_bytes(rows, cols, compute), dtype=torch.uint8, device=dev)
+    ifn.ns_schedule(Mt, Y, sched, q, compute, ws)
+    torch.cuda.synchronize()
+    return Y.float().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", SCHEDULES)
+@pytest.mark.parametrize("shape", [(128, 128), (128, 512), (200, 456), (456, 200), (1, 64), (70, 1)])
+def test_schedule_f32_matches_oracle(tdev, name, shape):
+    torch, dev = tdev
+    sched, q = configs.load_schedule(name)
+    print(f"case {name} {shape} f32", flush=True)
+    Mt, vals = _dev(torch, dev, gen.gaussian_np(*shape, seed=0), "f32")
+    Y = _run(torch, dev, Mt, sched, q, "f32")
+    Yo = BL.ns_schedule(vals, sched, q)
+    r = _rel(Y, Yo)
+    print(f"  rel {r:.2e}, oracle error ||YY^T - I||_F {oracle.orth_error(Yo):.4f}")
+    assert r <= TOL_F32
+
+
+@pytest.mark.parametrize("name", SCHEDULES)
+@pytest.mark.parametrize("shape", [(128, 512), (456, 200)])
+def test_schedule_bf16_matches_oracle(tdev, name, shape):
+    torch, dev = tdev
+    sched, q = configs.load_schedule(name)
+    print(f"case {name} {shape} bf16", flush=True)
+    Mt, vals = _dev(torch, dev, gen.gaussian_np(*shape, seed=0), "bf16")
+    Y = _run(torch, dev, Mt, sched, q, "bf16")
+    Yo = BL.ns_schedule(vals, sched, q)
+    r = _rel(Y, Yo)
+    eg, eo = oracle.orth_error(Y), oracle.orth_error(Yo)
+    print(f"  rel {r:.2e}; ||YY^T - I||_F device {eg:.4f}, oracle {eo:.4f}")
+    assert r <= TOL_BF16[name]
+
+
+def test_constant_schedule_is_classical_ns_bitwise(tdev):
+    """A schedule repeating one triple runs the same launches as ifnso_classical_ns."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    Mt, _ = _dev(torch, dev, gen.gaussian_np(200, 456, seed=3), "bf16")
+    Ya = _run(torch, dev, Mt, [configs.MUON_ABC] * 5, 0, "bf16")
+    Yb = torch.empty_like(Mt)
+    ws = torch.empty(ifn.classical_ns_workspace_bytes(200, 456, "bf16"), dtype=torch.uint8, device=dev)
+    ifn.classical_ns(Mt, Yb, 5, configs.MUON_ABC, "bf16", ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(Ya, Yb.float().cpu().numpy().astype(np.float64))
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(150, 300), (300, 150)])
+def test_scaling_alone(tdev, q, shape):
+    """The identity step (a, b, c) = (1, 0, 0) returns X_0 = A / s: the scale of Eq. (constraint)
+    (q = 0) or Gelfand's bound (q = 1, 2) against its closed form on a prescribed spectrum."""
+    torch, dev = tdev
+    r = min(shape)
+    sigma = 10.0 ** np.linspace(-2.0, 0.5, r)
+    U = gen.haar_np(shape[0], r, 9, 1)
+    V = gen.haar_np(shape[1], r, 9, 2)
+    M = (U * sigma) @ V.T
+    Mt, vals = _dev(torch, dev, M, "f32")
+    Y = _run(torch, dev, Mt, [(1.0, 0.0, 0.0)], q, "f32")
+    s = np.sqrt(np.sum(sigma ** 2)) if q == 0 else np.sum(sigma ** (4 * q)) ** (1.0 / (4 * q))
+    assert _rel(Y, vals / s) <= 1e-5
+
+
+def test_zero_input_gives_zero(tdev):
+    torch, dev = tdev
+    Mt = torch.zeros((130, 260), dtype=torch.bfloat16, device=dev)
+    sched, q = configs.load_schedule("cans_ns5_q2")
+    Y = _run(torch, dev, Mt, sched, q, "bf16")
+    assert not np.any(Y)
+
+
+def test_schedule_argument_errors(tdev):
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    Mt, _ = _dev(torch, dev, gen.gaussian_np(64, 128, seed=1), "f32")
+    Y = torch.empty_like(Mt)
+    ws = torch.empty(ifn.classical_ns_workspace_bytes(64, 128, "f32"), dtype=torch.uint8, device=dev)
+    with pytest.raises(ifn.IfnsoError):
+        ifn.ns_schedule(Mt, Y, [configs.MUON_ABC] * 17, 0, "f32", ws)
+    with pytest.raises(ifn.IfnsoError):
+        ifn.ns_schedule(Mt, Y, [configs.MUON_ABC], 3, "f32", ws)
+    with pytest.raises(ifn.IfnsoError):
+        ifn.ns_schedule(Mt, Y, [configs.MUON_ABC], 0, "bf16", ws)  # f32 data, bf16 compute

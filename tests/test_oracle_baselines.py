@@ -118,13 +118,18 @@ def test_cans_schedule_maps_interval_brute_force():
     """Every step sends its interval into the next one, and the composed map on [delta, 1]
     stays within [1 - E, 1 + E] of the last step, reaching both ends."""
     sched, iv = BL.cans_schedule(5, 1e-3, 5)
-    x = np.geomspace(1e-3, 1.0, 200001)
+    x = np.geomspace(1e-3, 1.0 * 1.02, 200001)
     for k, abc in enumerate(sched):
         y = BL.compose_scalar(x, [abc])
         lo, hi = iv[k + 1]
         assert y.min() >= lo - 1e-10 and y.max() <= hi + 1e-10
         assert abs(y.min() - lo) <= 1e-7 and abs(y.max() - hi) <= 1e-7
-        x = y
+        # the next step is built for [lo, 1.02 hi]
+        x = np.geomspace(lo, hi * 1.02, 200001)
+    # without the margin the same construction chains the plain intervals
+    s0, iv0 = BL.cans_schedule(2, 1e-3, 5, margin=0.0)
+    assert np.allclose(s0[0], BL.minimax_odd(1e-3, 1.0, 5)[0], rtol=1e-14, atol=0)
+    assert np.allclose(s0[1], BL.minimax_odd(*iv0[1], 5)[0], rtol=1e-14, atol=0)
     stored, q = configs.load_schedule("cans_ns5_q2")
     assert q == 2 and np.allclose(stored, sched, rtol=1e-12, atol=0)
 

@@ -36,7 +36,7 @@ __all__ = [
     "bf16_bits_to_f32_np", "f32_to_bf16_bits_np", "gaussian_np", "haar_np",
     "spectral_np", "uniform_torch", "normal_torch", "round_to_bf16_torch",
     "gaussian_torch", "haar_torch", "spectral_torch", "lowrank_plus_noise_torch",
-    "lowrank_plus_noise_np",
+    "lowrank_plus_noise_np", "fan_in_uniform_np",
 ]
 
 
@@ -229,3 +229,19 @@ def lowrank_plus_noise_torch(rows: int, cols: int, seed: int, std: float = 0.02,
     z2 = gaussian_torch(rank, cols, seed, 2, device=device)
     r = z1 @ z2
     return noise + r * (lr_norm / torch.linalg.norm(r))
+
+
+def fan_in_uniform_np(seed: int, layout) -> np.ndarray:
+    """Initial parameters of a layered network, flattened in `layout` order (a list of
+    (name, shape)): a weight (name starting with "W", shape (out, in)) is drawn
+    U(-1/sqrt(in), 1/sqrt(in)) from stream 100 + its position in `layout`; a bias is zero.
+    float64."""
+    parts = []
+    for i, (name, shape) in enumerate(layout):
+        n = int(np.prod(shape))
+        if name.startswith("W"):
+            bound = 1.0 / math.sqrt(shape[1])
+            parts.append((2.0 * uniform_np(seed, 100 + i, n) - 1.0) * bound)
+        else:
+            parts.append(np.zeros(n))
+    return np.concatenate(parts)
