@@ -700,7 +700,7 @@ def main():
                          "as a known-size reference for hardware byte counters")
     ap.add_argument("--tune", action="store_true",
                     help="time candidate tile schedules per stage first and keep the fastest (written to --tune-out)")
-    ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "schedules.json"))
+    ap.add_argument("--tune-out", default=os.path.join(ROOT, "tuned_schedules.json"))
     ap.add_argument("--schedules", default=os.path.join(ROOT, "paper_2602_02500_amd", "schedules.json"),
                     help="tuned schedules to apply when the plan's key is present")
     args = ap.parse_args()
