@@ -18,7 +18,8 @@ e4m3 and bfloat16 modes against the FP64 oracle on a sample of the batch. `--wor
 learned` trains the coefficient network and runs the set with it; `--workload tform` runs
 the paper's complement-basis form (depth 14) on the set in bfloat16; `--workload muon` runs
 whole Muon optimizer steps on the set; `--workload table1` reproduces the paper's Table 1
-comparison (five methods, three sizes) on the device.
+comparison (five methods, three sizes) on the device; `--workload ns` runs the
+Newton-Schulz baselines on the gradient set through the batched path, beside IFNSO.
 """
 from __future__ import annotations
 
@@ -568,6 +569,74 @@ def run_muon(args, torch, dev, hip, log):
     print(json.dumps(line), flush=True)
 
 
+def run_ns(args, torch, dev, hip, log):
+    """Newton-Schulz iterations on the gradient set through the batched 256-tile path, beside
+    IFNSO: Muon's quintic (5 steps), the Cesista-form quintics (5 steps), the cubic (8 steps)
+    and the CANS quintics (5 steps, Gelfand q = 1), each step one Gram-basis plan with
+    exponents {0, 1, 2} (bf16 iterates between steps); then the fixed-coefficient IFNSO plan.
+    Reports matrices/s and ||YY^T - I||_F / sqrt(h) per method."""
+    import numpy as np
+
+    import paper_2602_02500_amd as ifn
+    from workloads import configs
+    Ms = make_d3(torch, dev, args.layers)
+    shapes = [tuple(m.shape) for m in Ms]
+    n = len(Ms)
+    Ys = [torch.empty_like(m) for m in Ms]
+    tmp = [torch.empty_like(m) for m in Ms]
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    hs = np.sqrt([min(s) for s in shapes])
+    res = {}
+
+    def measure(call):
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        ifn.orth_error(Ys, out, ows)
+        oe = out.cpu().numpy() / hs
+        per = {}
+        for _, r, c in configs.LAYER_SHAPES:
+            idx = [i for i, s in enumerate(shapes) if s == (r, c)]
+            per[f"{r}x{c}"] = round(float(oe[idx].mean()), 5)
+        return {"matrices_per_s": round(n / dt, 2), "ms_per_step": round(dt * 1e3, 3),
+                "orth_err_over_sqrt_h_mean": round(float(oe.mean()), 5), "per_shape": per}
+
+    for name, q in (("muon_ns5", 0), ("cesista_ns5", 0), ("original_ns8", 0), ("cans_ns5_q2", 1)):
+        sched, _ = configs.load_schedule(name)
+        sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute="bf16")
+        ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
+        res[name] = measure(lambda: sp.orthogonalize_batched(Ms, Ys, ws, tmp))
+        res[name]["steps"] = len(sched)
+        res[name]["gelfand_q"] = q
+        log(f"{name}: {res[name]['matrices_per_s']} matrices/s")
+        del ws, sp
+    exps, coeffs = configs.load_coeffs("gform_v1")
+    plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    res["ifnso_gform_v1"] = measure(lambda: plan.orthogonalize_batched(Ms, Ys, ws))
+    del ws, plan
+    value = res["muon_ns5"]["matrices_per_s"]
+    line = {
+        "metric": "Newton-Schulz baselines on the 32-layer gradient set, batched 256-tile path: matrices/s and "
+                  "||YY^T - I||_F / sqrt(h), beside IFNSO",
+        "value": value, "unit": "matrices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["muon_ns5"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices; value: Muon's quintic, "
+                               "5 steps", "matrices": n},
+        "roofline": None, "cpu_baseline": None,
+        "methods": res,
+        "ifnso_speedup_over_muon_ns5": round(res["ifnso_gform_v1"]["matrices_per_s"] / value, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 TABLE1_SHAPES = ((128, 128), (128, 512), (128, 1024))
 
 
@@ -684,7 +753,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon", "table1"],
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon", "table1", "ns"],
                     default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
                          "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
@@ -735,6 +804,8 @@ def main():
         return run_muon(args, torch, dev, hip, log)
     if args.workload == "table1":
         return run_table1(args, torch, dev, hip, log)
+    if args.workload == "ns":
+        return run_ns(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()

@@ -12,7 +12,8 @@ import re
 from typing import Optional, Sequence
 
 __all__ = [
-    "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "classical_ns", "classical_ns_workspace_bytes", "ns_schedule",
+    "load", "LIB_PATH", "HEADER_PATH", "IfnsoError", "Plan", "SchedulePlan", "classical_ns",
+    "classical_ns_workspace_bytes", "ns_schedule",
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
     "FLAG_SPLIT_BF16",
@@ -286,6 +287,45 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class SchedulePlan:
+    """Newton-Schulz step schedules over a batch, on the batched 256-tile path: step k,
+    X <- a_k X + b_k (XX^T) X + c_k (XX^T)^2 X, is a Gram-basis plan with exponents {0, 1, 2}
+    (or {0, 1} when c_k = 0) and coefficients (a_k, b_k, c_k); the first step's plan scales the
+    input by ||A||_F (gelfand_q = 0) or ||AA^T||_F^(1/2) (gelfand_q = 1), the others not at all.
+    The iterates are stored in the plans' input type between steps. Steps with the same
+    coefficients share a plan; all plans share one workspace (workspace_bytes)."""
+
+    def __init__(self, schedule, shapes, gelfand_q: int = 0, compute="bf16", device: int = 0):
+        if gelfand_q not in (0, 1):
+            raise ValueError("batched schedules scale by ||A||_F (q = 0) or Gelfand's bound with q = 1")
+        self.schedule = [tuple(float(v) for v in abc) for abc in schedule]
+        if not self.schedule:
+            raise ValueError("empty schedule")
+        self._plans = {}
+        self._steps = []
+        for k, (a, b, c) in enumerate(self.schedule):
+            norm = ("frobenius" if gelfand_q == 0 else "gram_frobenius") if k == 0 else "none"
+            key = (a, b, c, norm)
+            if key not in self._plans:
+                exps, co = ((0, 1), (a, b)) if c == 0.0 else ((0, 1, 2), (a, b, c))
+                self._plans[key] = Plan(exps, co, shapes, basis="gram", norm=norm, compute=compute, device=device)
+            self._steps.append(self._plans[key])
+        self.shapes = self._steps[0].shapes
+        self.workspace_bytes = max(p.workspace_bytes for p in self._plans.values())
+
+    def orthogonalize_batched(self, Ms, Ys, workspace, tmp=None, stream=None):
+        """Ys <- the schedule applied to Ms. With more than one step, `tmp` (tensors shaped like
+        Ms, distinct from Ms and Ys) holds every other iterate."""
+        n = len(self._steps)
+        if n > 1 and tmp is None:
+            raise ValueError("a schedule of several steps needs tmp buffers")
+        src = Ms
+        for k, plan in enumerate(self._steps):
+            dst = Ys if (n - 1 - k) % 2 == 0 else tmp
+            plan.orthogonalize_batched(src, dst, workspace, stream)
+            src = dst
 
 
 def classical_ns_workspace_bytes(rows: int, cols: int, compute="bf16") -> int:

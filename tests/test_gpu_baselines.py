@@ -135,3 +135,31 @@ def test_schedule_argument_errors(tdev):
         ifn.ns_schedule(Mt, Y, [configs.MUON_ABC], 3, "f32", ws)
     with pytest.raises(ifn.IfnsoError):
         ifn.ns_schedule(Mt, Y, [configs.MUON_ABC], 0, "bf16", ws)  # f32 data, bf16 compute
+
+
+@pytest.mark.parametrize("name,q", [("muon_ns5", 0), ("cesista_ns5", 0), ("original_ns8", 0), ("cans_ns5_q2", 1)])
+def test_schedule_plan_batched_matches_oracle(tdev, name, q):
+    """The same schedules as chained batched plans on the 256-tile path (bf16 iterates between
+    steps), against the oracle's iteration with the same scaling; the CANS schedule runs with
+    Gelfand q = 1, which also bounds the singular values by 1."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    sched, _ = configs.load_schedule(name)
+    shapes = [(256, 512), (512, 256), (200, 456), (1, 64)]
+    print(f"case {name} q={q} batched", flush=True)
+    Ms, vals = [], []
+    for i, s in enumerate(shapes):
+        t, v = _dev(torch, dev, gen.gaussian_np(*s, seed=40 + i), "bf16")
+        Ms.append(t)
+        vals.append(v)
+    sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute="bf16")
+    ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.full_like(m, float("nan")) for m in Ms]
+    tmp = [torch.empty_like(m) for m in Ms]
+    sp.orthogonalize_batched(Ms, Ys, ws, tmp)
+    torch.cuda.synchronize()
+    for Y, v, s in zip(Ys, vals, shapes):
+        Yo = BL.ns_schedule(v, sched, q)
+        r = _rel(Y.float().cpu().numpy().astype(np.float64), Yo)
+        print(f"  {s}: rel {r:.2e}")
+        assert r <= TOL_BF16[name]
