@@ -57,3 +57,40 @@ def test_d2_pair_against_closed_form(tdev):
             print(f"  {compute} {rows}x{cols}: rel vs closed form {r:.3e}")
             assert r <= tol, (compute, rows, cols, r)
         del ws, Ys, Ms, plan
+
+
+def test_d2_pair_schedule_against_closed_form(tdev):
+    """Muon's five Newton-Schulz steps through chained batched plans (the `ns` benchmark's
+    launch configuration) on the same pair: the iteration acts on singular values only, so the
+    exact result is U diag(phi(sigma / ||sigma||)) V^T with phi the composed scalar map.
+    Bounds: float32 1e-4; bfloat16 0.1, three times what a float64 model of the bf16 storage
+    points (input, Gram operand, P, iterates) gives on a 1024x3584 matrix with the same
+    spectrum law (3.4e-2)."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    from oracle import baselines as BL
+    sched, q = configs.load_schedule("muon_ns5")
+    cases = [(4096, 4096, 1), (14336, 4096, 2)]
+    mats, closed = [], []
+    for rows, cols, seed in cases:
+        print(f"case d2 schedule {rows}x{cols} seed {seed}", flush=True)
+        sigma = configs.d2_sigma_np(min(rows, cols), seed)
+        M, U, V = gen.spectral_torch(rows, cols, sigma, seed, device=dev)
+        f = BL.compose_scalar(sigma / np.sqrt(np.sum(sigma ** 2)), sched)
+        closed.append((U.cpu().numpy() * f) @ V.cpu().numpy().T)
+        mats.append(M)
+        del U, V
+    shapes = [tuple(m.shape) for m in mats]
+    for compute, dt, tol in [("f32", torch.float32, 1e-4), ("bf16", torch.bfloat16, 0.1)]:
+        sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute=compute)
+        Ms = [m.to(dt).contiguous() for m in mats]
+        Ys = [torch.empty_like(m) for m in Ms]
+        tmp = [torch.empty_like(m) for m in Ms]
+        ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
+        sp.orthogonalize_batched(Ms, Ys, ws, tmp)
+        torch.cuda.synchronize()
+        for (rows, cols, _), Y, Yc in zip(cases, Ys, closed):
+            r = _rel(Y.double().cpu().numpy(), Yc)
+            print(f"  {compute} {rows}x{cols}: rel vs closed form {r:.3e}")
+            assert r <= tol, (compute, rows, cols, r)
+        del ws, Ys, Ms, tmp, sp
