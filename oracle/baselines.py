@@ -15,7 +15,7 @@ readings used here:
 * Cesista: five steps, one (gamma_k, r_k, u_k) per step, fitted jointly to minimise
   E_{x ~ U(0,1)} (phi(x) - 1)^2 of the composed scalar map phi (the objective the paper uses
   for its own coefficients, experiment section), the expectation taken by Gauss-Legendre
-  quadrature, by L-BFGS started from Muon's quintic on every step.
+  quadrature, by BFGS (exact gradient) started from Muon's quintic on every step.
 * CANS: step k applies the odd polynomial of degree 3 or 5 that minimises max |1 - p(x)| over
   the interval [lo_k, hi_k] known to hold the singular values (Remez exchange), widened at the
   top by a 2 % margin for rounding; the interval starts at [delta, 1] and becomes
@@ -35,7 +35,8 @@ import numpy as np
 from .ifnso import orient
 
 __all__ = [
-    "cesista_to_abc", "abc_to_cesista", "compose_scalar", "cesista_objective", "cesista_fit",
+    "cesista_to_abc", "abc_to_cesista", "compose_scalar", "cesista_objective", "cesista_objective_grad",
+    "cesista_fit",
     "minimax_odd", "cans_schedule", "gelfand_scale", "ns_schedule",
 ]
 
@@ -88,25 +89,59 @@ def cesista_objective(schedule, nodes: int = 400) -> float:
     return float(np.sum(w * (compose_scalar(x, schedule) - 1.0) ** 2))
 
 
+def cesista_objective_grad(params, nodes: int = 400):
+    """The objective of :func:`cesista_objective` for the schedule of (gamma_k, r_k, u_k) and its
+    gradient with respect to those parameters (reverse accumulation through the composed map:
+    g_k = g_{k+1} p_k'(x_k) with p_k' = a + 3 b x^2 + 5 c x^4, then the chain rule through
+    a = 1 + gamma alpha^2 beta^2, b = -gamma (alpha^2 + beta^2), c = gamma, alpha = 1 - u,
+    beta = 1 + r)."""
+    x, w = _gauss_legendre_unit(nodes)
+    params = [tuple(float(v) for v in p) for p in params]
+    abc = [cesista_to_abc(*p) for p in params]
+    xs = [np.asarray(x, dtype=np.float64)]
+    for a, b, c in abc:
+        t = xs[-1]
+        t2 = t * t
+        xs.append(t * (a + t2 * (b + c * t2)))
+    d = xs[-1] - 1.0
+    loss = float(np.sum(w * d * d))
+    g = 2.0 * w * d
+    grad = np.zeros((len(params), 3))
+    for k in range(len(params) - 1, -1, -1):
+        a, b, c = abc[k]
+        t = xs[k]
+        t2 = t * t
+        da, db, dc = float(np.sum(g * t)), float(np.sum(g * t * t2)), float(np.sum(g * t * t2 * t2))
+        gamma, r, u = params[k]
+        al, be = 1.0 - u, 1.0 + r
+        grad[k, 0] = da * al * al * be * be - db * (al * al + be * be) + dc
+        grad[k, 1] = da * gamma * al * al * 2.0 * be - db * gamma * 2.0 * be
+        grad[k, 2] = -da * gamma * be * be * 2.0 * al + db * gamma * 2.0 * al
+        g = g * (a + t2 * (3.0 * b + 5.0 * c * t2))
+    return loss, grad
+
+
 def cesista_fit(steps: int = 5, nodes: int = 400, start=(3.4445, -4.7750, 2.0315)):
     """Fits (gamma_k, r_k, u_k), k = 0..steps-1, to the objective of
-    :func:`cesista_objective`; starts every step at the (gamma, r, u) of the `start` quintic.
+    :func:`cesista_objective` by BFGS with the gradient of :func:`cesista_objective_grad`, to a
+    stationary point (gradient below 1e-10); starts every step at the (gamma, r, u) of the
+    `start` quintic.
     Returns (params [steps][3], schedule [steps][3] of (a, b, c))."""
     from scipy.optimize import minimize
 
-    x, w = _gauss_legendre_unit(nodes)
     theta0 = np.array(list(abc_to_cesista(*start)) * steps, dtype=np.float64)
 
-    def loss(theta):
-        sched = [cesista_to_abc(*theta[3 * k:3 * k + 3]) for k in range(steps)]
+    def fun(theta):
         with np.errstate(over="ignore", invalid="ignore"):  # trial points of the line search may diverge
-            v = float(np.sum(w * (compose_scalar(x, sched) - 1.0) ** 2))
-        return v if math.isfinite(v) else 1e300
+            v, g = cesista_objective_grad(theta.reshape(steps, 3), nodes)
+        if not (math.isfinite(v) and np.all(np.isfinite(g))):
+            return 1e300, np.zeros_like(theta)
+        return v, g.reshape(-1)
 
-    res = minimize(loss, theta0, method="L-BFGS-B", options={"maxiter": 5000, "maxfun": 200000, "ftol": 1e-15,
-                                                              "gtol": 1e-12})
-    params = [tuple(float(v) for v in res.x[3 * k:3 * k + 3]) for k in range(steps)]
-    return params, [cesista_to_abc(*p) for p in params]
+    res = minimize(fun, theta0, jac=True, method="BFGS", options={"maxiter": 20000, "gtol": 1e-10})
+    sched = [cesista_to_abc(*(float(v) for v in res.x[3 * k:3 * k + 3])) for k in range(steps)]
+    # (r, u) and (-u, -r) give the same polynomial: report the form with 1 - u <= 1 + r
+    return [abc_to_cesista(*abc) for abc in sched], sched
 
 
 # ---------------------------------------------------------------------------------------------

@@ -7,7 +7,7 @@ Tolerances (relative Frobenius distance to the oracle on the same input bytes):
   shapes for every schedule.
 * bfloat16: three times what a float64 model of the bf16 storage points (X_k, the Gram
   operand, B_k = b G + c G^2 rounded to bf16) gives on these shapes: the schedules differ
-  widely in gain. The model gives 0.5 % (cubic, 8 steps), 1.8 % (Muon), 0.8 % (Cesista form)
+  widely in gain. The model gives 0.5 % (cubic, 8 steps), 1.8 % (Muon), 1.1 % (Cesista form)
   and 5.5 % (CANS, whose first quintic has coefficients up to 25).
 """
 import numpy as np
@@ -21,7 +21,12 @@ pytestmark = pytest.mark.gpu
 
 SCHEDULES = ["original_ns8", "muon_ns5", "cesista_ns5", "cans_ns5_q2"]
 TOL_F32 = 1e-4
-TOL_BF16 = {"original_ns8": 1.5e-2, "muon_ns5": 6e-2, "cesista_ns5": 3e-2, "cans_ns5_q2": 0.17}
+TOL_BF16 = {"original_ns8": 1.5e-2, "muon_ns5": 6e-2, "cesista_ns5": 3.5e-2, "cans_ns5_q2": 0.17}
+# Vectors (h = 1) on the batched path: the iterate is rounded to bf16 between the chained plans
+# and the scalar map's slope at 1 amplifies that rounding (14 for the Cesista form's first step);
+# three times the same float64 model's error on the test's 1 x 64 vector (0.17 %, 0.46 %,
+# 3.5 %, 0.33 %).
+TOL_BF16_H1 = {"original_ns8": 6e-3, "muon_ns5": 1.5e-2, "cesista_ns5": 0.11, "cans_ns5_q2": 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -162,4 +167,4 @@ def test_schedule_plan_batched_matches_oracle(tdev, name, q):
         Yo = BL.ns_schedule(v, sched, q)
         r = _rel(Y.float().cpu().numpy().astype(np.float64), Yo)
         print(f"  {s}: rel {r:.2e}")
-        assert r <= TOL_BF16[name]
+        assert r <= (TOL_BF16_H1 if min(s) == 1 else TOL_BF16)[name]

@@ -48,16 +48,31 @@ def test_muon_quintic_round_trip():
         BL.abc_to_cesista(*configs.CUBIC_ABC)
 
 
-def test_cesista_fit_improves_on_muon_and_is_stored():
+def test_cesista_gradient_matches_central_differences():
+    params = [(2.05, 0.32, 0.12), (2.0, 0.3, 0.15), (1.9, 0.1, 0.05)]
+    L, g = BL.cesista_objective_grad(params)
+    assert abs(L - BL.cesista_objective([BL.cesista_to_abc(*p) for p in params])) <= 1e-15
+    th = np.array(params)
+    for i in range(th.shape[0]):
+        for j in range(3):
+            e = np.zeros_like(th)
+            e[i, j] = 1e-6
+            fd = (BL.cesista_objective_grad(th + e)[0] - BL.cesista_objective_grad(th - e)[0]) / 2e-6
+            assert abs(fd - g[i, j]) <= 1e-7 * max(1.0, abs(g[i, j]))
+
+
+def test_cesista_fit_is_stationary_and_stored():
+    """The stored schedule is a stationary point of the stated objective (the paper prints no
+    fitted values, so the values themselves are parity unpinned) and beats five Muon steps."""
     params, sched = BL.cesista_fit()
     assert len(sched) == 5
-    assert BL.cesista_objective(sched) < 0.1 * BL.cesista_objective([configs.MUON_ABC] * 5)
+    L, g = BL.cesista_objective_grad(params)
+    assert np.abs(g).max() <= 1e-8
+    assert L < 0.05 * BL.cesista_objective([configs.MUON_ABC] * 5)
     for p, abc in zip(params, sched):
         assert np.allclose(BL.abc_to_cesista(*abc), p, rtol=1e-9, atol=1e-12)
     stored, q = configs.load_schedule("cesista_ns5")
-    assert q == 0 and np.allclose(stored, sched, rtol=1e-9, atol=1e-12)
-    # deterministic: a second fit gives the same numbers
-    assert np.array_equal(np.array(BL.cesista_fit()[1]), np.array(sched))
+    assert q == 0 and np.allclose(stored, sched, rtol=1e-7, atol=1e-10)
 
 
 # ---------------------------------------------------------------------------------------------
