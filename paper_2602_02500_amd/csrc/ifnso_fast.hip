@@ -549,6 +549,9 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
 
 // bfloat16 value of v (round to nearest even), as a float
 __device__ __forceinline__ float bf16_value(float v) { return __uint_as_float((uint32_t)f32_to_bf16(v) << 16); }
+// The two bfloat16 values packed in a 32-bit word (the lower address in the low half).
+__device__ __forceinline__ float bf16_pair_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_pair_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 // Staged half tile as a bfloat16 operand: plain (leading dimension hp), or with SPLIT as the
 // pair hi = bf16(v), lo = bf16(v - hi) stored side by side ([X_hi | X_lo], leading dimension 2 hp).
@@ -802,7 +805,9 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
 // squaring (Gram basis and complement basis): level -> level + 1
 // ---------------------------------------------------------------------------------------------
 // SPLIT (complement basis): the operand is a split pair [D_hi | D_lo]; the product runs over
-// K = 3 hp as D_hi D_hi + D_hi D_lo + D_lo D_hi, and the next operand is written split.
+// K = 3 hp as D_hi D_hi + D_hi D_lo + D_lo D_hi, and the next operand is written split. The
+// epilogue's 2 D term reads the same pair (about 16 significant bits), so no float32 copy of
+// the levels is kept.
 // FUSE (level layout, last squaring only): the aggregation is folded into the epilogue
 // (store_p_fused) instead of storing the last level.
 template <bool AGG, bool SPLIT = false, bool FUSE = false>
@@ -874,7 +879,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
       // pass 1 (row-wise, upper tile): new level value `out`, running sum P; the staged value
       // is replaced by what is stored (out, or P on the last level) for the bf16 emit. The
       // float32 reads of a batch are issued together (they do not wait on the batch's stores).
-      constexpr int PER = 128 * 64 / NT, BATCH = 8;
+      constexpr int PER = 128 * 64 / NT, BATCH = SPLIT ? 4 : 8;
       for (int b0 = 0; b0 < PER; b0 += BATCH) {
         float4 pin[BATCH], dpv[BATCH];
 #pragma unroll
@@ -883,7 +888,18 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
           const int row = q >> 6, c4 = (q & 63) * 4;
           const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
           pin[u] = *(const float4 *)(P.accf + gi);
-          if (a.basis != kGram && level > 1) dpv[u] = *(const float4 *)(P.df[level & 1] + gi);
+          if constexpr (SPLIT) {
+            // D_level from its split operand (hi + lo) instead of a float32 copy
+            if (level > 1) {
+              const uint16_t *so = (const uint16_t *)P.opnd[(level - 1) & 1] + (int64_t)(m0 + half * 128 + row) * (2 * hp) +
+                                   n0 + c4;
+              const uint2 h2 = *(const uint2 *)so, l2 = *(const uint2 *)(so + hp);
+              dpv[u] = make_float4(bf16_pair_lo(h2.x) + bf16_pair_lo(l2.x), bf16_pair_hi(h2.x) + bf16_pair_hi(l2.x),
+                                   bf16_pair_lo(h2.y) + bf16_pair_lo(l2.y), bf16_pair_hi(h2.y) + bf16_pair_hi(l2.y));
+            }
+          } else if (a.basis != kGram && level > 1) {
+            dpv[u] = *(const float4 *)(P.df[level & 1] + gi);
+          }
         }
 #pragma unroll
         for (int u = 0; u < BATCH; u++) {
@@ -909,7 +925,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
                                          : pin[u];
             pv = make_float4(p0.x + c_next * outv.x, p0.y + c_next * outv.y, p0.z + c_next * outv.z,
                              p0.w + c_next * outv.w);
-            if (!last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
+            if (!SPLIT && !last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
           }
           if (!last) *(float4 *)(P.accf + gi) = pv;
           const double w = diag ? 1.0 : 2.0;

@@ -107,7 +107,7 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.off_opnd[1] = take(hh * op_size(op) * (split ? 2 : 1));
     L.off_accf = take(hh * 4);
   }
-  if (complement) {
+  if (complement && !split) {  // split plans read D_l from its split operand
     L.off_df[0] = take(hh * 4);
     L.off_df[1] = take(hh * 4);
   }

@@ -64,7 +64,7 @@ def _gradient_like(rows, cols, seed):
     return gen.lowrank_plus_noise_np(rows, cols, seed)
 
 
-SHAPES = [(256, 512), (512, 256), (200, 456), (520, 264), (1, 64)]
+SHAPES = [(256, 512), (512, 256), (200, 456), (520, 264), (384, 384), (1, 64)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
