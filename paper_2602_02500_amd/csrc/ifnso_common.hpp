@@ -29,7 +29,7 @@ struct ProbDev {
   int32_t vecM;        // M and Y allow 16-byte vector access
   void *opnd[2];       // h x h operand ping-pong (operand type), full symmetric
   float *accf;         // h x h float32: Gram (upper tiles), then the running sum P
-  float *df[2];        // complement basis: float32 D levels (upper tiles)
+  float *df[2];        // complement basis, single operands: float32 D levels (upper tiles)
   double *norm_part;   // [nt]         sum of squares of A per row block (diagonal Gram tiles)
   double *lvl_part;    // [levels][nt*nt] sum of squares of the stored level, upper tiles
   double *diag_part;   // [levels][nt]    trace partials of the stored level

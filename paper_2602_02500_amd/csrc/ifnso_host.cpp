@@ -74,8 +74,8 @@ void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
   nq = (int32_t)((rows + rq - 1) / rq);
 }
 
-// Workspace layout of one problem. levels = J + 2 partial slots; complement basis adds the
-// float32 D ping-pong; classical NS adds two h x w iterates.
+// Workspace layout of one problem. levels = J + 2 partial slots; the complement basis adds the
+// float32 D ping-pong unless its operands are split; classical NS adds two h x w iterates.
 ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
                           bool e4m3 = false, bool split = false) {
   ProbLayout L{};
