@@ -1,7 +1,8 @@
 """Writes workloads/coeffs.json: the fixed coefficient vectors used by the workloads.
 
 Run from the repository root: ``python -m oracle.write_coeffs``. Calls only the
-oracle's fitting routines.
+oracle's fitting routines (test infrastructure: the library never runs this script; it
+reads the stored vectors as ordinary coefficients).
 
 * gform_v1      exponents {0,1,2,4,8,16}: least-squares fit of sum_k c_k x^(2e_k+1) to 1
                 on x ~ U(0,1) with sum_k c_k = 1 (the paper's objective, Sec. 2.4, moved
