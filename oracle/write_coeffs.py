@@ -1,8 +1,9 @@
 """Writes workloads/coeffs.json: the fixed coefficient vectors used by the workloads.
 
 Run from the repository root: ``python -m oracle.write_coeffs``. Calls only the
-oracle's fitting routines (test infrastructure: the library never runs this script; it
-reads the stored vectors as ordinary coefficients).
+oracle's fitting routines (test infrastructure: nothing runs it at run time; the benchmark
+and the tests read the stored vectors through ``workloads/configs.py`` and hand them to
+the library as ordinary coefficients).
 
 * gform_v1      exponents {0,1,2,4,8,16}: least-squares fit of sum_k c_k x^(2e_k+1) to 1
                 on x ~ U(0,1) with sum_k c_k = 1 (the paper's objective, Sec. 2.4, moved
