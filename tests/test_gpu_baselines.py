@@ -168,3 +168,19 @@ def test_schedule_plan_batched_matches_oracle(tdev, name, q):
         r = _rel(Y.float().cpu().numpy().astype(np.float64), Yo)
         print(f"  {s}: rel {r:.2e}")
         assert r <= (TOL_BF16_H1 if min(s) == 1 else TOL_BF16)[name]
+
+
+@pytest.mark.parametrize("shape", [(64, 160), (1, 48), (48, 1)])
+def test_longest_schedule(tdev, shape):
+    """IFNSO_NS_MAX_STEPS (16) distinct triples: every entry of the schedule is used, including
+    the float64 scalar recursion of vector inputs, which reads the whole schedule at once."""
+    torch, dev = tdev
+    sched = [(1.0 + 0.02 * (k % 3), -0.01, 0.002) for k in range(16)]
+    Mt, vals = _dev(torch, dev, gen.gaussian_np(*shape, seed=5), "f32")
+    Y = _run(torch, dev, Mt, sched, 0, "f32")
+    Yo = BL.ns_schedule(vals, sched, 0)
+    assert _rel(Y, Yo) <= TOL_F32
+    # one entry changed in the middle changes the result: the per-step triples are all read
+    sched2 = list(sched)
+    sched2[9] = (1.3, -0.01, 0.002)
+    assert _rel(_run(torch, dev, Mt, sched2, 0, "f32"), Yo) > 1e-3
