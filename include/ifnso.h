@@ -23,8 +23,8 @@
  *    on the caller's HIP stream (passed as void *, a hipStream_t; NULL = default
  *    stream). Kernel-side faults surface at the caller's next synchronisation.
  *  - Errors are returned as ifnso_status; ifnso_last_error() gives a thread-local
- *    message. Argument checks happen before any HIP call, so an error return means
- *    that nothing was enqueued.
+ *    message. Argument checks happen before any HIP call, so an argument error
+ *    (INVALID_ARGUMENT, UNSUPPORTED, WORKSPACE_TOO_SMALL) means that nothing was enqueued.
  *  - A zero input matrix gives Y = 0 (no epsilon is added to any normalisation).
  *  - Concurrent calls that share a workspace race; give each in-flight call its own.
  */
@@ -70,8 +70,8 @@ typedef enum {
 } ifnso_norm;
 
 /* FIXED: the descriptor's coefficients for every problem.
- * LEARNED: per-problem coefficients predicted on the device by a small network (the
- *   "dynamic coefficients" the paper names as future work, Sec. 4) from the normalised
+ * LEARNED: per-problem coefficients predicted on the device by a small network (the paper
+ *   leaves coefficients that adapt to the input to future work, Sec. 4) from the normalised
  *   traces m_j = tr(G^(2^j))/h, j = 0..7, of the Gram powers the method forms (two extra
  *   squarings supply G^32 and G^64). Requires exponents {0,1,2,4,8,16}, the Gram basis, the
  *   Frobenius norm and bf16 compute; the descriptor's coefficients are the fallback for any
@@ -147,9 +147,10 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
  * transposed (rows > cols) problems, one squaring per level (in FP8_E4M3 plans with the
  * quantisation of the power it squares), the aggregation of the weighted powers, then the
  * product for the two groups in the same order: J + 6 slots where 2^J is the largest exponent.
- * A slot with no work in a call launches nothing (the aggregation runs only when the levels are
- * kept: bfloat16 Gram-basis plans with J >= 1, and every FP8_E4M3 plan). Returns the count, or
- * a negative status for NULL. */
+ * A slot with no work in a call launches nothing. The aggregation slot runs only in learned
+ * plans and in FP8_E4M3 plans without squarings; the other bfloat16 and FP8_E4M3 Gram-basis
+ * plans form the weighted sum in their last squaring, and the remaining plans accumulate it in
+ * every squaring. Returns the count, or a negative status for NULL. */
 int32_t ifnso_plan_num_launches(ifnso_plan_t plan);
 
 /* Stage of launch slot i (0 Gram, 1 squaring, 2 product, 3 aggregation, 4 preparation, with
