@@ -774,7 +774,7 @@ def main():
                     help="tuned schedules to apply when the plan's key is present")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the 224 matrices are independent and would be sharded by matrix across GPUs)", file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
   IFNSO_OK = 0,
   IFNSO_ERR_INVALID_ARGUMENT = 1,   /* bad pointer, size, descriptor, or plan mismatch */
-  IFNSO_ERR_UNSUPPORTED = 2,        /* a valid combination this build does not implement */
+  IFNSO_ERR_UNSUPPORTED = 2,        /* a valid combination the library does not implement */
   IFNSO_ERR_WORKSPACE_TOO_SMALL = 3,
   IFNSO_ERR_HIP = 4,                /* a HIP runtime call failed; see ifnso_last_error() */
   IFNSO_ERR_INTERNAL = 5
@@ -114,7 +114,7 @@ typedef struct ifnso_plan_s *ifnso_plan_t;
  * workspace. It owns those device buffers until ifnso_plan_destroy().
  * Errors: INVALID_ARGUMENT (null pointers, num_problems < 1, a dimension < 1,
  * bad exponents/coefficients/enums, LEARNED without a parameter blob of the right
- * length), UNSUPPORTED (dtype/compute combination not built), HIP. */
+ * length), UNSUPPORTED (dtype/compute combination not implemented), HIP. */
 ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_problems, const int64_t *rows,
                         const int64_t *cols, int32_t in_dtype, int32_t out_dtype, int32_t device,
                         ifnso_plan_t *out_plan);

@@ -444,7 +444,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
       return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d has shape %lld x %lld", i, (long long)rows[i],
                   (long long)cols[i]);
     if (std::min(rows[i], cols[i]) > 65536 || std::max(rows[i], cols[i]) > (1LL << 30))
-      return fail(IFNSO_ERR_UNSUPPORTED, "problem %d is larger than this build supports", i);
+      return fail(IFNSO_ERR_UNSUPPORTED, "problem %d is larger than the library supports", i);
   }
   // the e4m3 mode keeps bfloat16 levels, P and product operands; only the Gram and squaring
   // GEMMs read e4m3
@@ -1179,7 +1179,7 @@ static ifnso_status run_ns(const void *M, int64_t rows, int64_t cols, int64_t ld
   if (gelfand_q < 0) return fail(IFNSO_ERR_INVALID_ARGUMENT, "gelfand_q must be >= 0");
   for (int i = 0; i < 3 * nsched; i++)
     if (!std::isfinite(sched[i])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "coefficient not finite");
-  if (gelfand_q > 2) return fail(IFNSO_ERR_UNSUPPORTED, "gelfand_q above 2 is not built");
+  if (gelfand_q > 2) return fail(IFNSO_ERR_UNSUPPORTED, "gelfand_q above 2 is not implemented");
   const int op = ns_op(compute, dtype);
   if (op < 0) return fail(IFNSO_ERR_UNSUPPORTED, "classical NS supports F32/F32 and BF16/BF16 (dtype/compute)");
   if (std::min(rows, cols) > 65536) return fail(IFNSO_ERR_UNSUPPORTED, "matrix too large");
