@@ -106,6 +106,31 @@ __device__ __forceinline__ const ProbDev &prob_of(const StageArgs &a, const Task
 }
 
 // ---------------------------------------------------------------------------------------------
+// epilogue helpers: the accumulator tile staged in LDS, four consecutive elements stored at once
+// ---------------------------------------------------------------------------------------------
+template <typename TL, int TS>
+__device__ __forceinline__ void stage_tile(const TL &tile, float *ep) {  // ep: TS x TS, row-major
+#pragma unroll
+  for (int fm = 0; fm < TL::FM; fm++)
+#pragma unroll
+    for (int fn = 0; fn < TL::FN; fn++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) ep[TL::row_of(fm, r) * TS + TL::col_of(fn)] = tile.acc[fm][fn][r];
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T *p, float4 v);
+template <>
+__device__ __forceinline__ void store4<float>(float *p, float4 v) {
+  *(float4 *)p = v;
+}
+template <>
+__device__ __forceinline__ void store4<uint16_t>(uint16_t *p, float4 v) {
+  *(uint2 *)p = make_uint2((uint32_t)f32_to_bf16(v.x) | ((uint32_t)f32_to_bf16(v.y) << 16),
+                           (uint32_t)f32_to_bf16(v.z) | ((uint32_t)f32_to_bf16(v.w) << 16));
+}
+
+// ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
 template <typename T, int TS>
@@ -134,26 +159,37 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
     const int64_t hp = P.hp;
     const bool keep_f32 = (a.J >= 1 && !a.agg) || a.ns_step >= 0 || a.learned;
     double lv = 0.0, dg = 0.0;
+    // epilogue through LDS, as in the squaring: row chunks, then the mirrored block
+    float *ep = (float *)smem;
+    __syncthreads();
+    stage_tile<TL, TS>(tile, ep);
+    __syncthreads();
+    for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+      const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
+      const int i = m0 + row, j = n0 + c4;
+      const int64_t ij = (int64_t)i * hp + j;
+      const float4 v = *(const float4 *)(ep + row * TS + c4);
+      store4<T>(op + ij, v);
+      // both triangles: the 256-tile squaring kernels read whole diagonal 256 blocks
+      if (keep_f32) *(float4 *)(P.accf + ij) = v;
+      const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int fm = 0; fm < TL::FM; fm++)
-#pragma unroll
-      for (int fn = 0; fn < TL::FN; fn++)
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-          const int i = m0 + TL::row_of(fm, r), j = n0 + TL::col_of(fn);
-          const float v = tile.acc[fm][fn][r];
-          const T tv = Elem<T>::from_f(v);
-          op[i * hp + j] = tv;
-          if (!diag) op[j * hp + i] = tv;
-          if (keep_f32) {
-            // both triangles: the 256-tile squaring kernels read whole diagonal 256 blocks
-            P.accf[i * hp + j] = v;
-            if (!diag) P.accf[j * hp + i] = v;
-          }
-          const double dv = (double)v;
-          lv = fma(dv, diag ? dv : 2.0 * dv, lv);
-          if (i == j) dg += dv;
-        }
+      for (int e = 0; e < 4; e++) {
+        const double dv = (double)vv[e];
+        lv = fma(dv, diag ? dv : 2.0 * dv, lv);
+        if (i == j + e) dg += dv;
+      }
+    }
+    if (!diag) {
+      for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+        const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
+        const int64_t ji = (int64_t)(n0 + row) * hp + m0 + c4;
+        const float4 v = make_float4(ep[(c4 + 0) * TS + row], ep[(c4 + 1) * TS + row], ep[(c4 + 2) * TS + row],
+                                     ep[(c4 + 3) * TS + row]);
+        store4<T>(op + ji, v);
+        if (keep_f32) *(float4 *)(P.accf + ji) = v;
+      }
+    }
     if (!diag || !first_step) nrm = 0.0;
     block_sum3(lv, dg, nrm, (double *)smem);
     if (threadIdx.x == 0) {
@@ -217,43 +253,87 @@ __global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
     T *dst = (T *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
+    // The accumulator goes through LDS so that one short loop over float4 row chunks does the
+    // epilogue (a per-register epilogue unrolled over the tile is long code that a one-tile
+    // launch pays for in instruction fetch).
+    float *ep = (float *)smem;
+    __syncthreads();  // the mainloop's last LDS reads
+    stage_tile<TL, TS>(tile, ep);
+    __syncthreads();
+    // float4 row chunks, four per thread at a time so that their global reads overlap
+    constexpr int CHUNKS = TS * TS / 4 / kThreads, BATCH = 4;
+    static_assert(CHUNKS % BATCH == 0, "epilogue batches");
+    for (int b0 = 0; b0 < CHUNKS; b0 += BATCH) {
+      float4 fin[BATCH], d4[BATCH];
+      if (!a.ns_norm_pass) {
 #pragma unroll
-    for (int fm = 0; fm < TL::FM; fm++)
+        for (int u = 0; u < BATCH; u++) {
+          const int q = threadIdx.x + kThreads * (b0 + u);
+          const int64_t ij = (int64_t)(m0 + q / (TS / 4)) * hp + n0 + (q % (TS / 4)) * 4;
+          fin[u] = *(const float4 *)(P.accf + ij);
+          if (a.ns_step < 0 && a.basis != kGram && level > 1) d4[u] = *(const float4 *)(P.df[level & 1] + ij);
+        }
+      }
 #pragma unroll
-      for (int fn = 0; fn < TL::FN; fn++)
+      for (int u = 0; u < BATCH; u++) {
+        const int q = threadIdx.x + kThreads * (b0 + u);
+        const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
+        const int i = m0 + row, j = n0 + c4;
+        const int64_t ij = (int64_t)i * hp + j;
+        const float4 accv = *(const float4 *)(ep + row * TS + c4);
+        const float av[4] = {accv.x, accv.y, accv.z, accv.w};
+        if (a.ns_norm_pass) {
+          // Gelfand q = 2: the sum of squares of G_raw^2 only; nothing is stored
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-          const int i = m0 + TL::row_of(fm, r), j = n0 + TL::col_of(fn);
-          const int64_t ij = i * hp + j;
-          const float acc = tile.acc[fm][fn][r];
-          if (a.ns_norm_pass) {
-            // Gelfand q = 2: the sum of squares of G_raw^2 only; nothing is stored
-            const double dv = (double)acc;
+          for (int e = 0; e < 4; e++) {
+            const double dv = (double)av[e];
             lv = fma(dv, diag ? dv : 2.0 * dv, lv);
-            continue;
           }
+          continue;
+        }
+        const float fv[4] = {fin[u].x, fin[u].y, fin[u].z, fin[u].w};
+        const bool cdf = a.ns_step < 0 && a.basis != kGram && level > 1;
+        const float dp[4] = {cdf ? d4[u].x : 0.f, cdf ? d4[u].y : 0.f, cdf ? d4[u].z : 0.f, cdf ? d4[u].w : 0.f};
+        float ov[4], pvv[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
           float out, pv;
           if (a.ns_step >= 0) {
             // classical NS: B = b G + c G^2 (G = s G_raw at the first step)
-            out = ns_b * P.accf[ij] + ns_c * acc;
+            out = ns_b * fv[e] + ns_c * av[e];
             pv = out;
           } else if (a.basis == kGram) {
-            out = f_out * acc;
-            pv = (level == 1 ? c_first * P.accf[ij] : P.accf[ij]) + c_acc * acc;
+            out = f_out * av[e];
+            pv = (level == 1 ? c_first * fv[e] : fv[e]) + c_acc * av[e];
           } else {
-            const float dprev = (level == 1) ? dscale * P.accf[ij] : P.df[level & 1][ij];
-            out = 2.f * dprev + alpha * acc;
-            pv = (level == 1 ? c_first * dprev : P.accf[ij]) + c_next * out;
-            if (!last) P.df[(level + 1) & 1][ij] = out;
+            const float dprev = (level == 1) ? dscale * fv[e] : dp[e];
+            out = 2.f * dprev + alpha * av[e];
+            pv = (level == 1 ? c_first * dprev : fv[e]) + c_next * out;
           }
-          const T tv = Elem<T>::from_f(last ? pv : out);
-          dst[ij] = tv;
-          if (!diag) dst[j * hp + i] = tv;
-          if (!last) P.accf[ij] = pv;
+          ov[e] = out;
+          pvv[e] = pv;
           const double dv = (double)out;
           lv = fma(dv, diag ? dv : 2.0 * dv, lv);
-          if (i == j) dg += dv;
+          if (i == j + e) dg += dv;
         }
+        if (a.ns_step < 0 && a.basis != kGram && !last)
+          *(float4 *)(P.df[(level + 1) & 1] + ij) = make_float4(ov[0], ov[1], ov[2], ov[3]);
+        if (!last) *(float4 *)(P.accf + ij) = make_float4(pvv[0], pvv[1], pvv[2], pvv[3]);
+        const float4 sv = last ? make_float4(pvv[0], pvv[1], pvv[2], pvv[3]) : make_float4(ov[0], ov[1], ov[2], ov[3]);
+        store4<T>(dst + ij, sv);
+        *(float4 *)(ep + row * TS + c4) = sv;  // the stored value, for the mirror
+      }
+    }
+    if (!a.ns_norm_pass && !diag) {
+      __syncthreads();
+      // mirror: block (n0.., m0..) = transpose of the stored tile, written row-wise
+      for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+        const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
+        store4<T>(dst + (int64_t)(n0 + row) * hp + m0 + c4,
+                  make_float4(ep[(c4 + 0) * TS + row], ep[(c4 + 1) * TS + row], ep[(c4 + 2) * TS + row],
+                              ep[(c4 + 3) * TS + row]));
+      }
+    }
     block_sum3(lv, dg, unused, (double *)smem);
     if (threadIdx.x == 0 && (a.ns_step < 0 || a.ns_norm_pass)) {
       const int nt = P.nt;
