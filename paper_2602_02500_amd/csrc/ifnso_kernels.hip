@@ -431,25 +431,57 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
     } else {
       tile.template run<false, true>(smem, Pb, hp, m0, P.hp, true, X, ldx, n0, P.w, xvec, P.h, false);
     }
+    // Epilogue through LDS in float4 row chunks of the tile (tile row tr, column tc). X is read
+    // along tc in both orientations; the destination runs along tc unless it is stored
+    // transposed relative to the tile (then a second pass writes it from LDS column-wise).
+    //   logical wide-orientation element (i, n): tall_map ? (tc, tr) : (tr, tc)
+    //   destination: to Y, trans ? Y[n][i] : Y[i][n];  to xbuf, xbuf[i][n]
+    const bool dst_t = to_y ? (P.trans && !tall_map) : tall_map;
+    const int64_t ldd = to_y ? P.ldy : P.ldx;
+    float *ep = (float *)smem;
+    __syncthreads();
+    stage_tile<TL, TS>(tile, ep);
+    __syncthreads();
+    for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+      const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
+      const int tr = m0 + row;
+      float yv[4];
 #pragma unroll
-    for (int fm = 0; fm < TL::FM; fm++)
-#pragma unroll
-      for (int fn = 0; fn < TL::FN; fn++)
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-          const int tr = m0 + TL::row_of(fm, r), tc = n0 + TL::col_of(fn);
-          // logical (i, n) in the wide orientation
-          const int i = tall_map ? tc : tr, n = tall_map ? tr : tc;
-          if (i >= P.h || n >= P.w) continue;
-          const int64_t xidx = tall_map ? (int64_t)n * ldx + i : (int64_t)i * ldx + n;
-          const float x = load_el<T>(X, xidx);
-          const float y = sc0 * x + sps * tile.acc[fm][fn][r];
-          int64_t didx;
-          if (to_y) didx = P.trans ? (int64_t)n * P.ldy + i : (int64_t)i * P.ldy + n;
-          else didx = (int64_t)i * P.ldx + n;
-          if (dst_bf16) ((uint16_t *)dst)[didx] = f32_to_bf16(y);
-          else ((float *)dst)[didx] = y;
+      for (int e = 0; e < 4; e++) {
+        const int tc = n0 + c4 + e;
+        const int i = tall_map ? tc : tr, n = tall_map ? tr : tc;
+        yv[e] = 0.f;
+        if (i < P.h && n < P.w) {
+          const float x = load_el<T>(X, (int64_t)tr * ldx + tc);
+          yv[e] = sc0 * x + sps * ep[row * TS + c4 + e];
+          if (!dst_t) {
+            const int64_t didx = (int64_t)tr * ldd + tc;
+            if (dst_bf16) ((uint16_t *)dst)[didx] = f32_to_bf16(yv[e]);
+            else ((float *)dst)[didx] = yv[e];
+          }
         }
+      }
+      if (dst_t) *(float4 *)(ep + row * TS + c4) = make_float4(yv[0], yv[1], yv[2], yv[3]);
+    }
+    if (dst_t) {
+      __syncthreads();
+      // destination row = tile column tc, running along tile rows tr
+      for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+        const int col = q / (TS / 4), r4 = (q % (TS / 4)) * 4;
+        const int tc = n0 + col;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int tr = m0 + r4 + e;
+          const int i = tall_map ? tc : tr, n = tall_map ? tr : tc;
+          if (i < P.h && n < P.w) {
+            const float y = ep[(r4 + e) * TS + col];
+            const int64_t didx = (int64_t)tc * ldd + tr;
+            if (dst_bf16) ((uint16_t *)dst)[didx] = f32_to_bf16(y);
+            else ((float *)dst)[didx] = y;
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 }
