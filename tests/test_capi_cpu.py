@@ -194,3 +194,14 @@ def test_stage_config_argument_checks(L):
     c = ifn.StageConfig(1, 32, 4, 8, 32)
     assert L.ifnso_plan_get_config(None, 0, ctypes.byref(c)) == 1
     assert L.ifnso_plan_set_config(None, 0, ctypes.byref(c)) == 1
+
+
+def test_c_client_compiles_and_links(tmp_path):
+    """The plain-C client of the ABI builds with gcc against include/ifnso.h and libifnso.so
+    alone; without a GPU it stops after its device check."""
+    import subprocess
+    import __graft_entry__ as ge
+    exe = ge.build_capi_client(str(tmp_path / "capi_client"))
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode in (0, 2), r.stdout + r.stderr
+    assert ("no GPU" in r.stdout) or r.stdout.strip().endswith("OK")
