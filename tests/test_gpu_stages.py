@@ -1,0 +1,81 @@
+"""Stage-level parity on the GPU: the Gram matrix and each squaring level, one at a time,
+against the FP64 oracle's intermediates.
+
+The output exposes them without reading the workspace. For M = [Z | I] (h x 2h), X = M / s
+and Y = P X, so the right block of Y is P / s. With exponents {0, 2^j} and coefficients
+(0, 1) the sum P is the single power B^(2^j): the Gram matrix B = X X^T for j = 0, then the
+level that the j-th squaring produces (B = I - X X^T in the complement basis). Each case
+therefore checks one more stage than the one before it.
+
+Bounds (relative Frobenius distance to the oracle's power on the same input bytes): float32
+1e-4; split bf16 (complement basis) 3e-3, as for the end-to-end tests. Single bf16 operands:
+every stored level is rounded to bf16 (relative 2^-9 at most) and a squaring doubles the
+relative error of its operand, so level j carries up to (2^(j+1) - 1) 2^-9; the bound is three
+times that (5.9e-3 for the Gram, 0.18 for the fourth squaring).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02500_amd as ifn
+    ifn.load()
+    return torch, torch.device("cuda:0")
+
+
+def _input(h, seed):
+    Z = gen.gaussian_np(h, h, seed) * 0.5
+    return np.concatenate([Z, np.eye(h)], axis=1)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [
+    # (compute, basis, norm, flags, tolerance)
+    ("f32", "gram", "frobenius", 0, 1e-4),
+    ("bf16", "gram", "frobenius", 0, None),
+    ("f32", "complement", "gram_frobenius", 0, 1e-4),
+    ("bf16", "complement", "gram_frobenius", "split", 3e-3),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}-{'split' if c[3] else 'plain'}")
+@pytest.mark.parametrize("h", [256, 200])
+@pytest.mark.parametrize("j", [0, 1, 2, 3, 4])
+def test_single_power(tdev, case, h, j):
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    compute, basis, norm, flags, tol = case
+    exps, coeffs = (0, 1 << j), (0.0, 1.0)
+    M = _input(h, seed=300 + h)
+    if compute == "f32":
+        vals = M.astype(np.float32).astype(np.float64)
+        Mt = torch.from_numpy(vals.astype(np.float32)).to(dev)
+    else:
+        vals = gen.round_to_bf16_np(M)
+        Mt = torch.from_numpy(vals.astype(np.float32)).to(dev).to(torch.bfloat16)
+    fl = ifn.FLAG_SPLIT_BF16 if flags == "split" else 0
+    plan = ifn.Plan(exps, coeffs, [(h, 2 * h)], basis=basis, norm=norm, compute=compute,
+                    out_dtype=ifn.F32, flags=fl)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    Y = torch.full((h, 2 * h), float("nan"), dtype=torch.float32, device=dev)
+    plan.orthogonalize(Mt, Y, ws)
+    torch.cuda.synchronize()
+    parts = oracle.ifnso_parts(vals, exps, coeffs, basis, norm)
+    P_gpu = Y.cpu().numpy().astype(np.float64)[:, h:] * parts["scale"]
+    if tol is None:
+        tol = 3.0 * (2 ** (j + 1) - 1) * 2.0 ** -9
+    r = _rel(P_gpu, parts["P"])
+    print(f"{case[:2]} h={h} power 2^{j}: rel {r:.2e}")
+    assert r <= tol
