@@ -333,10 +333,20 @@ def classical_ns_workspace_bytes(rows: int, cols: int, compute="bf16") -> int:
     return int(load().ifnso_classical_ns_workspace_bytes(rows, cols, comp))
 
 
+def _ns_workspace(M, compute, workspace):
+    """The caller's workspace, or a new one of classical_ns_workspace_bytes on M's device."""
+    if workspace is not None:
+        return workspace
+    import torch
+    rows, cols = M.shape
+    return torch.empty(classical_ns_workspace_bytes(rows, cols, compute), dtype=torch.uint8, device=M.device)
+
+
 def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=None):
     L = load()
     comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
     rows, cols = M.shape
+    workspace = _ns_workspace(M, comp, workspace)
     abc_c = (ctypes.c_double * 3)(*[float(x) for x in abc])
     nb = workspace.numel() * workspace.element_size()
     _check(L.ifnso_classical_ns(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
@@ -346,10 +356,12 @@ def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=N
 def ns_schedule(M, Y, schedule, gelfand_q: int = 0, compute="bf16", workspace=None, stream=None):
     """Newton-Schulz with one (a, b, c) per step (``schedule``: a sequence of triples) and the
     input scaled by ||A||_F (gelfand_q = 0) or by ||(AA^T)^q||_F^(1/(2q)) (q = 1, 2).
-    Workspace: classical_ns_workspace_bytes(rows, cols, compute) bytes."""
+    Workspace: classical_ns_workspace_bytes(rows, cols, compute) bytes (allocated here when
+    None is passed)."""
     L = load()
     comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
     rows, cols = M.shape
+    workspace = _ns_workspace(M, comp, workspace)
     flat = [float(x) for abc in schedule for x in abc]
     if len(flat) != 3 * len(schedule):
         raise ValueError("schedule entries must be (a, b, c) triples")

@@ -184,3 +184,18 @@ def test_longest_schedule(tdev, shape):
     sched2 = list(sched)
     sched2[9] = (1.3, -0.01, 0.002)
     assert _rel(_run(torch, dev, Mt, sched2, 0, "f32"), Yo) > 1e-3
+
+
+def test_binding_allocates_a_workspace_when_none_is_given(tdev):
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    Mt, _ = _dev(torch, dev, gen.gaussian_np(96, 200, seed=8), "f32")
+    sched, q = configs.load_schedule("muon_ns5")
+    Ya = _run(torch, dev, Mt, sched, q, "f32")
+    Yb = torch.empty_like(Mt)
+    ifn.ns_schedule(Mt, Yb, sched, q, "f32")
+    Yc = torch.empty_like(Mt)
+    ifn.classical_ns(Mt, Yc, 5, configs.MUON_ABC, "f32")
+    torch.cuda.synchronize()
+    assert np.array_equal(Ya, Yb.cpu().numpy().astype(np.float64))
+    assert np.array_equal(Ya, Yc.cpu().numpy().astype(np.float64))
