@@ -37,6 +37,9 @@ struct ProbDev {
   double *stats;       // [IFNSO_STATS_PER_PROBLEM]
   void *xbuf[2];       // classical NS: h x w iterates (wide orientation), leading dim ldx
   int64_t ldx;
+  float *gpart;        // classical NS, split Gram: [tiles][chunks][128 x 128] float32 partial tiles
+  double *gnrm;        //   [tiles][chunks][threads] partial sums of squares of A
+  uint32_t *gcnt;      //   [tiles] chunks finished (the last one sums the partials, then resets it)
   void *lv;            // level layout: level l (l = 1..J+1) stored at lv + (l-1) * lv_stride bytes,
   int64_t lv_stride;   //   as a full symmetric h x h operand; level 1 later holds P
   // e4m3 compute: per-tensor scaled OCP e4m3 copy of A (h rows, leading dimension ldq, K
@@ -73,6 +76,8 @@ struct StageArgs {
   int32_t ns_steps;    // classical NS: total steps (used by the h == 1 scalar path)
   int32_t ns_nsched;   // classical NS: entries of ns_sched; step k uses entry min(k, ns_nsched - 1)
   int32_t ns_norm_pass;  // squaring stage: only the float64 partials of ||G_raw^2||_F^2 (slot 2)
+  int32_t ksplit;      // generic Gram: K chunks per tile (1: none)
+  int32_t kchunk;      // generic Gram: K elements per chunk (a multiple of 128)
   double ns_sched[kMaxNsSteps][3];  // classical NS: the whole schedule (h == 1 scalar path)
   // XCD-aware schedule (fast kernels): workgroup b runs on XCD b % 8 and works through that
   // XCD's task queue tasks[xcd_off[x] .. + xcd_cnt[x]) with stride gridDim.x / 8

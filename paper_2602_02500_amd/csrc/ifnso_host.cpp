@@ -58,6 +58,9 @@ struct ProbLayout {
   int32_t h, w, trans, hp, nt;
   size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2], off_lv;
   int64_t ldx, lv_stride;
+  // classical NS: the Gram split along K (ksplit chunks of kchunk columns) when it has few tiles
+  int32_t ksplit, kchunk;
+  size_t off_gpart, off_gnrm, off_gcnt;
   // e4m3 compute
   size_t off_q8, off_qpart, off_qamax, off_amaxp, off_qscale;
   int64_t ldq;
@@ -72,6 +75,21 @@ constexpr int kQScaleFloats = 2 * (kMaxLevels + 1);
 void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
   rq = (int32_t)std::max<int64_t>(1, kQElems / cols);
   nq = (int32_t)((rows + rq - 1) / rq);
+}
+
+// Classical NS: K chunks of the Gram. A single problem with few 128-tiles leaves most CUs idle
+// while each tile runs the whole long dimension, so the Gram is split into up to 16 chunks of
+// at least 256 columns (a multiple of 128 each), aiming at about one workgroup per CU.
+static void ns_ksplit(int nt, int64_t w, int32_t &S, int32_t &kchunk) {
+  const int64_t nsym = (int64_t)nt * (nt + 1) / 2;
+  const int64_t want = std::min<int64_t>(16, std::min<int64_t>((256 + nsym - 1) / nsym, (w + 255) / 256));
+  if (want <= 1) {
+    S = 1;
+    kchunk = (int32_t)w;
+    return;
+  }
+  kchunk = (int32_t)round_up((w + want - 1) / want, 128);
+  S = (int32_t)((w + kchunk - 1) / kchunk);
 }
 
 // Workspace layout of one problem. levels = J + 2 partial slots; the complement basis adds the
@@ -119,6 +137,13 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.ldx = round_up(L.w, 8);
     L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
     L.off_xbuf[1] = take((size_t)L.h * L.ldx * op_size(op));
+    ns_ksplit(L.nt, L.w, L.ksplit, L.kchunk);
+    if (L.ksplit > 1) {
+      const size_t tiles = (size_t)L.nt * (L.nt + 1) / 2;
+      L.off_gpart = take(tiles * L.ksplit * kTS * kTS * 4);
+      L.off_gnrm = take(tiles * L.ksplit * kThreads * 8);
+      L.off_gcnt = take(tiles * 4);
+    }
   }
   if (e4m3) {
     // one e4m3 buffer: A (h x ldq) for the Gram, then each level (hp x hp) for its squaring
@@ -161,6 +186,9 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
   d.xbuf[0] = L.off_xbuf[0] ? ws + L.off_xbuf[0] : nullptr;
   d.xbuf[1] = L.off_xbuf[1] ? ws + L.off_xbuf[1] : nullptr;
   d.ldx = L.ldx;
+  d.gpart = L.off_gpart ? (float *)(ws + L.off_gpart) : nullptr;
+  d.gnrm = L.off_gnrm ? (double *)(ws + L.off_gnrm) : nullptr;
+  d.gcnt = L.off_gcnt ? (uint32_t *)(ws + L.off_gcnt) : nullptr;
   d.lv = L.lv_stride ? ws + L.off_lv : nullptr;
   d.lv_stride = L.lv_stride;
   if (L.ldq) {
@@ -1205,6 +1233,11 @@ static ifnso_status run_ns(const void *M, int64_t rows, int64_t cols, int64_t ld
     for (int i = 0; i < 3; i++) a.ns_sched[k][i] = sched[3 * k + i];
   const int nsym = L.nt * (L.nt + 1) / 2;
   hipStream_t s = (hipStream_t)stream;
+  if (L.ksplit > 1) {
+    a.ksplit = L.ksplit;
+    a.kchunk = L.kchunk;
+    HIP_TRY(launch_zero_u32(a.one.gcnt, nsym, s));  // the workspace arrives uninitialised
+  }
   a.ns_steps = steps;
   // h == 1: the product kernel runs the scalar recursion from the float64 norm in one pass
   const int passes = L.h == 1 ? 1 : steps;
@@ -1216,7 +1249,7 @@ static ifnso_status run_ns(const void *M, int64_t rows, int64_t cols, int64_t ld
     a.ntasks = nsym;
     a.level = 1;
     a.last = 1;
-    HIP_TRY(launch_stage(op, kTS, kStageGram, a, grid_for(op, kStageGram, nsym, cus), 0, s));
+    HIP_TRY(launch_stage(op, kTS, kStageGram, a, grid_for(op, kStageGram, nsym * std::max(1, a.ksplit), cus), 0, s));
     if (L.h > 1 && k == 0 && gelfand_q == 2) {
       // ||G_raw^2||_F^2 into level slot 2 before any consumer of the scale runs
       a.ns_norm_pass = 1;

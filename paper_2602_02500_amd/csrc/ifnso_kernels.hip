@@ -137,23 +137,33 @@ template <typename T, int TS>
 __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
   using TL = Tile<T, TS, TS>;
   __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
-  for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
-    const Task task = fetch_task<TS>(a, t, kStageGram);
+  __shared__ int s_last;
+  // Split K (single-problem launches with few tiles): task t is chunk t % S of tile t / S. Each
+  // chunk stores its partial tile; the last chunk of a tile to finish sums the S partials in
+  // chunk order (so the result does not depend on which one finishes last) and runs the epilogue.
+  const int S = a.ksplit > 1 ? a.ksplit : 1;
+  for (int t = blockIdx.x; t < a.ntasks * S; t += gridDim.x) {
+    const int tt = t / S, chunk = t % S;
+    const Task task = fetch_task<TS>(a, tt, kStageGram);
     const ProbDev &P = prob_of(a, task);
     const int m0 = task.tm * TS, n0 = task.tn * TS;
     const bool diag = task.tm == task.tn;
     const bool first_step = a.ns_step <= 0;
+    const int k0 = S > 1 ? chunk * a.kchunk : 0;
+    const int klen = S > 1 ? min(a.kchunk, P.w - k0) : P.w;
     TL tile;
-    double nrm;
-    if (!first_step) {  // classical NS, later steps: X_k (wide, K-major) from the workspace
-      const T *X = (const T *)P.xbuf[(a.ns_step - 1) & 1];
-      nrm = tile.template run<false, false>(smem, X, P.ldx, m0, P.h, true, X, P.ldx, n0, P.h, true, P.w, false);
+    double nrm = 0.0;
+    if (m0 >= P.h || n0 >= P.h) {  // a tile of the padding beyond h: zero
+      tile.zero();
+    } else if (!first_step) {  // classical NS, later steps: X_k (wide, K-major) from the workspace
+      const T *X = (const T *)P.xbuf[(a.ns_step - 1) & 1] + k0;
+      nrm = tile.template run<false, false>(smem, X, P.ldx, m0, P.h, true, X, P.ldx, n0, P.h, true, klen, false);
     } else if (P.trans) {
-      const T *M = (const T *)P.M;
-      nrm = tile.template run<true, true>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, P.w, diag);
+      const T *M = (const T *)P.M + (int64_t)k0 * P.ldm;
+      nrm = tile.template run<true, true>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, klen, diag);
     } else {
-      const T *M = (const T *)P.M;
-      nrm = tile.template run<false, false>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, P.w, diag);
+      const T *M = (const T *)P.M + k0;
+      nrm = tile.template run<false, false>(smem, M, P.ldm, m0, P.h, P.vecM, M, P.ldm, n0, P.h, P.vecM, klen, diag);
     }
     T *op = (T *)P.opnd[0];
     const int64_t hp = P.hp;
@@ -162,7 +172,36 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
     // epilogue through LDS, as in the squaring: row chunks, then the mirrored block
     float *ep = (float *)smem;
     __syncthreads();
-    stage_tile<TL, TS>(tile, ep);
+    if (S > 1) {
+      float *part = P.gpart + ((int64_t)tt * S + chunk) * (TS * TS);
+#pragma unroll
+      for (int fm = 0; fm < TL::FM; fm++)
+#pragma unroll
+        for (int fn = 0; fn < TL::FN; fn++)
+#pragma unroll
+          for (int r = 0; r < 16; r++) part[TL::row_of(fm, r) * TS + TL::col_of(fn)] = tile.acc[fm][fn][r];
+      P.gnrm[((int64_t)tt * S + chunk) * kThreads + threadIdx.x] = nrm;
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) s_last = atomicAdd(P.gcnt + tt, 1u) == (uint32_t)(S - 1);
+      __syncthreads();
+      if (!s_last) continue;  // the same for the whole workgroup
+      __threadfence();
+      const float *base = P.gpart + (int64_t)tt * S * (TS * TS);
+      for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
+        float4 v = *(const float4 *)(base + q * 4);
+        for (int c = 1; c < S; c++) {
+          const float4 w4 = *(const float4 *)(base + (int64_t)c * (TS * TS) + q * 4);
+          v = make_float4(v.x + w4.x, v.y + w4.y, v.z + w4.z, v.w + w4.w);
+        }
+        *(float4 *)(ep + q * 4) = v;
+      }
+      nrm = 0.0;
+      for (int c = 0; c < S; c++) nrm += P.gnrm[((int64_t)tt * S + c) * kThreads + threadIdx.x];
+      if (threadIdx.x == 0) P.gcnt[tt] = 0u;  // ready for the next launch
+    } else {
+      stage_tile<TL, TS>(tile, ep);
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < TS * TS / 4; q += kThreads) {
       const int row = q / (TS / 4), c4 = (q % (TS / 4)) * 4;
@@ -249,7 +288,8 @@ __global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
     const int64_t hp = P.hp;
     const T *src = (const T *)P.opnd[(level - 1) & 1];
     TL tile;
-    tile.template run<false, false>(smem, src, hp, m0, P.hp, true, src, hp, n0, P.hp, true, P.h, false);
+    if (m0 >= P.h || n0 >= P.h) tile.zero();  // a tile of the padding beyond h: zero
+    else tile.template run<false, false>(smem, src, hp, m0, P.hp, true, src, hp, n0, P.hp, true, P.h, false);
     T *dst = (T *)P.opnd[level & 1];
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
@@ -581,6 +621,16 @@ hipError_t launch_stage(int op, int ts, int stage, const StageArgs &a, int grid,
     if (ts == 128) return launch_stage_t<float, 128>(stage, a, grid, out_bf16, s);
   }
   return hipErrorInvalidValue;
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu) {

@@ -23,6 +23,8 @@ struct OrthArgs {
 };
 
 hipError_t launch_stage(int op, int ts, int stage, const StageArgs &a, int grid, int out_bf16, hipStream_t s);
+// n zero words at p (device), as a kernel (no memset node when captured in a graph)
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 hipError_t stage_occupancy(int op, int ts, int stage, int *blocks_per_cu);
 // bfloat16 fast path, 256 x 256 tiles (see ifnso_fast.hip for the operand requirements)
 hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid, int out_bf16, hipStream_t s);

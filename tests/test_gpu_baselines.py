@@ -199,3 +199,21 @@ def test_binding_allocates_a_workspace_when_none_is_given(tdev):
     torch.cuda.synchronize()
     assert np.array_equal(Ya, Yb.cpu().numpy().astype(np.float64))
     assert np.array_equal(Ya, Yc.cpu().numpy().astype(np.float64))
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(128, 8192), (100, 3000), (3000, 100), (260, 1500)])
+def test_long_inputs_split_gram(tdev, compute, shape):
+    """Few Gram tiles over a long dimension: the Gram is split along K into chunks (up to 16 of
+    them, the last one ragged, on the transposed path for tall inputs) whose partial tiles the last
+    chunk to finish adds in chunk order. Against the oracle, and bitwise equal over repeated calls."""
+    torch, dev = tdev
+    sched, q = configs.load_schedule("muon_ns5")
+    print(f"case split gram {shape} {compute}", flush=True)
+    Mt, vals = _dev(torch, dev, gen.gaussian_np(*shape, seed=21), compute)
+    Y = _run(torch, dev, Mt, sched, q, compute)
+    r = _rel(Y, BL.ns_schedule(vals, sched, q))
+    print(f"  rel {r:.2e}")
+    assert r <= (TOL_F32 if compute == "f32" else TOL_BF16["muon_ns5"])
+    for _ in range(3):
+        assert np.array_equal(_run(torch, dev, Mt, sched, q, compute), Y)
