@@ -218,7 +218,10 @@ ifnso_status ifnso_muon_step(ifnso_plan_t plan, const ifnso_muon_params *params,
  *   X_0 = A / ||A||_F,  X_{k+1} = a X_k + (b G_k + c G_k^2) X_k,  G_k = X_k X_k^T,
  * for `steps` steps (abc = {a, b, c}; {1.5, -0.5, 0} is the cubic of
  * Eq. (one_iteration_matrix)). M: device rows x cols (ldm), dtype `dtype` (F32 with
- * compute F32, BF16 with compute BF16); Y: device, same shape and dtype, ldy.
+ * compute F32, BF16 with compute BF16); Y: device, same shape and dtype, ldy. workspace:
+ * device, 256-byte aligned, ifnso_classical_ns_workspace_bytes bytes, owned by the caller; its
+ * contents on entry do not matter (the call clears the counters it uses before its first
+ * launch), and two calls that overlap in time must not share it.
  * Errors: INVALID_ARGUMENT, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP. */
 ifnso_status ifnso_classical_ns(const void *M, int64_t rows, int64_t cols, int64_t ldm, int32_t dtype,
                                 void *Y, int64_t ldy, int32_t steps, const double abc[3], int32_t compute,

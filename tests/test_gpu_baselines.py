@@ -217,3 +217,21 @@ def test_long_inputs_split_gram(tdev, compute, shape):
     assert r <= (TOL_F32 if compute == "f32" else TOL_BF16["muon_ns5"])
     for _ in range(3):
         assert np.array_equal(_run(torch, dev, Mt, sched, q, compute), Y)
+
+
+def test_workspace_contents_on_entry_do_not_matter(tdev):
+    """The split Gram's chunk counters live in the workspace: a workspace full of 0xff bytes (every
+    counter at its largest value) gives the same bits as a zeroed one."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    Mt, _ = _dev(torch, dev, gen.gaussian_np(128, 2048, seed=13), "bf16")
+    sched, q = configs.load_schedule("muon_ns5")
+    nbytes = ifn.classical_ns_workspace_bytes(128, 2048, "bf16")
+    out = []
+    for fill in (0, 255, 0):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device=dev)
+        Y = torch.empty_like(Mt)
+        ifn.ns_schedule(Mt, Y, sched, q, "bf16", ws)
+        torch.cuda.synchronize()
+        out.append(Y.float().cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
