@@ -58,7 +58,7 @@ struct ProbLayout {
   int32_t h, w, trans, hp, nt;
   size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2], off_lv;
   int64_t ldx, lv_stride;
-  // classical NS: the Gram split along K (ksplit chunks of kchunk columns) when it has few tiles
+  // the generic Gram split along K (ksplit chunks of kchunk columns) when it has few tiles
   int32_t ksplit, kchunk;
   size_t off_gpart, off_gnrm, off_gcnt;
   // e4m3 compute
@@ -77,10 +77,11 @@ void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
   nq = (int32_t)((rows + rq - 1) / rq);
 }
 
-// Classical NS: K chunks of the Gram. A single problem with few 128-tiles leaves most CUs idle
-// while each tile runs the whole long dimension, so the Gram is split into up to 16 chunks of
-// at least 256 columns (a multiple of 128 each), aiming at about one workgroup per CU.
-static void ns_ksplit(int nt, int64_t w, int32_t &S, int32_t &kchunk) {
+// K chunks of the generic Gram (Newton-Schulz, and single-problem plans on the generic kernels).
+// A single problem with few 128-tiles leaves most CUs idle while each tile runs the whole long
+// dimension, so the Gram is split into up to 16 chunks of at least 256 columns (a multiple of 128
+// each), aiming at about one workgroup per CU.
+static void gram_ksplit(int nt, int64_t w, int32_t &S, int32_t &kchunk) {
   const int64_t nsym = (int64_t)nt * (nt + 1) / 2;
   const int64_t want = std::min<int64_t>(16, std::min<int64_t>((256 + nsym - 1) / nsym, (w + 255) / 256));
   if (want <= 1) {
@@ -95,7 +96,7 @@ static void ns_ksplit(int nt, int64_t w, int32_t &S, int32_t &kchunk) {
 // Workspace layout of one problem. levels = J + 2 partial slots; the complement basis adds the
 // float32 D ping-pong unless its operands are split; classical NS adds two h x w iterates.
 ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
-                          bool e4m3 = false, bool split = false) {
+                          bool e4m3 = false, bool split = false, bool gsplit = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -137,7 +138,9 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.ldx = round_up(L.w, 8);
     L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
     L.off_xbuf[1] = take((size_t)L.h * L.ldx * op_size(op));
-    ns_ksplit(L.nt, L.w, L.ksplit, L.kchunk);
+  }
+  if (ns || gsplit) {
+    gram_ksplit(L.nt, L.w, L.ksplit, L.kchunk);
     if (L.ksplit > 1) {
       const size_t tiles = (size_t)L.nt * (L.nt + 1) / 2;
       L.off_gpart = take(tiles * L.ksplit * kTS * kTS * 4);
@@ -534,8 +537,10 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   p->fuse_agg = p->agg && !p->learned && p->J >= 1;
   size_t off = 0;
   for (int i = 0; i < num_problems; i++) {
+    // a single problem that always runs on the generic kernels may split its Gram along K
+    const bool gsplit = num_problems == 1 && !p->fast && !p->agg && !e4m3;
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
-                                    p->agg, e4m3, p->split));
+                                    p->agg, e4m3, p->split, gsplit));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -767,7 +772,19 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     } else if (t == 0) {
       a.ntasks = one ? ntiles_sym(kTS) : p->n_gram;
       if (!one) a.tasks = p->d_tasks + p->off_gram;
-      e = launch_stage(p->op, kTS, kStageGram, a, grid_for(p->op, kStageGram, a.ntasks, cus), outbf, s);
+      // split along K on the direct single-problem path only (a captured graph would keep the
+      // first call's counter address)
+      const bool ks = one && L0->ksplit > 1;
+      if (ks) {
+        a.ksplit = L0->ksplit;
+        a.kchunk = L0->kchunk;
+        e = launch_zero_u32(a.one.gcnt, a.ntasks, s);  // the workspace arrives uninitialised
+      }
+      if (e == hipSuccess)
+        e = launch_stage(p->op, kTS, kStageGram, a, grid_for(p->op, kStageGram, a.ntasks * (ks ? a.ksplit : 1), cus),
+                         outbf, s);
+      a.ksplit = 0;
+      a.kchunk = 0;
     }
     if (e != hipSuccess) return e;
   }

@@ -149,11 +149,14 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
     const int m0 = task.tm * TS, n0 = task.tn * TS;
     const bool diag = task.tm == task.tn;
     const bool first_step = a.ns_step <= 0;
+    // a tile of the padding beyond h is zero: its first chunk writes it without partials
+    const bool pad = m0 >= P.h || n0 >= P.h;
+    if (pad && chunk != 0) continue;  // uniform over the workgroup
     const int k0 = S > 1 ? chunk * a.kchunk : 0;
     const int klen = S > 1 ? min(a.kchunk, P.w - k0) : P.w;
     TL tile;
     double nrm = 0.0;
-    if (m0 >= P.h || n0 >= P.h) {  // a tile of the padding beyond h: zero
+    if (pad) {
       tile.zero();
     } else if (!first_step) {  // classical NS, later steps: X_k (wide, K-major) from the workspace
       const T *X = (const T *)P.xbuf[(a.ns_step - 1) & 1] + k0;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
     // epilogue through LDS, as in the squaring: row chunks, then the mirrored block
     float *ep = (float *)smem;
     __syncthreads();
-    if (S > 1) {
+    if (S > 1 && !pad) {
       float *part = P.gpart + ((int64_t)tt * S + chunk) * (TS * TS);
 #pragma unroll
       for (int fm = 0; fm < TL::FM; fm++)

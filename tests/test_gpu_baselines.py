@@ -202,11 +202,12 @@ def test_binding_allocates_a_workspace_when_none_is_given(tdev):
 
 
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
-@pytest.mark.parametrize("shape", [(128, 8192), (100, 3000), (3000, 100), (260, 1500)])
+@pytest.mark.parametrize("shape", [(128, 8192), (100, 3000), (3000, 100), (260, 1500), (1, 5000), (4100, 1)])
 def test_long_inputs_split_gram(tdev, compute, shape):
     """Few Gram tiles over a long dimension: the Gram is split along K into chunks (up to 16 of
     them, the last one ragged, on the transposed path for tall inputs) whose partial tiles the last
-    chunk to finish adds in chunk order. Against the oracle, and bitwise equal over repeated calls."""
+    chunk to finish adds in chunk order. Vectors split too (1 x 5000: 14 chunks, the last one 8
+    wide). Against the oracle, and bitwise equal over repeated calls."""
     torch, dev = tdev
     sched, q = configs.load_schedule("muon_ns5")
     print(f"case split gram {shape} {compute}", flush=True)

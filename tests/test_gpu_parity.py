@@ -112,6 +112,24 @@ def test_complement_basis_f32_paper_mode(torch_dev, shape):
     assert _rel(Y, oracle.ifnso_algorithm1(vals, c[1:])) <= TOL["f32"]
 
 
+@pytest.mark.parametrize("shape", [(128, 4096), (4100, 100), (1, 5000), (260, 1500)])
+def test_single_problem_split_gram_f32(torch_dev, shape):
+    """A single problem on the generic kernels with few Gram tiles over a long dimension: the Gram
+    splits along K (up to 16 chunks, the last one ragged; padding tiles written once). Both bases
+    against the oracle, and bitwise equal over repeated calls."""
+    torch, dev = torch_dev
+    M = gen.gaussian_np(*shape, seed=17)
+    for basis, norm, (exps, c) in (("gram", "frobenius", configs.load_coeffs("gform_v1")),
+                                   ("complement", "gram_frobenius", configs.load_coeffs("paper_L14"))):
+        print(f"case split gram {shape} {basis}", flush=True)
+        Y, vals = run_single(torch, dev, M, exps, c, basis=basis, norm=norm, compute="f32")
+        r = _rel(Y, oracle.ifnso(vals, exps, c, basis, norm))
+        print(f"  rel {r:.2e}")
+        assert r <= TOL["f32"]
+        for _ in range(2):
+            assert np.array_equal(run_single(torch, dev, M, exps, c, basis=basis, norm=norm, compute="f32")[0], Y)
+
+
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
 def test_complement_basis_moderate(torch_dev, compute):
     torch, dev = torch_dev
