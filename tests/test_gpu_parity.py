@@ -130,6 +130,22 @@ def test_single_problem_split_gram_f32(torch_dev, shape):
             assert np.array_equal(run_single(torch, dev, M, exps, c, basis=basis, norm=norm, compute="f32")[0], Y)
 
 
+@pytest.mark.parametrize("shape", [(128, 4096), (3000, 200)])
+def test_single_problem_split_gram_bf16_generic(torch_dev, monkeypatch, shape):
+    """bf16 plans created with the 256-tile kernels switched off (IFNSO_FAST=0) take the generic
+    kernels, and split their Gram along K like the float32 ones."""
+    torch, dev = torch_dev
+    monkeypatch.setenv("IFNSO_FAST", "0")
+    M = gen.gaussian_np(*shape, seed=19)
+    exps, c = configs.load_coeffs("gform_v1")
+    print(f"case split gram bf16 generic {shape}", flush=True)
+    Y, vals = run_single(torch, dev, M, exps, c, compute="bf16")
+    r = _rel(Y, oracle.ifnso(vals, exps, c))
+    print(f"  rel {r:.2e}")
+    assert r <= TOL["bf16"]
+    assert np.array_equal(run_single(torch, dev, M, exps, c, compute="bf16")[0], Y)
+
+
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
 def test_complement_basis_moderate(torch_dev, compute):
     torch, dev = torch_dev
