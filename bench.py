@@ -107,9 +107,21 @@ PROFILE_KERNEL = {"square": "kf_square<true, false, false>", "square_last": "kf_
                   "gram_tall": "kf_gram<true, false>", "product_wide": "kf_product<false, false>",
                   "product_tall": "kf_product<true, false>",
                   "aggregate": "kf_aggregate"}
+# the e4m3 workload: only its bf16 products come from the source file the summary's hash covers
+E4M3_PROFILE_KERNEL = {"product_wide": "kf_product<false, false>", "product_tall": "kf_product<true, false>"}
+# the paper's form with split bf16 operands: the squaring over K = 3 hp
+TFORM_PROFILE_KERNEL = {"square": "kf_square<false, true, false>"}
 
 
-def measured_traffic(kernel, summary):
+def _attach_traffic(line, kernel, summary, names=None):
+    """Adds the measured HBM bytes per launch of `kernel` to the line's roofline, when known."""
+    tr = measured_traffic(kernel, os.path.join(ROOT, "profiles", summary), names)
+    if tr is not None:
+        line["roofline"].update({"traffic": round(tr["bytes"]), "traffic_read": round(tr["read"]),
+                                 "traffic_write": round(tr["write"]), "traffic_source": tr["source"]})
+
+
+def measured_traffic(kernel, summary, names=None):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
     (calibrated against a plain copy of known size), or None when the summary is missing, lacks
     the kernel, or was taken on a different revision of the kernel source."""
@@ -120,7 +132,7 @@ def measured_traffic(kernel, summary):
         with open(os.path.join(ROOT, prof["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != prof["source_sha256"]:
                 return None
-        k = prof["kernels"][PROFILE_KERNEL[kernel]]
+        k = prof["kernels"][(names or PROFILE_KERNEL)[kernel]]
     except (OSError, KeyError, ValueError):
         return None
     return {"bytes": k["read_bytes"] + k["write_bytes"], "read": k["read_bytes"], "write": k["write_bytes"],
@@ -344,6 +356,8 @@ def run_e4m3(args, torch, dev, hip, log):
                      "avg_launch_ms": round(dur_ms, 3)},
         "cpu_baseline": cpu,
     }
+    if n == 64:
+        _attach_traffic(line, dom, "traffic_e4m3_batch64_2048x8192.json", E4M3_PROFILE_KERNEL)
     line.update(extra)
     print(json.dumps(line), flush=True)
 
@@ -508,6 +522,8 @@ def run_tform(args, torch, dev, hip, log):
         "parity_layer0_1024x4096_rel_vs_oracle": rel,
         "oracle_orth_err_over_sqrt_h_layer0_1024x4096": orth_o,
     }
+    if args.layers == 32 and split:
+        _attach_traffic(line, dom, "traffic_tform_gradset_224_bf16.json", TFORM_PROFILE_KERNEL)
     print(json.dumps(line), flush=True)
 
 
@@ -901,11 +917,8 @@ def main():
                      "avg_launch_ms": round(dur_ms, 3)},
         "cpu_baseline": cpu,
     }
-    tr = measured_traffic(dom, os.path.join(ROOT, "profiles", "traffic_gradset_224_bf16.json")) \
-        if args.layers == 32 else None
-    if tr is not None:
-        line["roofline"].update({"traffic": round(tr["bytes"]), "traffic_read": round(tr["read"]),
-                                 "traffic_write": round(tr["write"]), "traffic_source": tr["source"]})
+    if args.layers == 32:
+        _attach_traffic(line, dom, "traffic_gradset_224_bf16.json")
     line.update(extra)
     print(json.dumps(line), flush=True)
 
