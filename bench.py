@@ -200,6 +200,35 @@ def cpu_baseline_tform(Mh, Yd, exps, coeffs):
     return cpu, rel, orth
 
 
+def slot_names(plan):
+    """Kernel name of each launch slot of a Gram-basis bf16 plan, from the stage the library
+    reports for it (the two Grams and products are the wide and the tall list)."""
+    names, g, p = [], 0, 0
+    for i in range(plan.num_launches):
+        st = plan.launch_info(i)[0]
+        if st == 0:
+            names.append(("gram_wide", "gram_tall")[g])
+            g += 1
+        elif st == 1:
+            names.append("square")
+        elif st == 2:
+            names.append(("product_wide", "product_tall")[p])
+            p += 1
+        else:
+            names.append("aggregate" if st == 3 else "prep")
+    return names
+
+
+def roofline_of(kern):
+    """The roofline object of the kernel with the largest time per step (bf16 MFMA peak)."""
+    dom = max((k for k in kern if kern[k][2] > 0), key=lambda k: kern[k][0])
+    dur_ms = kern[dom][0] / kern[dom][1]
+    achieved = kern[dom][2] / kern[dom][1] / (dur_ms * 1e-3) / 1e12
+    return dom, {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                 "avg_launch_ms": round(dur_ms, 3)}
+
+
 def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
     """Warm-up, graph-replay timing, then `steps` timed calls with a HIP event before every
     launch slot (on the call's stream) and one after the last. Returns per-kernel
@@ -422,6 +451,9 @@ def run_learned(args, torch, dev, hip, log):
         if mode == "learned":
             st = plan.stats()
             entry["network_used_fraction"] = float(np.mean([row[25] for row in st]))
+            # per-launch times with HIP events on the call's stream, for the roofline
+            tp = time_plan(torch, hip, plan, Ms, Ys, ws, slot_names(plan), 3, 1, log)
+            dom, roof = roofline_of(tp["kern"])
         res[mode] = entry
         del ws, Ys, plan
     value = res["learned"]["matrices_per_s"]
@@ -437,8 +469,11 @@ def run_learned(args, torch, dev, hip, log):
                      "seconds": round(train_s, 3), "loss_first50": first, "loss_last50": last},
         "held_out_polar_dist2_over_h": held_out,
         "gradset": res,
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
+    if args.layers == 32:  # the same matrices and squaring kernel as the gradient-set summary
+        _attach_traffic(line, dom, "traffic_gradset_224_bf16.json")
     print(json.dumps(line), flush=True)
 
 
