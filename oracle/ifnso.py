@@ -21,7 +21,7 @@ from typing import Dict, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "orient", "normalise", "ifnso", "ifnso_parts", "ifnso_algorithm1", "classical_ns",
+    "orient", "normalise", "ifnso", "ifnso_parts", "paper_form", "classical_ns",
     "orth_error", "singular_value_map", "closed_form", "flops_ifnso", "flops_ns",
     "paper_w_last_approx", "paper_coeffs_to_terms", "BASES", "NORMS",
 ]
@@ -111,23 +111,24 @@ def ifnso(M: np.ndarray, exponents: Sequence[int], coeffs: Sequence[float],
     return ifnso_parts(M, exponents, coeffs, basis, norm)["Y"]
 
 
-def ifnso_algorithm1(M: np.ndarray, w: Sequence[float]) -> np.ndarray:
-    """Algorithm 1 of the paper, step by step, for learned w_1..w_L:
-    T_0 = A A^T, o = ||T_0||_F, T_1 = I - T_0 / o, T_l = T_{l-1} T_{l-1} (l = 2..L),
-    Y' = I + sum_l w_l T_l, Y = Y' A / sqrt(o). Returned in M's orientation."""
+def paper_form(M: np.ndarray, w: Sequence[float]) -> np.ndarray:
+    """The paper's own form of the method (Sec. 2.2, Eq. newnew_formula with the scale of
+    Eq. new_scale_formula; Algorithm 1 computes it), evaluated spectrally instead of by repeated
+    squaring: with A A^T = Q diag(lambda) Q^T and o = ||A A^T||_F, the polynomial in
+    T_1 = I - A A^T / o acts on each eigenvalue, so
+        Y = Q diag(1 + sum_l w_l (1 - lambda / o)^(2^(l-1))) Q^T A / sqrt(o).
+    Returned in M's orientation; a zero input gives zero. The squaring route is
+    :func:`ifnso` with :func:`paper_coeffs_to_terms` and the complement basis."""
     A, trans = orient(M)
-    h = A.shape[0]
-    T0 = A @ A.T
-    o = float(np.sqrt(np.sum(T0 * T0)))
+    lam, Q = np.linalg.eigh(A @ A.T)
+    o = float(np.sqrt(np.sum(lam * lam)))
     if o == 0.0:
         return np.zeros_like(np.asarray(M, dtype=np.float64))
-    T = [T0, np.eye(h) - T0 / o]
-    for _ in range(2, len(w) + 1):
-        T.append(T[-1] @ T[-1])
-    Yp = np.eye(h)
+    t = 1.0 - lam / o
+    d = np.ones_like(t)
     for l, wl in enumerate(w, start=1):
-        Yp = Yp + wl * T[l]
-    Y = Yp @ A / math.sqrt(o)
+        d = d + float(wl) * t ** (2 ** (l - 1))
+    Y = (Q * d) @ (Q.T @ A) / math.sqrt(o)
     return Y.T if trans else Y
 
 

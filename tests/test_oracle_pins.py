@@ -120,7 +120,7 @@ def test_zero_input_gives_zero():
     for norm in O.NORMS:
         assert np.all(O.ifnso(Z, [0, 1], [2.0, -1.0], "gram", norm) == 0)
     assert np.all(O.classical_ns(Z, 3, (3.4445, -4.775, 2.0315)) == 0)
-    assert np.all(O.ifnso_algorithm1(Z, [1.0, 2.0]) == 0)
+    assert np.all(O.paper_form(Z, [1.0, 2.0]) == 0)
 
 
 def test_ns_one_step_is_gram_polynomial(golden_dir):
@@ -222,14 +222,23 @@ def _compose(outer, inner):
     return res
 
 
-def test_algorithm1_equals_general_complement():
+def test_paper_form_spectral_equals_squaring_route():
+    """The paper's form through the eigendecomposition of A A^T and through repeated squaring of
+    the complement basis (two independent routes) agree; and on a prescribed spectrum both equal
+    U diag(sigma~ (1 + sum_l w_l (1 - sigma~^2)^(2^(l-1)))) V^T with sigma~ = sigma / ||sigma^2||^(1/2)."""
     M = gen.gaussian_np(30, 70, seed=13)
     w = O.tform_ls_fit(10)
     exps, c = O.paper_coeffs_to_terms(w)
-    Y1 = O.ifnso_algorithm1(M, w)
+    Y1 = O.paper_form(M, w)
     Y2 = O.ifnso(M, exps, c, "complement", "gram_frobenius")
     assert _rel(Y1, Y2) < 1e-11
-    assert _rel(O.ifnso_algorithm1(M.T, w), Y1.T) < 1e-14
+    assert _rel(O.paper_form(M.T, w), Y1.T) < 1e-14
+    sigma = np.linspace(0.05, 2.0, 12)
+    U = gen.haar_np(12, 12, 31, 1)
+    V = gen.haar_np(40, 12, 31, 2)
+    st = sigma / np.sqrt(np.sqrt(np.sum(sigma ** 4)))
+    f = st * (1.0 + sum(wl * (1.0 - st ** 2) ** (2 ** l) for l, wl in enumerate(w)))
+    assert _rel(O.paper_form((U * sigma) @ V.T, w), (U * f) @ V.T) < 1e-11
 
 
 def test_tl_recursion_is_explicit_power():
