@@ -5,10 +5,12 @@ generic kernels.
 Tolerances (relative Frobenius distance to the oracle on the same input bytes):
 * float32: 1e-4. A float32 numpy run of the same iterations stays below 1.2e-5 on these
   shapes for every schedule.
-* bfloat16: three times what a float64 model of the bf16 storage points (X_k, the Gram
-  operand, B_k = b G + c G^2 rounded to bf16) gives on these shapes: the schedules differ
-  widely in gain. The model gives 0.5 % (cubic, 8 steps), 1.8 % (Muon), 1.1 % (Cesista form)
-  and 5.5 % (CANS, whose first quintic has coefficients up to 25).
+* bfloat16: between three and four times what the float64 model of the bf16 storage points
+  gives on the cases the bound covers (oracle.bf16_model: ns_generic for the single-call path,
+  X_k, the Gram operand and B_k = b G + c G^2 rounded to bf16; ns_chained for the batched
+  plans), since the schedules differ widely in gain. The model gives up to 0.48 % (cubic,
+  8 steps), 2.1 % (Muon, on the long inputs), 0.99 % (Cesista form) and 4.9 % (CANS, whose first
+  quintic has coefficients up to 25). tests/test_oracle_bounds.py recomputes every bound.
 """
 import numpy as np
 import pytest
@@ -20,11 +22,17 @@ from workloads import configs, gen
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = ["original_ns8", "muon_ns5", "cesista_ns5", "cans_ns5_q2"]
+# cases shared with the bound check on the CPU: single calls in bf16 (seed 0), chained batched
+# plans (seed 40 + index), long inputs with a split Gram (Muon's schedule, seed 21)
+BF16_SHAPES = [(128, 512), (456, 200)]
+BATCHED_CASES = [("muon_ns5", 0), ("cesista_ns5", 0), ("original_ns8", 0), ("cans_ns5_q2", 1)]
+BATCHED_SHAPES = [(256, 512), (512, 256), (200, 456), (1, 64)]
+LONG_SHAPES = [(128, 8192), (100, 3000), (3000, 100), (260, 1500), (1, 5000), (4100, 1)]
 TOL_F32 = 1e-4
-TOL_BF16 = {"original_ns8": 1.5e-2, "muon_ns5": 6e-2, "cesista_ns5": 3.5e-2, "cans_ns5_q2": 0.17}
+TOL_BF16 = {"original_ns8": 1.5e-2, "muon_ns5": 7e-2, "cesista_ns5": 3.5e-2, "cans_ns5_q2": 0.17}
 # Vectors (h = 1) on the batched path: the iterate is rounded to bf16 between the chained plans
 # and the scalar map's slope at 1 amplifies that rounding (14 for the Cesista form's first step);
-# three times the same float64 model's error on the test's 1 x 64 vector (0.17 %, 0.46 %,
+# three to four times the same model's error on the test's 1 x 64 vector (0.17 %, 0.46 %,
 # 3.5 %, 0.33 %).
 TOL_BF16_H1 = {"original_ns8": 6e-3, "muon_ns5": 1.5e-2, "cesista_ns5": 0.11, "cans_ns5_q2": 1e-2}
 
@@ -76,7 +84,7 @@ def test_schedule_f32_matches_oracle(tdev, name, shape):
 
 
 @pytest.mark.parametrize("name", SCHEDULES)
-@pytest.mark.parametrize("shape", [(128, 512), (456, 200)])
+@pytest.mark.parametrize("shape", BF16_SHAPES)
 def test_schedule_bf16_matches_oracle(tdev, name, shape):
     torch, dev = tdev
     sched, q = configs.load_schedule(name)
@@ -142,7 +150,7 @@ def test_schedule_argument_errors(tdev):
         ifn.ns_schedule(Mt, Y, [configs.MUON_ABC], 0, "bf16", ws)  # f32 data, bf16 compute
 
 
-@pytest.mark.parametrize("name,q", [("muon_ns5", 0), ("cesista_ns5", 0), ("original_ns8", 0), ("cans_ns5_q2", 1)])
+@pytest.mark.parametrize("name,q", BATCHED_CASES)
 def test_schedule_plan_batched_matches_oracle(tdev, name, q):
     """The same schedules as chained batched plans on the 256-tile path (bf16 iterates between
     steps), against the oracle's iteration with the same scaling; the CANS schedule runs with
@@ -150,7 +158,7 @@ def test_schedule_plan_batched_matches_oracle(tdev, name, q):
     torch, dev = tdev
     import paper_2602_02500_amd as ifn
     sched, _ = configs.load_schedule(name)
-    shapes = [(256, 512), (512, 256), (200, 456), (1, 64)]
+    shapes = BATCHED_SHAPES
     print(f"case {name} q={q} batched", flush=True)
     Ms, vals = [], []
     for i, s in enumerate(shapes):
@@ -202,7 +210,7 @@ def test_binding_allocates_a_workspace_when_none_is_given(tdev):
 
 
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
-@pytest.mark.parametrize("shape", [(128, 8192), (100, 3000), (3000, 100), (260, 1500), (1, 5000), (4100, 1)])
+@pytest.mark.parametrize("shape", LONG_SHAPES)
 def test_long_inputs_split_gram(tdev, compute, shape):
     """Few Gram tiles over a long dimension: the Gram is split along K into chunks (up to 16 of
     them, the last one ragged, on the transposed path for tall inputs) whose partial tiles the last

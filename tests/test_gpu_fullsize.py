@@ -15,6 +15,9 @@ from workloads import configs, gen
 
 pytestmark = pytest.mark.gpu
 
+# Muon's five steps as chained bf16 plans on the pair (test_d2_pair_schedule_against_closed_form)
+TOL_D2_SCHEDULE_BF16 = 7.5e-2
+
 
 @pytest.fixture(scope="module")
 def tdev():
@@ -63,9 +66,10 @@ def test_d2_pair_schedule_against_closed_form(tdev):
     """Muon's five Newton-Schulz steps through chained batched plans (the `ns` benchmark's
     launch configuration) on the same pair: the iteration acts on singular values only, so the
     exact result is U diag(phi(sigma / ||sigma||)) V^T with phi the composed scalar map.
-    Bounds: float32 1e-4; bfloat16 0.1, three times what a float64 model of the bf16 storage
-    points (input, Gram operand, P, iterates) gives on a 1024x3584 matrix with the same
-    spectrum law (3.4e-2)."""
+    Bounds: float32 1e-4; bfloat16 7.5e-2, three times what the float64 model of the bf16 storage
+    points (oracle.bf16_model.ns_chained: input, stored Gram, P, iterates) gives on these two
+    matrices (2.0e-2 and 2.4e-2; tests/golden/bf16_bounds.json, rechecked by
+    tests/test_oracle_bounds.py)."""
     torch, dev = tdev
     import paper_2602_02500_amd as ifn
     from oracle import baselines as BL
@@ -81,7 +85,7 @@ def test_d2_pair_schedule_against_closed_form(tdev):
         mats.append(M)
         del U, V
     shapes = [tuple(m.shape) for m in mats]
-    for compute, dt, tol in [("f32", torch.float32, 1e-4), ("bf16", torch.bfloat16, 0.1)]:
+    for compute, dt, tol in [("f32", torch.float32, 1e-4), ("bf16", torch.bfloat16, TOL_D2_SCHEDULE_BF16)]:
         sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute=compute)
         Ms = [m.to(dt).contiguous() for m in mats]
         Ys = [torch.empty_like(m) for m in Ms]
@@ -94,3 +98,49 @@ def test_d2_pair_schedule_against_closed_form(tdev):
             print(f"  {compute} {rows}x{cols}: rel vs closed form {r:.3e}")
             assert r <= tol, (compute, rows, cols, r)
         del ws, Ys, Ms, tmp, sp
+
+
+# heavy-tailed batch (the e4m3 workload's matrices) through the bf16 path
+D4_SAMPLED = [0, 21, 42, 63]
+TOL_D4_CLOSED = 2e-2       # includes the bf16 rounding of the input (4.9e-3 of the 5.2e-3 the model gives)
+TOL_D4_ORACLE = 6e-3       # against the polynomial of the rounded input: 3.4x the model's 1.77e-3
+
+
+def test_heavy_tailed_batch_bf16(tdev):
+    """The 64 matrices 2048x8192 with sigma_i = i^-1.5 (Haar factors, seeds 3000 + i) through one
+    bf16 Gram-basis plan with the fixed coefficients, as the 256-tile path runs a batch. With
+    this spectrum the normalised largest singular value is 0.91, so every power of the Gram
+    matrix carries weight in the polynomial (the G^16 term alone moves f(sigma~_1) by 0.23): a
+    wrong squaring, level scale, mirror store or aggregation shows here, unlike on Gaussian or
+    log-uniform inputs where c_0 X dominates. Sampled matrices against the closed form
+    U diag(f(sigma~)) V^T, one against the float64 polynomial of its rounded input; the bounds
+    are derived from oracle.bf16_model.gram_levels (tests/golden/bf16_bounds.json)."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    exps, c = configs.load_coeffs("gform_v1")
+    rows, cols = configs.D4_SHAPE
+    n = configs.D4_BATCH
+    sigma = configs.d4_sigma(min(rows, cols))
+    Ms, keep = [], {}
+    for i in range(n):
+        M, U, V = gen.spectral_torch(rows, cols, sigma, configs.d4_seed(i), device=dev)
+        Ms.append(gen.round_to_bf16_torch(M))
+        if i in D4_SAMPLED:
+            keep[i] = (U.cpu().numpy(), V.cpu().numpy())
+        del M, U, V
+    print(f"case d4-shaped bf16 batch {n} x {rows}x{cols}", flush=True)
+    plan = ifn.Plan(exps, c, [(rows, cols)] * n, compute="bf16")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    for i in D4_SAMPLED:
+        U, V = keep[i]
+        Yd = Ys[i].double().cpu().numpy()
+        r = _rel(Yd, oracle.closed_form(U, sigma, V, exps, c))
+        print(f"  matrix {i}: rel vs closed form {r:.3e}")
+        assert r <= TOL_D4_CLOSED, (i, r)
+    vals = Ms[0].double().cpu().numpy()
+    r = _rel(Ys[0].double().cpu().numpy(), oracle.ifnso(vals, exps, c))
+    print(f"  matrix 0: rel vs the polynomial of its rounded input {r:.3e}")
+    assert r <= TOL_D4_ORACLE

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import bf16_model
 from workloads import configs, gen, spectra
 
 pytestmark = pytest.mark.gpu
@@ -112,7 +113,14 @@ def test_learned_plan_matches_oracle(tdev):
     for i, v in enumerate(vals):
         sig = np.linalg.svd(v, compute_uv=False)
         phi = oracle.features_from_spectrum(sig)
-        assert np.max(np.abs(np.array(st[i][1:9]) / (8 * 2.0 ** np.arange(8)) - phi)) < 2e-3
+        # log2 m_j on the device against the exact spectrum's, per j: within three times what the
+        # bf16 storage-point model of the trace computation deviates (up to 0.04 for m_7 on these
+        # inputs) plus 1e-4 for float32 accumulation
+        l2m = phi * (8 * 2.0 ** np.arange(8))
+        dev_l2m = np.array(st[i][1:9])
+        bound = 3.0 * np.abs(bf16_model.gram_traces(v) - l2m) + 1e-4
+        print(f"  problem {i}: |log2 m_j| deviations {np.abs(dev_l2m - l2m)}, bounds {bound}")
+        assert np.all(np.abs(dev_l2m - l2m) <= bound), i
         c_or, _ = oracle.mlp_forward(theta.astype(np.float64), phi)
         c_gpu = np.array(st[i][9:15])
         assert st[i][25] == 1.0

@@ -4,10 +4,11 @@ Tolerances are relative Frobenius errors: <= 1e-4 for the float32 path and <= 2e
 the bfloat16 path. Inputs are seeded; the oracle receives the exact values the device
 consumed (bfloat16-rounded where the device reads bfloat16).
 
-Classical Newton-Schulz in bfloat16 rounds every iterate and Gram operand to bfloat16, and five
-of Muon's steps amplify that rounding: a float64 model of those storage points already sits at
-1.5-2.0e-2 from the oracle on these shapes (1.7e-3 after one step). Its bound is three times
-that, 6e-2, as for the other Newton-Schulz schedules.
+Classical Newton-Schulz in bfloat16 rounds every iterate, Gram operand and B_k to bfloat16, and
+five of Muon's steps amplify that rounding: the float64 model of those storage points
+(oracle.bf16_model.ns_generic) sits at up to 2.01e-2 from the oracle on NS_SHAPES (1.7e-3 after
+one step). Its bound is 6.5e-2, between three and four times the model, as for the other
+Newton-Schulz schedules; tests/test_oracle_bounds.py recomputes it.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,10 @@ from workloads import configs, gen
 pytestmark = pytest.mark.gpu
 
 TOL = {"f32": 1e-4, "bf16": 2e-2}
-TOL_NS = {"f32": 1e-4, "bf16": 6e-2}
+TOL_NS = {"f32": 1e-4, "bf16": 6.5e-2}
+# classical Newton-Schulz cases (seed 0), shared with the bound check on the CPU
+NS_SHAPES = [(256, 512), (512, 256), (130, 300), (1, 40)]
+NS_STEPS = [1, 5]
 
 
 @pytest.fixture(scope="module")
@@ -101,15 +105,15 @@ def test_norms(torch_dev, compute, norm):
 
 @pytest.mark.parametrize("shape", [(200, 333), (333, 200), (64, 64), (1, 50)])
 def test_complement_basis_f32_paper_mode(torch_dev, shape):
-    """Algorithm 1 (T_l sequence with the Gram-Frobenius scale), depth L = 14, float32."""
+    """The paper's form (complement basis with the Gram-Frobenius scale), depth L = 14, float32."""
     torch, dev = torch_dev
     exps, c = configs.load_coeffs("paper_L14")
     M = gen.gaussian_np(*shape, seed=5)
     Y, vals = run_single(torch, dev, M, exps, c, basis="complement", norm="gram_frobenius", compute="f32")
     Yo = oracle.ifnso(vals, exps, c, "complement", "gram_frobenius")
     assert _rel(Y, Yo) <= TOL["f32"]
-    # and the literal Algorithm 1 of the oracle
-    assert _rel(Y, oracle.ifnso_algorithm1(vals, c[1:])) <= TOL["f32"]
+    # and the paper's form evaluated through the eigendecomposition of A A^T
+    assert _rel(Y, oracle.paper_form(vals, c[1:])) <= TOL["f32"]
 
 
 @pytest.mark.parametrize("shape", [(128, 4096), (4100, 100), (1, 5000), (260, 1500)])
@@ -241,8 +245,8 @@ def test_batched_mixed_shapes(torch_dev, compute):
 
 
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
-@pytest.mark.parametrize("shape", [(256, 512), (512, 256), (130, 300), (1, 40)])
-@pytest.mark.parametrize("steps", [1, 5])
+@pytest.mark.parametrize("shape", NS_SHAPES)
+@pytest.mark.parametrize("steps", NS_STEPS)
 def test_classical_ns(torch_dev, compute, shape, steps):
     torch, dev = torch_dev
     import paper_2602_02500_amd as ifn

@@ -8,11 +8,11 @@ operands lose the small eigencomponents of D that those coefficients amplify; sp
 (hi + lo pairs, three bf16 products per squaring, float32 accumulation, P as a pair) keep
 about 16 significant bits.
 
-Tolerance: relative Frobenius distance <= 3e-3 with float32 output. A float64 model of the
-split arithmetic (every squaring operand and P rounded to a hi + lo bf16 pair, all else exact)
-stays near 1e-4 on these shapes; the rest of the budget covers float32 accumulation over
-K = 3 hp, amplified by the coefficients. The unsplit bf16 path is reported alongside and must
-be at least ten times further from the oracle.
+Tolerance: relative Frobenius distance <= 7e-4 with float32 output, three to four times what
+the model of the split arithmetic gives on SHAPES (oracle.bf16_model.complement_split with
+float32 products: every squaring operand and P rounded to a hi + lo bf16 pair; up to 2.2e-4, at
+384 x 384; tests/test_oracle_bounds.py recomputes it). The unsplit bf16 path is reported
+alongside and must be at least ten times further from the oracle.
 """
 import numpy as np
 import pytest
@@ -22,7 +22,7 @@ from workloads import configs, gen
 
 pytestmark = pytest.mark.gpu
 
-TOL_SPLIT = 3e-3
+TOL_SPLIT = 7e-4
 
 
 @pytest.fixture(scope="module")
