@@ -177,6 +177,48 @@ def _dtype_code(t) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
+WORKSPACE_ALIGN = 256  # bytes; every workspace of the library starts at such an address
+_DTYPE_NAME = {F32: "float32", BF16: "bfloat16"}
+
+
+def check_matrix(t, name: str, shape, dtype: int, device: int) -> None:
+    """Raises unless `t` is a torch tensor that the library can read or write as a row-major
+    `shape` matrix of `dtype` (F32 or BF16) on GPU `device`: dtype, then shape, then unit
+    column stride and a row stride of at least the column count, then the device. Nothing
+    reaches the C ABI before every tensor of a call has passed."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = torch.float32 if dtype == F32 else torch.bfloat16
+    if t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype}, the plan needs {_DTYPE_NAME[dtype]}")
+    if t.dim() != 2 or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, the plan needs {tuple(shape)}")
+    if t.stride(1) != 1 or t.stride(0) < max(1, shape[1]):
+        raise ValueError(f"{name}: strides {t.stride()} are not a row-major layout (unit column stride, "
+                         f"row stride >= {shape[1]})")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name}: on {t.device}, the plan runs on cuda:{device}")
+
+
+def check_workspace(ws, need: int, device: int) -> int:
+    """Raises unless `ws` is a contiguous tensor of at least `need` bytes on GPU `device`,
+    starting at a WORKSPACE_ALIGN-byte address; returns its size in bytes."""
+    import torch
+    if not isinstance(ws, torch.Tensor):
+        raise TypeError(f"workspace: expected a torch tensor, got {type(ws).__name__}")
+    nb = ws.numel() * ws.element_size()
+    if nb < need:
+        raise ValueError(f"workspace: {nb} bytes, the call needs {need}")
+    if not ws.is_contiguous():
+        raise ValueError("workspace: not contiguous")
+    if ws.device.type != "cuda" or ws.device.index != device:
+        raise ValueError(f"workspace: on {ws.device}, the plan runs on cuda:{device}")
+    if ws.data_ptr() % WORKSPACE_ALIGN:
+        raise ValueError(f"workspace: address not {WORKSPACE_ALIGN}-byte aligned")
+    return nb
+
+
 class Plan:
     """A plan over problems of the given (rows, cols) shapes (ifnso_plan)."""
 
@@ -205,6 +247,7 @@ class Plan:
         if out_dtype is None:
             out_dtype = in_dtype
         self.in_dtype, self.out_dtype = int(in_dtype), int(out_dtype)
+        self.device = int(device)
         h = ctypes.c_void_p()
         _check(L.ifnso_plan(ctypes.byref(d), n, rows, cols, self.in_dtype, self.out_dtype, int(device),
                             ctypes.byref(h)))
@@ -215,25 +258,45 @@ class Plan:
         _check(L.ifnso_muon_workspace_bytes(h, ctypes.byref(b)))
         self.muon_workspace_bytes = b.value
 
+    def check_io(self, Ms, Ys) -> None:
+        """Raises unless Ms and Ys are the plan's problems in order: dtype, shape, layout and
+        device (check_matrix)."""
+        if len(Ms) != len(self.shapes) or len(Ys) != len(self.shapes):
+            raise ValueError(f"{len(Ms)} inputs and {len(Ys)} outputs for a plan of {len(self.shapes)} problems")
+        for i, (m, y, s) in enumerate(zip(Ms, Ys, self.shapes)):
+            check_matrix(m, f"M[{i}]", s, self.in_dtype, self.device)
+            check_matrix(y, f"Y[{i}]", s, self.out_dtype, self.device)
+
     def orthogonalize(self, M, Y, workspace, stream=None):
-        ws = _ptr(workspace)
-        nb = self.workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
-        _check(self._L.ifnso_orthogonalize(self._h, _ptr(M), int(M.stride(0)), _ptr(Y), int(Y.stride(0)), ws, nb,
-                                           _stream(stream)))
+        if len(self.shapes) != 1:
+            raise ValueError("orthogonalize takes a single-problem plan; use orthogonalize_batched")
+        self.check_io([M], [Y])
+        nb = check_workspace(workspace, self.workspace_bytes, self.device)
+        _check(self._L.ifnso_orthogonalize(self._h, _ptr(M), int(M.stride(0)), _ptr(Y), int(Y.stride(0)),
+                                           _ptr(workspace), nb, _stream(stream)))
 
     def orthogonalize_batched(self, Ms, Ys, workspace, stream=None):
+        self.check_io(Ms, Ys)
+        nb = check_workspace(workspace, self.workspace_bytes, self.device)
         n = len(Ms)
         mp = (ctypes.c_void_p * n)(*[_ptr(m) for m in Ms])
         yp = (ctypes.c_void_p * n)(*[_ptr(y) for y in Ys])
         ldm = (ctypes.c_int64 * n)(*[int(m.stride(0)) for m in Ms])
         ldy = (ctypes.c_int64 * n)(*[int(y.stride(0)) for y in Ys])
-        nb = self.workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
         _check(self._L.ifnso_orthogonalize_batched(self._h, mp, ldm, yp, ldy, _ptr(workspace), nb, _stream(stream)))
 
     def muon_step(self, Ws, Gs, Bs, workspace, lr, momentum, weight_decay=0.0, nesterov=True, stream=None):
         """One Muon step (ifnso_muon_step): Ws, Bs float32 weights and momentum (updated in place),
         Gs gradients in the plan's input type, workspace of muon_workspace_bytes."""
         n = len(Ws)
+        if not (len(Gs) == len(Bs) == n == len(self.shapes)):
+            raise ValueError(f"{n} weights, {len(Gs)} gradients, {len(Bs)} momenta for a plan of "
+                             f"{len(self.shapes)} problems")
+        for i, s in enumerate(self.shapes):
+            check_matrix(Ws[i], f"W[{i}]", s, F32, self.device)
+            check_matrix(Gs[i], f"G[{i}]", s, self.in_dtype, self.device)
+            check_matrix(Bs[i], f"B[{i}]", s, F32, self.device)
+        nb = check_workspace(workspace, self.muon_workspace_bytes, self.device)
         wp = (ctypes.c_void_p * n)(*[_ptr(w) for w in Ws])
         gp = (ctypes.c_void_p * n)(*[_ptr(g) for g in Gs])
         bp = (ctypes.c_void_p * n)(*[_ptr(b) for b in Bs])
@@ -241,7 +304,6 @@ class Plan:
         ldg = (ctypes.c_int64 * n)(*[int(g.stride(0)) for g in Gs])
         ldb = (ctypes.c_int64 * n)(*[int(b.stride(0)) for b in Bs])
         hp = MuonParams(float(lr), float(momentum), float(weight_decay), 1 if nesterov else 0)
-        nb = self.muon_workspace_bytes if isinstance(workspace, int) else workspace.numel() * workspace.element_size()
         _check(self._L.ifnso_muon_step(self._h, ctypes.byref(hp), wp, ldw, gp, ldg, bp, ldb, _ptr(workspace), nb,
                                        _stream(stream)))
 
@@ -333,22 +395,29 @@ def classical_ns_workspace_bytes(rows: int, cols: int, compute="bf16") -> int:
     return int(load().ifnso_classical_ns_workspace_bytes(rows, cols, comp))
 
 
-def _ns_workspace(M, compute, workspace):
-    """The caller's workspace, or a new one of classical_ns_workspace_bytes on M's device."""
-    if workspace is not None:
-        return workspace
+def _ns_args(M, Y, compute, workspace):
+    """Checks M, Y (same dtype, shape and GPU, row-major) and the workspace of a single-matrix
+    Newton-Schulz call; allocates the workspace (classical_ns_workspace_bytes on M's device)
+    when None is passed. Returns (rows, cols, workspace, its size in bytes)."""
     import torch
-    rows, cols = M.shape
-    return torch.empty(classical_ns_workspace_bytes(rows, cols, compute), dtype=torch.uint8, device=M.device)
+    if not isinstance(M, torch.Tensor) or M.dim() != 2:
+        raise TypeError("M: expected a 2-d torch tensor")
+    rows, cols = (int(x) for x in M.shape)
+    dt = _dtype_code(M)
+    dev = M.device.index if M.device.type == "cuda" else -1
+    check_matrix(M, "M", (rows, cols), dt, dev)
+    check_matrix(Y, "Y", (rows, cols), dt, dev)
+    need = classical_ns_workspace_bytes(rows, cols, compute)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=M.device)
+    return rows, cols, workspace, check_workspace(workspace, need, dev)
 
 
 def classical_ns(M, Y, steps: int, abc, compute="bf16", workspace=None, stream=None):
     L = load()
     comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
-    rows, cols = M.shape
-    workspace = _ns_workspace(M, comp, workspace)
+    rows, cols, workspace, nb = _ns_args(M, Y, comp, workspace)
     abc_c = (ctypes.c_double * 3)(*[float(x) for x in abc])
-    nb = workspace.numel() * workspace.element_size()
     _check(L.ifnso_classical_ns(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
                                 int(steps), abc_c, comp, _ptr(workspace), nb, _stream(stream)))
 
@@ -360,13 +429,11 @@ def ns_schedule(M, Y, schedule, gelfand_q: int = 0, compute="bf16", workspace=No
     None is passed)."""
     L = load()
     comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
-    rows, cols = M.shape
-    workspace = _ns_workspace(M, comp, workspace)
+    rows, cols, workspace, nb = _ns_args(M, Y, comp, workspace)
     flat = [float(x) for abc in schedule for x in abc]
     if len(flat) != 3 * len(schedule):
         raise ValueError("schedule entries must be (a, b, c) triples")
     abc_c = (ctypes.c_double * max(len(flat), 3))(*flat)
-    nb = workspace.numel() * workspace.element_size()
     _check(L.ifnso_ns_schedule(_ptr(M), rows, cols, int(M.stride(0)), _dtype_code(M), _ptr(Y), int(Y.stride(0)),
                                len(schedule), abc_c, int(gelfand_q), comp, _ptr(workspace), nb, _stream(stream)))
 

@@ -205,3 +205,47 @@ def test_c_client_compiles_and_links(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode in (0, 2), r.stdout + r.stderr
     assert ("no GPU" in r.stdout) or r.stdout.strip().endswith("OK")
+
+
+def test_binding_rejects_mismatched_tensors():
+    """The binding checks every tensor against the plan before any pointer reaches the C ABI:
+    dtype, shape, row-major layout with unit column stride, device, and for workspaces size,
+    contiguity and alignment. On the CPU the device check is the last one to fire."""
+    import torch
+    shape = (6, 10)
+    good = torch.zeros(shape, dtype=torch.bfloat16)
+    with pytest.raises(TypeError):
+        ifn.check_matrix(good.float(), "M", shape, ifn.BF16, 0)
+    with pytest.raises(TypeError):
+        ifn.check_matrix(good, "Y", shape, ifn.F32, 0)
+    with pytest.raises(TypeError):
+        ifn.check_matrix([1.0], "M", shape, ifn.BF16, 0)
+    with pytest.raises(ValueError):
+        ifn.check_matrix(torch.zeros((6, 11), dtype=torch.bfloat16), "M", shape, ifn.BF16, 0)
+    with pytest.raises(ValueError):
+        ifn.check_matrix(torch.zeros((60,), dtype=torch.bfloat16), "M", shape, ifn.BF16, 0)
+    with pytest.raises(ValueError):  # a column-strided view: every other element
+        ifn.check_matrix(torch.zeros((6, 20), dtype=torch.bfloat16)[:, ::2], "M", shape, ifn.BF16, 0)
+    with pytest.raises(ValueError):  # a transposed view (column-major)
+        ifn.check_matrix(torch.zeros((10, 6), dtype=torch.bfloat16).t(), "M", shape, ifn.BF16, 0)
+    with pytest.raises(ValueError) as e:  # every other property holds: the device is wrong
+        ifn.check_matrix(good, "M", shape, ifn.BF16, 0)
+    assert "cuda:0" in str(e.value)
+    # a row-padded view (leading dimension above the column count) is a valid layout
+    padded = torch.zeros((6, 16), dtype=torch.bfloat16)[:, :10]
+    with pytest.raises(ValueError) as e:
+        ifn.check_matrix(padded, "M", shape, ifn.BF16, 0)
+    assert "cuda:0" in str(e.value)
+
+
+def test_binding_rejects_bad_workspaces():
+    import torch
+    with pytest.raises(TypeError):
+        ifn.check_workspace(12345, 64, 0)
+    with pytest.raises(ValueError):
+        ifn.check_workspace(torch.empty(63, dtype=torch.uint8), 64, 0)
+    with pytest.raises(ValueError):
+        ifn.check_workspace(torch.empty((16, 8), dtype=torch.uint8).t(), 64, 0)
+    with pytest.raises(ValueError) as e:
+        ifn.check_workspace(torch.empty(64, dtype=torch.uint8), 64, 0)
+    assert "cuda:0" in str(e.value)

@@ -112,8 +112,18 @@ def test_argument_checks(tdev):
     plan = ifn.Plan(exps, c, shapes, compute="bf16")
     Ws, Gs, Bs, _ = _setup(torch, dev, shapes, seed=95)
     small = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)  # the plan's alone is too small
-    with pytest.raises(ifn.IfnsoError):
+    with pytest.raises(ValueError):  # the binding refuses it before the call
         plan.muon_step(Ws, Gs, Bs, small, 0.1, 0.9)
+    # and so does the library itself, called directly
+    import ctypes
+    L = ifn.load()
+    n = len(shapes)
+    arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+    lds = lambda ts: (ctypes.c_int64 * n)(*[t.stride(0) for t in ts])  # noqa: E731
+    hp = ifn.MuonParams(0.1, 0.9, 0.0, 1)
+    st = L.ifnso_muon_step(plan._h, ctypes.byref(hp), arr(Ws), lds(Ws), arr(Gs), lds(Gs), arr(Bs), lds(Bs),
+                           small.data_ptr(), small.numel(), torch.cuda.current_stream().cuda_stream)
+    assert st == 3, L.ifnso_last_error()  # IFNSO_ERR_WORKSPACE_TOO_SMALL
     ws = torch.empty(plan.muon_workspace_bytes, dtype=torch.uint8, device=dev)
     with pytest.raises(ifn.IfnsoError):
         plan.muon_step(Ws, Gs, Bs, ws, float("nan"), 0.9)
