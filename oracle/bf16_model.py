@@ -166,11 +166,30 @@ def complement_split(M, exponents: Sequence[int], coeffs: Sequence[float], norm:
     (module docstring): D_1 = -X X^T, D_{l+1} = 2 D_l + D_l^2 (T = I + D), P = sum_{k>=1} c_k
     D_{e_k} carried as a split pair, Y = (sum_k c_k) X + P X. ``accum=np.float32`` evaluates the
     matrix products in float32 (the device's accumulation type; the operands are exact in it).
+    ``accum="f32seq"`` also rounds every value the kernels keep in float32 (the Gram, D_l, the
+    running sum P) and sums each product in float32 along K, one rounding per 16 products into
+    one accumulator over the concatenated K (hi hi, then hi lo, then lo hi), as a matrix-core
+    accumulator does; the order inside a step is not modelled.
     Returns Y in M's orientation (float32 output)."""
     e, c = _check_terms(exponents, coeffs)
     A, trans = orient(M)
     h = A.shape[0]
-    G = A @ A.T
+    seq = isinstance(accum, str) and accum == "f32seq"
+
+    def r32(x):  # a float32 store (f32seq only; the other modes keep float64)
+        return np.asarray(x, dtype=np.float32).astype(np.float64) if seq else x
+
+    def mm(*pairs):
+        """sum of x @ y over the pairs: one accumulation over the concatenated K"""
+        if seq:
+            acc = np.zeros((pairs[0][0].shape[0], pairs[0][1].shape[1]))
+            for x, y in pairs:
+                for k0 in range(0, x.shape[1], 16):
+                    acc = r32(acc + x[:, k0:k0 + 16] @ y[k0:k0 + 16, :])
+            return acc
+        return sum((x.astype(accum) @ y.astype(accum)).astype(np.float64) for x, y in pairs)
+
+    G = mm((A, A.T)) if seq else A @ A.T
     n = _scale(A, G, norm)
     if n == 0.0:
         Y = np.zeros_like(A)
@@ -181,36 +200,31 @@ def complement_split(M, exponents: Sequence[int], coeffs: Sequence[float], norm:
         v = sum(ck * g ** ek for ek, ck in zip(e, c))
         Y = v * A / n
         return Y.T if trans else Y
-
-    def mm(x, y):
-        return (x.astype(accum) @ y.astype(accum)).astype(np.float64)
-
     J = 0
     while (1 << J) < e[-1]:
         J += 1
     coef = {ek: ck for ek, ck in zip(e, c)}
-    D = -G / (n * n)                           # D_1 from the float32 Gram
-    P = coef.get(1, 0.0) * D
+    D = r32(-G / (n * n))                      # D_1 from the float32 Gram
+    P = r32(coef.get(1, 0.0) * D)
     op = split_pair(G, store)                  # the Gram operand, split
     for l in range(1, J + 1):
         hi, lo = op
-        sq = mm(hi, hi) + mm(hi, lo) + mm(lo, hi)
+        sq = mm((hi, hi), (hi, lo), (lo, hi))
         if l == 1:
             sq = sq / (n * n) ** 2
             Dl = D
         else:
             Dl = hi + lo                       # D_l read back from its split operand
-        D = 2.0 * Dl + sq
-        P = P + coef.get(1 << l, 0.0) * D
+        D = r32(2.0 * Dl + sq)
+        P = r32(P + coef.get(1 << l, 0.0) * D)
         op = split_pair(D, store)
     if J >= 1:
         ph, pl = split_pair(P, store)
     else:  # no squaring: the product reads c_1 D_1 from the split Gram operand
         w1 = -coef.get(1, 0.0) / (n * n)
         ph, pl = w1 * op[0], w1 * op[1]
-    Y = (csum * A + mm(ph, A) + mm(pl, A)) / n
+    Y = (csum * A + mm((ph, A), (pl, A))) / n
     return Y.T if trans else Y
-
 
 
 def gram_traces(M, levels: int = 8, store=bf16_round) -> np.ndarray:
