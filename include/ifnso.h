@@ -133,6 +133,21 @@ ifnso_status ifnso_plan_destroy(ifnso_plan_t plan);
 ifnso_status ifnso_orthogonalize(ifnso_plan_t plan, const void *M, int64_t ldm, void *Y, int64_t ldy,
                                  void *workspace, size_t workspace_bytes, void *stream);
 
+/* ifnso_orthogonalize without a workspace argument, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid allocation).
+ * The workspace is a fixed scratch area inside the library, IFNSO_STATIC_SCRATCH_BYTES
+ * (64 MiB) on each GPU, held from the library's first use of that GPU until the process ends;
+ * the call allocates nothing. Same arguments, layout and result as ifnso_orthogonalize
+ * (bitwise), for a plan with num_problems == 1 whose ifnso_plan_workspace_bytes is at most
+ * IFNSO_STATIC_SCRATCH_BYTES. Every call on one GPU shares that GPU's area and leaves its
+ * contents behind (nothing in it needs to start at zero): calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race and must be serialised
+ * by the caller. Errors: INVALID_ARGUMENT as ifnso_orthogonalize, WORKSPACE_TOO_SMALL when
+ * the plan needs more than the area holds, HIP. */
+#define IFNSO_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+ifnso_status ifnso_orthogonalize_static(ifnso_plan_t plan, const void *M, int64_t ldm, void *Y, int64_t ldy,
+                                        void *stream);
+
 /* Orthogonalises every problem of the plan in one grouped schedule: one persistent
  * launch per stage (Gram, each squaring level, product) over the tiles of all
  * problems, replayed as a HIP graph. M, ldm, Y, ldy are host arrays of length

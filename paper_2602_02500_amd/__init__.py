@@ -20,7 +20,7 @@ __all__ = [
     "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
     "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes", "StageConfig",
     "quantize_e4m3", "quantize_e4m3_workspace_bytes", "STAGE_GRAM", "STAGE_SQUARE", "STAGE_PRODUCT",
-    "MuonParams",
+    "MuonParams", "STATIC_SCRATCH_BYTES",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ COEFF_FIXED, COEFF_LEARNED = 0, 1
 FLAG_ENFORCE_SUM_ONE = 1
 FLAG_SPLIT_BF16 = 2
 STATS_PER_PROBLEM = 26
+STATIC_SCRATCH_BYTES = 64 << 20  # IFNSO_STATIC_SCRATCH_BYTES
 MLP_NUM_PARAMS = 5126
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "WORKSPACE_TOO_SMALL", 4: "HIP", 5: "INTERNAL"}
 
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
     L.ifnso_plan_destroy.argtypes = [vp]
     L.ifnso_orthogonalize.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp]
     L.ifnso_orthogonalize_batched.argtypes = [vp, ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64, vp, sz, vp]
+    L.ifnso_orthogonalize_static.argtypes = [vp, vp, i64, vp, i64, vp]
+    L.ifnso_orthogonalize_static.restype = ctypes.c_int
     L.ifnso_muon_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     L.ifnso_muon_step.argtypes = [vp, ctypes.POINTER(MuonParams), ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64,
                                   ctypes.POINTER(vp), P64, vp, sz, vp]
@@ -274,6 +277,16 @@ class Plan:
         nb = check_workspace(workspace, self.workspace_bytes, self.device)
         _check(self._L.ifnso_orthogonalize(self._h, _ptr(M), int(M.stride(0)), _ptr(Y), int(Y.stride(0)),
                                            _ptr(workspace), nb, _stream(stream)))
+
+    def orthogonalize_static(self, M, Y, stream=None):
+        """ifnso_orthogonalize_static: the single problem with the library's fixed scratch area
+        (STATIC_SCRATCH_BYTES per GPU) instead of a workspace; allocates nothing. Calls that
+        overlap on one GPU race on that area."""
+        if len(self.shapes) != 1:
+            raise ValueError("orthogonalize_static takes a single-problem plan")
+        self.check_io([M], [Y])
+        _check(self._L.ifnso_orthogonalize_static(self._h, _ptr(M), int(M.stride(0)), _ptr(Y), int(Y.stride(0)),
+                                                  _stream(stream)))
 
     def orthogonalize_batched(self, Ms, Ys, workspace, stream=None):
         self.check_io(Ms, Ys)

@@ -20,7 +20,8 @@ ARCH = "gfx950"
 HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["ifnso_kernels.hip", "ifnso_fast.hip", "ifnso_fp8.hip", "ifnso_mlp.hip", "ifnso_muon.hip", "ifnso_host.cpp"]
+SOURCES = ["ifnso_kernels.hip", "ifnso_fast.hip", "ifnso_fp8.hip", "ifnso_mlp.hip", "ifnso_muon.hip", "ifnso_static.hip",
+           "ifnso_host.cpp"]
 
 
 def _hipcc() -> str:

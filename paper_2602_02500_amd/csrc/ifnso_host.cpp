@@ -1050,6 +1050,20 @@ extern "C" ifnso_status ifnso_orthogonalize(ifnso_plan_t p, const void *M, int64
   return run_batched(p, Ms, &ldm, Ys, &ldy, workspace, workspace_bytes, (hipStream_t)stream, true);
 }
 
+extern "C" ifnso_status ifnso_orthogonalize_static(ifnso_plan_t p, const void *M, int64_t ldm, void *Y, int64_t ldy,
+                                                   void *stream) {
+  if (!p) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (p->num != 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "plan has %d problems; use the batched call", p->num);
+  if (p->ws_bytes > kStaticScratchBytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "plan needs %zu bytes of workspace; the static scratch area holds %zu",
+                p->ws_bytes, kStaticScratchBytes);
+  void *ws = nullptr;
+  HIP_TRY(static_scratch(p->device, &ws));
+  const void *Ms[1] = {M};
+  void *Ys[1] = {Y};
+  return run_batched(p, Ms, &ldm, Ys, &ldy, ws, kStaticScratchBytes, (hipStream_t)stream, true);
+}
+
 extern "C" ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t p, const void *const *M, const int64_t *ldm,
                                                     void *const *Y, const int64_t *ldy, void *workspace,
                                                     size_t workspace_bytes, void *stream) {

@@ -54,6 +54,11 @@ hipError_t launch_learned(const StageArgs &a, int nprob, const float *params, co
 
 hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
 
+// The fixed scratch area of ifnso_orthogonalize_static (ifnso_static.hip): its device address
+// on `device`, resolved once per device (that device made current for the lookup).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+hipError_t static_scratch(int device, void **ptr);
+
 // Muon step around a batched orthogonalisation (ifnso_muon.hip)
 struct MuonProb {
   float *W;         // rows x cols float32, leading dimension ldw
