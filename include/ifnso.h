@@ -151,7 +151,11 @@ ifnso_status ifnso_orthogonalize_static(ifnso_plan_t plan, const void *M, int64_
 /* Orthogonalises every problem of the plan in one grouped schedule: one persistent
  * launch per stage (Gram, each squaring level, product) over the tiles of all
  * problems, replayed as a HIP graph. M, ldm, Y, ldy are host arrays of length
- * num_problems holding device pointers and leading dimensions. */
+ * num_problems holding device pointers and leading dimensions.
+ * The call's problem table (pointers, leading dimensions, workspace offsets) goes to one of
+ * four plan-owned device slots: a call whose table equals a slot's reuses that slot and its
+ * captured graph as they are; otherwise the least recently filled slot is refilled in stream
+ * order, after a device-side wait for the calls that last read it. The host never blocks. */
 ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M, const int64_t *ldm,
                                          void *const *Y, const int64_t *ldy, void *workspace,
                                          size_t workspace_bytes, void *stream);

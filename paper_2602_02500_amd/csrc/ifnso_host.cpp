@@ -307,19 +307,16 @@ struct ifnso_plan_s {
   int grid[3] = {1, 1, 1};
   int cus = 256;
   // per-call tables
+  // Each slot's device table and the host copy of what it holds; a call whose table equals a
+  // slot's reuses it (and that slot's captured graph) without an upload.
   ProbDev *d_table[kSlotsRing] = {};
-  ProbDev *h_table[kSlotsRing] = {};
+  std::vector<ProbDev> h_table[kSlotsRing];
   hipEvent_t ev[kSlotsRing] = {};
   bool ev_used[kSlotsRing] = {};
   int next_slot = 0;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2 * kSlotsRing] = {};  // per table slot, generic / fast I/O
   std::vector<hipEvent_t> stage_events;  // pending measurement request (one call)
-  // Muon steps: pinned staging of the problem table (allocated on first use) and the event of
-  // the last step that read it
-  MuonProb *h_muon = nullptr;
-  hipEvent_t ev_muon = nullptr;
-  bool ev_muon_used = false;
   std::mutex mu;
 };
 
@@ -592,7 +589,6 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   }
   for (int s = 0; s < kSlotsRing && e == hipSuccess; s++) {
     e = hipMalloc(&p->d_table[s], (size_t)num_problems * sizeof(ProbDev));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_table[s], (size_t)num_problems * sizeof(ProbDev), 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev[s], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -638,13 +634,7 @@ extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
       (void)hipEventDestroy(p->ev[s]);
     }
     if (p->d_table[s]) (void)hipFree(p->d_table[s]);
-    if (p->h_table[s]) (void)hipHostFree(p->h_table[s]);
   }
-  if (p->ev_muon) {
-    (void)hipEventSynchronize(p->ev_muon);
-    (void)hipEventDestroy(p->ev_muon);
-  }
-  if (p->h_muon) (void)hipHostFree(p->h_muon);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_coef) (void)hipFree(p->d_coef);
@@ -922,16 +912,28 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
     HIP_TRY(enqueue_plan(p, nullptr, &one, p->fast && fast_io_ok(p, one, p->lay[0]), s, evp));
     return IFNSO_OK;
   }
-  const int slot = p->next_slot;
-  p->next_slot = (slot + 1) % kSlotsRing;
-  if (p->ev_used[slot]) HIP_TRY(hipEventSynchronize(p->ev[slot]));  // table slot free again
-  ProbDev *ht = p->h_table[slot];
+  // The problem table of this call. A slot that already holds the same table is reused as it
+  // is (the usual case: the same buffers every step); otherwise the least recently filled slot
+  // takes it, after the calls that read that slot (a device-side wait on their event, so the
+  // host never blocks), uploaded in stream order.
+  std::vector<ProbDev> ht(p->num);
+  memset((void *)ht.data(), 0, (size_t)p->num * sizeof(ProbDev));  // padding compares equal
   for (int i = 0; i < p->num; i++)
     fill_dev(ht[i], p->lay[i], base + p->ws_off[i], M[i], ldm[i], Y[i], ldy[i], p->op,
              p->d_coef + (size_t)i * kSlots, p->d_stats + (size_t)i * kStatsPerProblem);
+  const size_t tbytes = (size_t)p->num * sizeof(ProbDev);
+  int slot = -1;
+  for (int k = 0; k < kSlotsRing && slot < 0; k++)
+    if (p->h_table[k].size() == ht.size() && memcmp(p->h_table[k].data(), ht.data(), tbytes) == 0) slot = k;
+  if (slot < 0) {
+    slot = p->next_slot;
+    p->next_slot = (slot + 1) % kSlotsRing;
+    if (p->ev_used[slot]) HIP_TRY(hipStreamWaitEvent(s, p->ev[slot], 0));
+    HIP_TRY(upload_table(p->d_table[slot], ht.data(), tbytes, s));
+    p->h_table[slot] = ht;
+  }
   bool fast_io = p->fast;
   for (int i = 0; i < p->num && fast_io; i++) fast_io = fast_io_ok(p, ht[i], p->lay[i]);
-  HIP_TRY(hipMemcpyAsync(p->d_table[slot], ht, (size_t)p->num * sizeof(ProbDev), hipMemcpyHostToDevice, s));
   const int gi = slot * 2 + (fast_io ? 1 : 0);
   if (use_graphs() && !evp) {
     if (!p->gexec[gi]) {
@@ -1152,18 +1154,14 @@ extern "C" ifnso_status ifnso_muon_step(ifnso_plan_t p, const ifnso_muon_params 
   MuonArgs a;
   int per = 1;
   {
-    std::lock_guard<std::mutex> lock(p->mu);  // the staging table is the plan's
     DeviceGuard dg(p->device);
     HIP_TRY(dg.e);
-    if (!p->h_muon) {
-      HIP_TRY(hipHostMalloc((void **)&p->h_muon, (size_t)p->num * sizeof(MuonProb), 0));
-      HIP_TRY(hipEventCreateWithFlags(&p->ev_muon, hipEventDisableTiming));
-    }
-    if (p->ev_muon_used) HIP_TRY(hipEventSynchronize(p->ev_muon));  // staging free again
     const double lr = hp->lr;
+    std::vector<MuonProb> mt(p->num);
+    memset((void *)mt.data(), 0, (size_t)p->num * sizeof(MuonProb));
     for (int i = 0; i < p->num; i++) {
       const ProbLayout &L = p->lay[i];
-      MuonProb &q = p->h_muon[i];
+      MuonProb &q = mt[i];
       q.W = W[i];
       q.G = G[i];
       q.B = B[i];
@@ -1182,10 +1180,9 @@ extern "C" ifnso_status ifnso_muon_step(ifnso_plan_t p, const ifnso_muon_params 
       U[i] = q.U;
       Y[i] = const_cast<void *>(q.Y);
     }
+    // the table lives in the caller's workspace: uploaded every step, in stream order
     MuonProb *d_table = (MuonProb *)(base + m.off_table);
-    HIP_TRY(hipMemcpyAsync(d_table, p->h_muon, (size_t)p->num * sizeof(MuonProb), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(p->ev_muon, s));
-    p->ev_muon_used = true;
+    HIP_TRY(upload_table(d_table, mt.data(), (size_t)p->num * sizeof(MuonProb), s));
     a.probs = d_table;
     a.momentum = hp->momentum;
     a.decay = (float)(1.0 - lr * hp->weight_decay);

@@ -58,6 +58,9 @@ hipError_t launch_orth_error(const OrthArgs &a, int bf16, hipStream_t s);
 // on `device`, resolved once per device (that device made current for the lookup).
 constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
 hipError_t static_scratch(int device, void **ptr);
+// bytes (a multiple of 4) from host memory to device memory `dst`, in stream order, through
+// kernel arguments: `src` may be reused as soon as the call returns
+hipError_t upload_table(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // Muon step around a batched orthogonalisation (ifnso_muon.hip)
 struct MuonProb {

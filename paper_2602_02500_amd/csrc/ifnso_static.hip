@@ -3,6 +3,7 @@
 // file-scope array per GPU, sized at build time, whose address each device resolves once.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <string.h>
 
 #include <mutex>
 
@@ -39,6 +40,38 @@ hipError_t static_scratch(int device, void **ptr) {
     g_ptr[device] = p;
   }
   *ptr = g_ptr[device];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Small host tables (problem tables of a call) copied to device memory in stream order through
+// kernel arguments: the runtime copies a launch's arguments when the launch is enqueued, so the
+// host buffer is free again on return and no pinned staging buffer (whose reuse would have to
+// wait for the copy) is needed.
+// ---------------------------------------------------------------------------------------------
+namespace {
+constexpr int kUploadWords = 768;  // 3 KiB of arguments per launch
+struct UploadChunk {
+  uint32_t w[kUploadWords];
+};
+
+__global__ __launch_bounds__(256) void k_upload(uint32_t *dst, const UploadChunk c, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = c.w[i];
+}
+}  // namespace
+
+hipError_t upload_table(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes % 4 || (uintptr_t)dst % 4) return hipErrorInvalidValue;
+  const uint32_t *w = (const uint32_t *)src;
+  const size_t n = bytes / 4;
+  UploadChunk c;
+  for (size_t o = 0; o < n; o += kUploadWords) {
+    const int m = (int)(n - o < (size_t)kUploadWords ? n - o : (size_t)kUploadWords);
+    memcpy(c.w, w + o, (size_t)m * 4);
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, (uint32_t *)dst + o, c, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -412,3 +412,38 @@ def test_schedule_configs_leave_results_bitwise(torch_dev):
     assert all(np.array_equal(a, b) for a, b in zip(out, ref))
     with pytest.raises(ifn.IfnsoError):
         plan.set_config(ifn.STAGE_GRAM, dict(xcd_sched=2, group=32, block_rows=4, block_cols=8, wg_per_xcd=32))
+
+
+def test_batched_tables_across_calls_and_streams(torch_dev):
+    """Seven batched calls with fresh output buffers (each a new problem table, so the plan's four
+    table slots wrap around), rotating over three streams with their own workspaces (so a slot is
+    refilled on another stream than the call that read it last), then a
+    call that repeats the first call's buffers (its slot is reused without an upload): every output
+    equals the first one bitwise. The slot refills wait on the device for the calls that read the
+    slot before, never on the host."""
+    torch, dev = torch_dev
+    import paper_2602_02500_amd as ifn
+    exps, c = configs.load_coeffs("gform_v1")
+    shapes = [(300, 600), (640, 320), (256, 512)]
+    plan = ifn.Plan(exps, c, shapes, compute="bf16")
+    Ms = [_to_dev(torch, dev, gen.gaussian_np(*s, seed=90 + i), "bf16")[0] for i, s in enumerate(shapes)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    wss = [torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev) for _ in streams]
+    torch.cuda.synchronize()
+    outs = []
+    for k in range(7):
+        st = streams[k % 3]
+        with torch.cuda.stream(st):
+            Ys = [torch.empty(s, dtype=torch.bfloat16, device=dev) for s in shapes]
+            plan.orthogonalize_batched(Ms, Ys, wss[k % 3])
+        outs.append(Ys)
+    with torch.cuda.stream(streams[0]):
+        plan.orthogonalize_batched(Ms, outs[0], wss[0])  # the first call's table again
+    torch.cuda.synchronize()
+    ref = [y.float().cpu() for y in outs[0]]
+    for k, Ys in enumerate(outs):
+        for i, y in enumerate(Ys):
+            assert torch.equal(y.float().cpu(), ref[i]), (k, i)
+    vals = [_to_dev(torch, dev, gen.gaussian_np(*s, seed=90 + i), "bf16")[1] for i, s in enumerate(shapes)]
+    for y, v in zip(ref, vals):
+        assert _rel(y.numpy().astype(np.float64), oracle.ifnso(v, exps, c)) <= TOL["bf16"]
