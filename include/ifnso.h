@@ -80,6 +80,20 @@ typedef enum { IFNSO_COEFF_FIXED = 0, IFNSO_COEFF_LEARNED = 1 } ifnso_coeff_mode
 
 enum {
   IFNSO_FLAG_ENFORCE_SUM_ONE = 1, /* reject coefficients with |sum c - 1| > 1e-12 */
+  /* Bitwise reproducibility. Always in force: every reduction (norms, traces, level scales,
+   * split-K partial tiles) is summed in a fixed order that does not depend on which workgroup
+   * runs which tile, so a plan gives the same bits on the same inputs call after call and under
+   * any schedule (ifnso_plan_set_config). The flag is accepted and changes nothing. */
+  IFNSO_FLAG_DETERMINISTIC = 2,
+  /* Gram basis with bf16 compute and at least one squaring: P = sum_{k>=1} c_k B^(e_k) is
+   * carried into the final product as a split pair P_hi + P_lo of bf16 values (P_hi = bf16(P),
+   * P_lo = bf16(P - P_hi)) and the product forms P_hi A + P_lo A (Algorithm 1's Y = Y' A with Y'
+   * held to about 16 significant bits instead of 8). Worth it when the coefficients are large
+   * with alternating signs, so that P is much larger than the result. Costs 2x the product work
+   * and one more hp x hp level slot of workspace. Needs fixed coefficients and problems that take
+   * the 256-tile kernels (as IFNSO_FLAG_SPLIT_BF16; otherwise a call returns
+   * IFNSO_ERR_UNSUPPORTED). */
+  IFNSO_FLAG_SPLIT_P = 4,
   /* Complement basis with bf16 compute: carry every squaring operand and P as a split pair
    * X = X_hi + X_lo of bf16 values (X_hi = bf16(X), X_lo = bf16(X - X_hi)), so a squaring forms
    * X_hi X_hi + X_hi X_lo + X_lo X_hi (three bf16 products, float32 accumulation) and the
@@ -89,7 +103,7 @@ enum {
    * squaring and 2x the product work. Needs fixed coefficients and problems that take the
    * 256-tile kernels (16-byte aligned rows, a multiple of 8 columns; otherwise a call returns
    * IFNSO_ERR_UNSUPPORTED). */
-  IFNSO_FLAG_SPLIT_BF16 = 2
+  IFNSO_FLAG_SPLIT_BF16 = 8
 };
 
 /* Polynomial descriptor. Arrays are read during ifnso_plan() only (copied). */

@@ -61,10 +61,11 @@ def _scale(A: np.ndarray, G: np.ndarray, norm: str) -> float:
 
 
 def gram_levels(M, exponents: Sequence[int], coeffs: Sequence[float], norm: str = "frobenius",
-                out_bf16: bool = True, store=bf16_round) -> np.ndarray:
+                out_bf16: bool = True, store=bf16_round, split_p: bool = False) -> np.ndarray:
     """Gram-basis polynomial Y = sum_k c_k (X X^T)^(e_k) X with the bf16 plans' storage points
-    (module docstring). M holds the input values as the device reads them. Returns Y in M's
-    orientation."""
+    (module docstring). M holds the input values as the device reads them. ``split_p``: P is
+    stored as a split pair hi + lo (IFNSO_FLAG_SPLIT_P) instead of one bf16 value. Returns Y in
+    M's orientation."""
     e, c = _check_terms(exponents, coeffs)
     r_out = store if out_bf16 else _identity
     A, trans = orient(M)
@@ -100,7 +101,9 @@ def gram_levels(M, exponents: Sequence[int], coeffs: Sequence[float], norm: str 
         l = ek.bit_length()
         lev = last if (l == J + 1 and J >= 1) else L[l]
         P = P + ck * lev / n ** (2 ** l)
-    P = store(P) if J >= 1 else P  # J = 0: the product reads the stored Gram (already rounded)
+    if J >= 1:
+        P = sum(split_pair(P, store)) if split_p else store(P)
+    # J = 0: the product reads the stored Gram (already rounded)
     Y = r_out((c0 * A + P @ A) / n)
     return Y.T if trans else Y
 

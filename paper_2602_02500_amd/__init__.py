@@ -16,7 +16,7 @@ __all__ = [
     "classical_ns_workspace_bytes", "ns_schedule",
     "orth_error", "F32", "BF16", "COMPUTE_F32", "COMPUTE_BF16", "COMPUTE_FP8", "BASIS_GRAM",
     "BASIS_COMPLEMENT", "NORM_FROBENIUS", "NORM_GRAM_FROBENIUS", "NORM_NONE", "FLAG_ENFORCE_SUM_ONE",
-    "FLAG_SPLIT_BF16",
+    "FLAG_SPLIT_BF16", "FLAG_DETERMINISTIC", "FLAG_SPLIT_P",
     "header_functions", "STATUS", "orth_error_workspace_bytes", "MLP_NUM_PARAMS", "STATS_PER_PROBLEM",
     "mlp_features", "mlp_forward", "mlp_train_step", "mlp_train_workspace_bytes", "StageConfig",
     "quantize_e4m3", "quantize_e4m3_workspace_bytes", "STAGE_GRAM", "STAGE_SQUARE", "STAGE_PRODUCT",
@@ -33,7 +33,9 @@ BASIS_GRAM, BASIS_COMPLEMENT = 0, 1
 NORM_FROBENIUS, NORM_GRAM_FROBENIUS, NORM_NONE = 0, 1, 2
 COEFF_FIXED, COEFF_LEARNED = 0, 1
 FLAG_ENFORCE_SUM_ONE = 1
-FLAG_SPLIT_BF16 = 2
+FLAG_DETERMINISTIC = 2
+FLAG_SPLIT_P = 4
+FLAG_SPLIT_BF16 = 8
 STATS_PER_PROBLEM = 26
 STATIC_SCRATCH_BYTES = 64 << 20  # IFNSO_STATIC_SCRATCH_BYTES
 MLP_NUM_PARAMS = 5126

@@ -90,6 +90,7 @@ struct StageArgs {
   int32_t split;       // complement basis, fast path: operands stored as split bf16 pairs
   int32_t fuse_agg;    // level layout: the last squaring forms P (no separate aggregate stage)
   int32_t p_slot;      // level layout: the level slot that holds P for the product
+  int32_t split_p;     // level layout: the last squaring stores P as a split pair (hp x 2hp, two slots)
   ProbDev one;         // the problem of a single-problem launch
 };
 

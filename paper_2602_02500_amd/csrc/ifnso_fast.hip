@@ -745,7 +745,7 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
 template <bool ROUND = false>
 __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char *smem, const float *wl,
                                               const ProbDev &P, int J, const Task &task, float c_last,
-                                              float f_store = 1.f) {
+                                              float f_store = 1.f, bool split_p = false) {
   float *ep = (float *)smem;
   const int m0 = task.tm * BM, n0 = task.tn * BN;
   const bool diag = task.tm == task.tn;
@@ -796,7 +796,8 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
       for (int u = 0; u < UR; u++) *(float4 *)(src + (it + u) * RS * EP_LD) = v[u];
     }
     __syncthreads();
-    emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
+    if (split_p) emit_operand<true>(ep, dst, hp, m0, n0, half, diag);  // [P_hi | P_lo], slots J and J + 1
+    else emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
     __syncthreads();
   }
 }
@@ -869,7 +870,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
     const bool last = a.last;
     double lv = 0.0, dg = 0.0, unused = 0.0;
     if constexpr (AGG) {
-      if constexpr (fuse) store_p_fused<false>(acc, smem, wl, P, level, task, c_acc);  // wl written before the mainloop
+      if constexpr (fuse) store_p_fused<false>(acc, smem, wl, P, level, task, c_acc, 1.f, a.split_p != 0);  // wl written before the mainloop
       else store_level<false>(acc, smem, P, level + 1, task, f_out);
       continue;
     } else {

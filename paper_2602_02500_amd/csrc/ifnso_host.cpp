@@ -96,7 +96,7 @@ static void gram_ksplit(int nt, int64_t w, int32_t &S, int32_t &kchunk) {
 // Workspace layout of one problem. levels = J + 2 partial slots; the complement basis adds the
 // float32 D ping-pong unless its operands are split; classical NS adds two h x w iterates.
 ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool complement, bool ns, bool agg = false,
-                          bool e4m3 = false, bool split = false, bool gsplit = false) {
+                          bool e4m3 = false, bool split = false, bool gsplit = false, bool split_p = false) {
   ProbLayout L{};
   L.rows = rows;
   L.cols = cols;
@@ -114,9 +114,9 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
   };
   if (agg) {
     // level layout: J + 1 full symmetric bf16 levels; the first one doubles as the Gram
-    // operand and, after the aggregate stage, as P
+    // operand and, after the aggregate stage, as P. A split P (hp x 2hp) takes slots J and J + 1.
     L.lv_stride = (int64_t)align_up(hh * op_size(op), kAlign);
-    L.off_lv = take((size_t)(J + 1) * L.lv_stride);
+    L.off_lv = take((size_t)(J + (split_p ? 2 : 1)) * L.lv_stride);
     L.off_opnd[0] = L.off_lv;
     L.off_opnd[1] = L.off_lv;
     L.off_accf = L.off_lv;  // never written in the level layout
@@ -288,6 +288,7 @@ struct ifnso_plan_s {
   bool learned = false;
   bool e4m3 = false;  // e4m3 Gram and squarings (level layout), bfloat16 aggregate and product
   bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
+  bool split_p = false;  // Gram basis: P carried into the product as a split bf16 pair
   bool fuse_agg = false;  // level layout with fixed coefficients: the last squaring forms P
   int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
@@ -413,8 +414,15 @@ static ifnso_status validate_desc(const ifnso_poly_desc *d) {
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad compute %d", d->compute);
   if (d->coeff_mode != IFNSO_COEFF_FIXED && d->coeff_mode != IFNSO_COEFF_LEARNED)
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad coeff_mode %d", d->coeff_mode);
-  if (d->flags & ~(uint32_t)(IFNSO_FLAG_ENFORCE_SUM_ONE | IFNSO_FLAG_SPLIT_BF16))
+  if (d->flags & ~(uint32_t)(IFNSO_FLAG_ENFORCE_SUM_ONE | IFNSO_FLAG_DETERMINISTIC | IFNSO_FLAG_SPLIT_P |
+                             IFNSO_FLAG_SPLIT_BF16))
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "unknown flags");
+  if ((d->flags & IFNSO_FLAG_SPLIT_P) &&
+      (d->compute != IFNSO_COMPUTE_BF16 || d->basis != IFNSO_BASIS_GRAM || d->coeff_mode != IFNSO_COEFF_FIXED))
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "IFNSO_FLAG_SPLIT_P needs bf16 compute, the Gram basis and fixed "
+                                            "coefficients");
+  if ((d->flags & IFNSO_FLAG_SPLIT_P) && d->exponents[d->num_terms - 1] < 2)
+    return fail(IFNSO_ERR_UNSUPPORTED, "IFNSO_FLAG_SPLIT_P needs at least one squaring (an exponent >= 2)");
   if ((d->flags & IFNSO_FLAG_SPLIT_BF16) &&
       (d->compute != IFNSO_COMPUTE_BF16 || d->basis != IFNSO_BASIS_COMPLEMENT || d->coeff_mode != IFNSO_COEFF_FIXED))
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "IFNSO_FLAG_SPLIT_BF16 needs bf16 compute, the complement basis and fixed "
@@ -529,6 +537,10 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (p->learned && !p->agg)
     return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "learned mode needs the bf16 fast path (IFNSO_FAST != 0)"));
   p->Jsq = p->learned ? p->J + 2 : p->J;
+  p->split_p = (desc->flags & IFNSO_FLAG_SPLIT_P) != 0;
+  if (p->split_p && !p->agg)
+    return cleanup_early(p, fail(IFNSO_ERR_UNSUPPORTED, "IFNSO_FLAG_SPLIT_P needs the bf16 fast path (IFNSO_FAST != 0, "
+                                                        "h below 32512)"));
   // the aggregation needs the coefficients before the last squaring: not in learned mode (the
   // network reads the last levels)
   p->fuse_agg = p->agg && !p->learned && p->J >= 1;
@@ -537,7 +549,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
     // a single problem that always runs on the generic kernels may split its Gram along K
     const bool gsplit = num_problems == 1 && !p->fast && !p->agg && !e4m3;
     p->lay.push_back(layout_problem(rows[i], cols[i], op, p->Jsq, p->basis == IFNSO_BASIS_COMPLEMENT, false,
-                                    p->agg, e4m3, p->split, gsplit));
+                                    p->agg, e4m3, p->split, gsplit, p->split_p));
     p->ws_off.push_back(off);
     off = align_up(off + p->lay.back().bytes, kAlign);
   }
@@ -662,6 +674,7 @@ static StageArgs base_args(const ifnso_plan_s *p) {
   a.split = p->split ? 1 : 0;
   a.fuse_agg = p->fuse_agg ? 1 : 0;
   a.p_slot = p->fuse_agg ? p->J : 0;  // P lands in level slot J + 1 (index J), else in level 1
+  a.split_p = p->split_p ? 1 : 0;
   return a;
 }
 
@@ -832,7 +845,10 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
         set_xcd(a, p->xq_prod[t][0], p->xq_prod[t][1], p->cfg[kStageProduct]);
       }
       apply_cfg(a, p->cfg[kStageProduct]);
+      const int sp = a.split;
+      a.split = p->split || p->split_p;  // a split P (either form) takes the split product
       e = launch_fast_stage(kStageProduct, t, a, fast_grid(a, cus), outbf, s);
+      a.split = sp;
       a.xcd_sched = 0;
     } else if (t == 0) {
       a.ntasks = one ? ntiles_prod(kTS) : p->n_prod;
@@ -881,7 +897,7 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
   for (int i = 0; i < p->num; i++) {
     ifnso_status st = check_matrix_args(p, i, M[i], ldm[i], Y[i], ldy[i]);
     if (st != IFNSO_OK) return st;
-    if (p->split) {  // only the 256-tile kernels know the split layout
+    if (p->split || p->split_p) {  // only the 256-tile kernels know the split layouts
       ProbDev t{};
       t.M = M[i];
       t.ldm = ldm[i];

@@ -67,7 +67,28 @@ def test_split_flag_requirements(L):
     assert b"SPLIT" in L.ifnso_last_error()
     assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=0, flags=split)[0] == 1  # float32 compute
     assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=2, flags=split)[0] == 1  # e4m3 compute
-    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=1, flags=8)[0] == 1      # unknown bit
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=1, flags=16)[0] == 1     # unknown bit
+
+
+def test_flag_values_and_split_p_requirements(L):
+    """The flag bits of the C ABI; split P is a Gram-basis, bf16-compute, fixed-coefficient
+    option that needs a squaring; the deterministic flag is accepted everywhere."""
+    import re
+    hdr = open(ifn.HEADER_PATH).read()
+    for name, val in (("ENFORCE_SUM_ONE", 1), ("DETERMINISTIC", 2), ("SPLIT_P", 4), ("SPLIT_BF16", 8)):
+        assert re.search(r"IFNSO_FLAG_%s = %d\b" % (name, val), hdr), name
+        assert getattr(ifn, "FLAG_" + name) == val
+    sp = ifn.FLAG_SPLIT_P
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=1, compute=1, flags=sp)[0] == 1      # complement basis
+    assert b"SPLIT_P" in L.ifnso_last_error()
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=0, compute=0, flags=sp)[0] == 1      # float32 compute
+    assert _plan(L, [0, 1, 2], [1, 1, 1], basis=0, compute=2, flags=sp)[0] == 1      # e4m3 compute
+    assert _plan(L, [0, 1], [1.5, -0.5], basis=0, compute=1, flags=sp)[0] == 2       # no squaring
+    for compute, basis in ((0, 0), (1, 0), (1, 1), (2, 0)):  # accepted: fails later only at the device
+        ind = ifn.F32 if compute == 0 else ifn.BF16
+        st, _ = _plan(L, [0, 1, 2], [0.5, 0.25, 0.25], basis=basis, compute=compute, flags=ifn.FLAG_DETERMINISTIC,
+                      ind=ind, outd=ind)
+        assert st in (0, 4), L.ifnso_last_error()
 
 
 def test_unsupported_combinations(L):
