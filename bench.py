@@ -139,10 +139,23 @@ def measured_traffic(kernel, summary, names=None):
             "source": os.path.relpath(summary, ROOT)}
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
-    """The FP64 oracle on a bounded sample (layer 0: its 7 matrices), on the host cores."""
+    """The FP64 oracle on a bounded sample (layer 0: its 7 matrices), on the host cores; then
+    layer 0's two 1024x4096 matrices again on one thread."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import oracle
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -153,9 +166,19 @@ def cpu_baseline(Ms_host, exps, coeffs, Ys_dev):
     for Yo, Yd in zip(outs, Ys_dev):
         rel.append(float(np.linalg.norm(Yd - Yo) / np.linalg.norm(Yo)))
     orth = [oracle.orth_error(Yo) / math.sqrt(min(Yo.shape)) for Yo in outs]
+    small = [M for M in Ms_host if min(M.shape) == 1024][:2]
+    with threadpool_limits(1):
+        t1 = time.perf_counter()
+        for M in small:
+            oracle.ifnso(M, exps, coeffs)
+        dt1 = time.perf_counter() - t1
     return {"value": len(Ms_host) / dt, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
             "sample": f"layer 0 of the set ({len(Ms_host)} matrices: 2x 4096x4096, 2x 1024x4096, "
-                      f"2x 14336x4096, 1x 4096x14336), float64 numpy, {dt:.1f} s"}, rel, orth
+                      f"2x 14336x4096, 1x 4096x14336), float64 numpy, {dt:.1f} s",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core": {"value": len(small) / dt1, "unit": "matrices/s", "threads": 1,
+                         "sample": f"layer 0's {len(small)} matrices of 1024x4096 on one thread, {dt1:.2f} s"}}, \
+        rel, orth
 
 
 def _oracle_threads():
@@ -178,6 +201,7 @@ def cpu_baseline_learned(theta, coeffs, held):
         lf.append(oracle.spectral_loss(coeffs, sgm)[0])
     dt = time.perf_counter() - t0
     cpu = {"value": len(held) / dt, "unit": "spectra/s", "cores": _oracle_threads(), "kind": "oracle",
+           "cpu_model": _cpu_model(),
            "sample": f"{len(held)} held-out spectra: features, network, polar distance of the learned and "
                      f"fixed polynomials, float64 numpy, {dt:.1f} s"}
     return cpu, {"learned": float(np.mean(ll)), "fixed": float(np.mean(lf)), "spectra": len(held)}
@@ -195,6 +219,7 @@ def cpu_baseline_tform(Mh, Yd, exps, coeffs):
     rel = [float(np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)) for Y, Yo in zip(Yd, outs)]
     orth = [float(oracle.orth_error(Yo) / np.sqrt(min(Yo.shape))) for Yo in outs]
     cpu = {"value": len(Mh) / dt, "unit": "matrices/s", "cores": _oracle_threads(), "kind": "oracle",
+           "cpu_model": _cpu_model(),
            "sample": f"layer 0's {len(Mh)} matrices of 1024x4096, complement basis, depth 14, float64 numpy, "
                      f"{dt:.1f} s"}
     return cpu, rel, orth
@@ -229,11 +254,14 @@ def roofline_of(kern):
                  "avg_launch_ms": round(dur_ms, 3)}
 
 
-def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
-    """Warm-up, graph-replay timing, then `steps` timed calls with a HIP event before every
-    launch slot (on the call's stream) and one after the last. Returns per-kernel
-    (ms per step, launches per step, algorithmic flops per step), the timed wall time and
-    the graph-replay ms per step."""
+def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log, slots=True):
+    """Warm-up calls, then the timed region: `steps` calls as a user makes them (the plan's
+    captured graph replayed), bracketed by torch.cuda.synchronize() and timed by the wall clock
+    and by HIP events around the whole region on the calls' stream. Then, unless `slots` is
+    false, a separate pass of `steps` calls with a HIP event before every launch slot and one
+    after the last (launched directly, not from the graph) for the per-kernel times. Returns
+    per-kernel (ms per step, launches per step, algorithmic flops per step), the timed wall
+    time, the event time of the timed region and the per-slot pass's ms per step."""
     import numpy as np
     nl = plan.num_launches
     info = [plan.launch_info(i) for i in range(nl)]
@@ -242,15 +270,21 @@ def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
     torch.cuda.synchronize()
     log("warmup done")
 
-    # graph replay (no events)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    tg0 = time.perf_counter()
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
         plan.orthogonalize_batched(Ms, Ys, ws)
+    e1.record()
     torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - tg0) / max(warmup, 1) * 1e3
+    elapsed = time.perf_counter() - t0
+    event_ms = e0.elapsed_time(e1)
+    log(f"timed {steps} steps: {elapsed:.3f} s")
+    if not slots:
+        return {"kern": {}, "elapsed": elapsed, "event_ms": event_ms, "slot_pass_ms": None, "slot_ms": None}
 
-    # the timed region: K steps, a HIP event before every launch slot and one after the last
+    # per-slot pass: a HIP event before every launch slot and one after the last
     evs = []
     for _ in range(steps):
         row = []
@@ -260,13 +294,12 @@ def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
             row.append(e.value)
         evs.append(row)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    t1 = time.perf_counter()
     for k in range(steps):
         plan.launch_events(evs[k])
         plan.orthogonalize_batched(Ms, Ys, ws)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {steps} steps: {elapsed:.3f} s")
+    slot_pass_ms = (time.perf_counter() - t1) / steps * 1e3
     slot_ms = np.zeros((steps, nl))
     f = ctypes.c_float()
     for k in range(steps):
@@ -282,7 +315,7 @@ def time_plan(torch, hip, plan, Ms, Ys, ws, names, steps, warmup, log):
         t, n_l, flop = kern.get(nm, (0.0, 0, 0.0))
         if info[i][1] > 0 or (info[i][0] in (3, 4) and per[i] > 0.001):  # memory-bound slots
             kern[nm] = (t + per[i], n_l + 1, flop + info[i][1])
-    return {"kern": kern, "elapsed": elapsed, "graph_ms": graph_ms, "slot_ms": per}
+    return {"kern": kern, "elapsed": elapsed, "event_ms": event_ms, "slot_pass_ms": slot_pass_ms, "slot_ms": per}
 
 
 def run_e4m3(args, torch, dev, hip, log):
@@ -320,7 +353,8 @@ def run_e4m3(args, torch, dev, hip, log):
     t_min_ms = ((fl["gram"] + J * fl["square"]) / (PEAK_FP8_TFLOPS * 1e12) + fl["product"] / (PEAK_BF16_TFLOPS * 1e12)) * 1e3
     hw = sum(r * c for r, c in shapes)
     prep_bytes = 5.0 * hw  # pre-pass reads M, quantisation reads M and writes e4m3 A
-    extra = {"graph_ms_per_step": round(t["graph_ms"], 3), "schedules": sched,
+    extra = {"event_ms_per_step": round(t["event_ms"] / args.steps, 3),
+             "slot_pass_ms_per_step": round(t["slot_pass_ms"], 3), "schedules": sched,
              "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
                              "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
                          for k, v in kern.items()},
@@ -565,19 +599,34 @@ def run_tform(args, torch, dev, hip, log):
 def run_muon(args, torch, dev, hip, log):
     """One Muon optimizer step per timed step on the gradient set: float32 weights and momentum,
     the bf16 gradients as G, Nesterov momentum 0.95, lr 0.02, weight decay 0.01, the fixed
-    Gram-basis coefficients as the orthogonalisation. Reports matrices/s of whole steps and the
-    time of the orthogonalisation alone on the same inputs."""
+    Gram-basis coefficients as the orthogonalisation (with --learned: the coefficient network,
+    trained first, picks each matrix's coefficients inside every step). Reports matrices/s of
+    whole steps and the time of the orthogonalisation alone on the same inputs."""
     import numpy as np
 
     import paper_2602_02500_amd as ifn
     from workloads import configs, gen
     exps, coeffs = configs.load_coeffs("gform_v1")
+    theta, training = None, None
+    if args.learned:  # the coefficient network in the loop: trained first, as the learned workload does
+        from paper_2602_02500_amd import learn
+        from workloads import spectra
+        samples = spectra.spectral_mixture(args.train_samples, seed=5)
+        sig, nsig = spectra.pad_spectra(samples)
+        params = torch.from_numpy(gen.fan_in_uniform_np(0, learn.PARAM_LAYOUT).astype(np.float32)).to(dev)
+        t0 = time.perf_counter()
+        learn.train(torch.from_numpy(sig).to(dev), torch.from_numpy(nsig).to(dev), params, epochs=args.epochs,
+                    batch=256, lr=2e-3)
+        torch.cuda.synchronize()
+        training = {"samples": len(samples), "epochs": args.epochs, "seconds": round(time.perf_counter() - t0, 3)}
+        theta = params.cpu().numpy()
+        log(f"trained the coefficient network in {training['seconds']} s")
     Gs = make_d3(torch, dev, args.layers)
     shapes = [tuple(g.shape) for g in Gs]
     n = len(Gs)
-    Ws = [gen.gaussian_torch(r, c, 5000 + i, 0, 0.02, device=dev) for i, (r, c) in enumerate(shapes)]
+    Ws = [gen.gaussian_torch(r, c, 5000 + i, 0, 0.02, device=dev).float() for i, (r, c) in enumerate(shapes)]
     Bs = [torch.zeros(s, dtype=torch.float32, device=dev) for s in shapes]
-    plan = ifn.Plan(exps, coeffs, shapes, compute="bf16")
+    plan = ifn.Plan(exps, coeffs, shapes, compute="bf16", mlp_params=theta)
     ws = torch.empty(plan.muon_workspace_bytes, dtype=torch.uint8, device=dev)
     log(f"muon workspace {plan.muon_workspace_bytes / 2**30:.1f} GiB")
     hp = dict(lr=0.02, momentum=0.95, weight_decay=0.01, nesterov=True)
@@ -602,14 +651,21 @@ def run_muon(args, torch, dev, hip, log):
     # elementwise bytes: momentum pass reads B, G and writes B, U; update pass reads W, Y, writes W
     ew_bytes = elems * (4 + 2 + 4 + 2 + 4 + 2 + 4)
     finite = all(bool(torch.isfinite(w).all()) for w in Ws)
+    network = None
+    if args.learned:
+        st = plan.stats()
+        network = {"used_fraction": float(np.mean([row[25] for row in st])), "training": training,
+                   "coeffs_mean": [round(float(v), 4) for v in np.mean([row[9:15] for row in st], axis=0)]}
     line = {
         "metric": "Muon optimizer steps on the 32-layer gradient set (momentum, IFNSO, weight update)",
         "value": round(n / dt, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"d3 gradient set, {args.layers} layers x 7 matrices as gradients; float32 weights "
-                               "N(0, 0.02^2) and momentum", "matrices": n, "coeffs": "gform_v1",
+                               "N(0, 0.02^2) and momentum", "matrices": n,
+                   "coeffs": "learned (fixed fallback gform_v1)" if args.learned else "gform_v1",
                    "optimizer": hp},
+        "coefficient_network": network,
         "roofline": None, "cpu_baseline": None,
         "orthogonalize_ms": round(dto * 1e3, 3),
         "elementwise_ms": round((dt - dto) * 1e3, 3),
@@ -634,7 +690,6 @@ def run_ns(args, torch, dev, hip, log):
     shapes = [tuple(m.shape) for m in Ms]
     n = len(Ms)
     Ys = [torch.empty_like(m) for m in Ms]
-    tmp = [torch.empty_like(m) for m in Ms]
     out = torch.empty(n, dtype=torch.float64, device=dev)
     ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)
     hs = np.sqrt([min(s) for s in shapes])
@@ -662,7 +717,7 @@ def run_ns(args, torch, dev, hip, log):
         sched, _ = configs.load_schedule(name)
         sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute="bf16")
         ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
-        res[name] = measure(lambda: sp.orthogonalize_batched(Ms, Ys, ws, tmp))
+        res[name] = measure(lambda: sp.orthogonalize_batched(Ms, Ys, ws))
         res[name]["steps"] = len(sched)
         res[name]["gelfand_q"] = q
         log(f"{name}: {res[name]['matrices_per_s']} matrices/s")
@@ -689,6 +744,125 @@ def run_ns(args, torch, dev, hip, log):
 
 
 TABLE1_SHAPES = ((128, 128), (128, 512), (128, 1024))
+
+
+def _call_ms(torch, call, reps, warmup=3):
+    """Median time per call (ms) from CUDA events around each call, after `warmup` calls."""
+    import numpy as np
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        call()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), float(np.percentile(ts, 10)), float(np.percentile(ts, 90))
+
+
+def run_d1(args, torch, dev, hip, log):
+    """The small parity configuration: one 256x512 float32 N(0,1) matrix (seed 0); Muon's five
+    Newton-Schulz steps and the Gram-basis polynomial with exponents {0,1,2,4,8} and the seeded
+    coefficients, each in float32 and bf16, one call at a time (latency-bound: a handful of
+    one-tile launches). Reports the median time per call and the distance to the float64
+    oracle; `value` is IFNSO's bf16 calls per second."""
+    import numpy as np
+
+    import oracle
+    import paper_2602_02500_amd as ifn
+    from workloads import configs, gen
+    rows, cols = 256, 512
+    M64 = gen.gaussian_np(rows, cols, seed=0)
+    exps, c = configs.D1_EXPONENTS, configs.d1_coeffs()
+    res = {}
+    for compute in ("f32", "bf16"):
+        vals = M64.astype(np.float32).astype(np.float64) if compute == "f32" else gen.round_to_bf16_np(M64)
+        dt = torch.float32 if compute == "f32" else torch.bfloat16
+        Mt = torch.from_numpy(vals.astype(np.float32)).to(dev).to(dt)
+        Y = torch.empty_like(Mt)
+        plan = ifn.Plan(exps, c, [(rows, cols)], compute=compute)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        med, p10, p90 = _call_ms(torch, lambda: plan.orthogonalize(Mt, Y, ws), args.steps * 10)
+        rel = float(np.linalg.norm(Y.double().cpu().numpy() - oracle.ifnso(vals, exps, c)) /
+                    np.linalg.norm(oracle.ifnso(vals, exps, c)))
+        res[f"ifnso_{compute}"] = {"ms_per_call": round(med, 4), "p10": round(p10, 4), "p90": round(p90, 4),
+                                   "rel_vs_oracle": rel}
+        wns = torch.empty(ifn.classical_ns_workspace_bytes(rows, cols, compute), dtype=torch.uint8, device=dev)
+        Yn = torch.empty_like(Mt)
+        med, p10, p90 = _call_ms(torch, lambda: ifn.classical_ns(Mt, Yn, 5, configs.MUON_ABC, compute, wns),
+                                 args.steps * 10)
+        Yo = oracle.classical_ns(vals, 5, configs.MUON_ABC)
+        rel = float(np.linalg.norm(Yn.double().cpu().numpy() - Yo) / np.linalg.norm(Yo))
+        res[f"ns5_{compute}"] = {"ms_per_call": round(med, 4), "p10": round(p10, 4), "p90": round(p90, 4),
+                                 "rel_vs_oracle": rel}
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            oracle.ifnso(M64, exps, c)
+        dt = time.perf_counter() - t0
+        cpu = {"value": reps / dt, "unit": "matrices/s", "cores": _oracle_threads(), "kind": "oracle",
+               "cpu_model": _cpu_model(), "sample": f"{reps} calls of the IFNSO oracle on the 256x512 matrix, "
+                                                   f"float64 numpy, {dt:.2f} s"}
+    line = {
+        "metric": "256x512 single-matrix latency: IFNSO vs Muon's 5-step Newton-Schulz, float32 and bf16",
+        "value": round(1e3 / res["ifnso_bf16"]["ms_per_call"], 2), "unit": "matrices/s", "n_gpus": 1,
+        "steps": args.steps * 10, "warmup": 3, "ms_per_step": res["ifnso_bf16"]["ms_per_call"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "256x512 N(0,1) seed 0; IFNSO exponents {0,1,2,4,8} with the seeded coefficients; "
+                               "NS: 5 steps (3.4445, -4.7750, 2.0315)", "matrices": 1},
+        "roofline": None, "cpu_baseline": cpu, "calls": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_d2(args, torch, dev, hip, log):
+    """The FP32-versus-BF16 pair: 4096x4096 (seed 1) and 14336x4096 (seed 2), U diag(sigma) V^T
+    with Haar factors and sigma log-uniform on [1e-3, 1], exponents {0..16} with the fixed
+    coefficients, through one batched plan per path. Reports matrices/s of each path, the
+    speed-up, and each path's distance to the exact result U diag(f(sigma~)) V^T."""
+    import numpy as np
+
+    import oracle
+    import paper_2602_02500_amd as ifn
+    from workloads import configs, gen
+    exps, c = configs.load_coeffs("gform_v1")
+    cases = [(4096, 4096, 1), (14336, 4096, 2)]
+    mats, closed = [], []
+    for rows, cols, seed in cases:
+        sigma = configs.d2_sigma_np(min(rows, cols), seed)
+        M, U, V = gen.spectral_torch(rows, cols, sigma, seed, device=dev)
+        closed.append(oracle.closed_form(U.cpu().numpy(), sigma, V.cpu().numpy(), exps, c))
+        mats.append(M)
+        del U, V
+    shapes = [tuple(m.shape) for m in mats]
+    res = {}
+    for compute, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        Ms = [m.to(dt).contiguous() for m in mats]
+        Ys = [torch.empty_like(m) for m in Ms]
+        plan = ifn.Plan(exps, c, shapes, compute=compute)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        t = time_plan(torch, hip, plan, Ms, Ys, ws, None, args.steps, args.warmup, log, slots=False)
+        ms = t["elapsed"] / args.steps * 1e3
+        rel = [float(np.linalg.norm(Y.double().cpu().numpy() - Yc) / np.linalg.norm(Yc)) for Y, Yc in zip(Ys, closed)]
+        res[compute] = {"matrices_per_s": round(2 / (ms * 1e-3), 2), "ms_per_step": round(ms, 3),
+                        "rel_vs_closed_form": rel}
+        del Ms, Ys, ws, plan
+    line = {
+        "metric": "FP32 vs BF16 path on the 4096x4096 and 14336x4096 pair: matrices/s and error vs the exact result",
+        "value": res["bf16"]["matrices_per_s"], "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["bf16"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "4096x4096 (seed 1) and 14336x4096 (seed 2), Haar factors, sigma log-uniform "
+                               "[1e-3, 1]; exponents {0,1,2,4,8,16}, gform_v1", "matrices": 2},
+        "roofline": None, "cpu_baseline": None, "paths": res,
+        "speedup_bf16_over_f32": round(res["bf16"]["matrices_per_s"] / res["f32"]["matrices_per_s"], 2),
+    }
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline_table1(methods, inputs):
@@ -804,17 +978,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the float64 orthogonality check")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain float32 comparison")
-    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon", "table1", "ns"],
+    ap.add_argument("--workload", choices=["gradset", "e4m3", "learned", "tform", "muon", "table1", "ns", "d1", "d2"],
                     default="gradset",
                     help="gradset: the 32-layer gradient set in bf16 (the headline); e4m3: 64 x 2048x8192 "
                          "heavy-tailed matrices with e4m3 Gram and squarings; learned: train the coefficient "
                          "network on the GPU, then run the gradient set with learned and fixed coefficients; "
                          "tform: the paper's complement-basis form (L = 14) on the gradient set; muon: whole "
-                         "Muon optimizer steps on the gradient set")
+                         "Muon optimizer steps on the gradient set (--learned: the coefficient network in the "
+                         "loop); table1: the paper's Table 1 methods on the device; ns: Newton-Schulz baselines "
+                         "on the gradient set; d1: 256x512 single-matrix latency; d2: FP32 vs BF16 on the "
+                         "4096x4096 / 14336x4096 pair")
     ap.add_argument("--train-samples", type=int, default=100000, help="learned workload: training spectra")
     ap.add_argument("--epochs", type=int, default=3, help="learned workload: training epochs")
     ap.add_argument("--batch", type=int, default=64, help="e4m3 workload: matrices in the batch")
     ap.add_argument("--unsplit", action="store_true", help="tform workload: single bf16 operands")
+    ap.add_argument("--learned", action="store_true", help="muon workload: the coefficient network in the loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain elementwise copy (out = x + 0, float32) that reads and writes BYTES, "
                          "as a known-size reference for hardware byte counters")
@@ -857,6 +1035,10 @@ def main():
         return run_table1(args, torch, dev, hip, log)
     if args.workload == "ns":
         return run_ns(args, torch, dev, hip, log)
+    if args.workload == "d1":
+        return run_d1(args, torch, dev, hip, log)
+    if args.workload == "d2":
+        return run_d2(args, torch, dev, hip, log)
 
     exps, coeffs = configs.load_coeffs("gform_v1")
     t0 = time.perf_counter()
@@ -878,7 +1060,7 @@ def main():
         ["aggregate", "product_wide", "product_tall"]
 
     t = time_plan(torch, hip, plan, Ms, Ys, ws, names, args.steps, args.warmup, log)
-    kern, elapsed, graph_ms = t["kern"], t["elapsed"], t["graph_ms"]
+    kern, elapsed = t["kern"], t["elapsed"]
     dom = max((k for k in kern if kern[k][2] > 0), key=lambda k: kern[k][0])
     dur_ms = kern[dom][0] / kern[dom][1]
     flop_per_launch = kern[dom][2] / kern[dom][1]
@@ -887,7 +1069,8 @@ def main():
     value = n * args.steps / elapsed
     step_tflops = fl["step"] / (ms_per_step * 1e-3) / 1e12
 
-    extra = {"graph_ms_per_step": round(graph_ms, 3), "schedules": sched,
+    extra = {"event_ms_per_step": round(t["event_ms"] / args.steps, 3),
+             "slot_pass_ms_per_step": round(t["slot_pass_ms"], 3), "schedules": sched,
              "kernels": {k: {"ms_per_step": round(v[0], 3), "launches": v[1],
                              "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 1) if v[0] > 0 and v[2] > 0 else None}
                          for k, v in kern.items()},
@@ -909,13 +1092,11 @@ def main():
         del ws
         plan32 = ifn.Plan(exps, coeffs, shapes, compute="f32")
         ws32 = torch.empty(plan32.workspace_bytes, dtype=torch.uint8, device=dev)
-        plan32.orthogonalize_batched(M32, Y32, ws32)
-        torch.cuda.synchronize()
-        t32 = time.perf_counter()
-        plan32.orthogonalize_batched(M32, Y32, ws32)
-        torch.cuda.synchronize()
-        t32 = time.perf_counter() - t32
-        extra["f32_path"] = {"matrices_per_s": n / t32, "speedup_bf16_over_f32": value / (n / t32)}
+        f32_steps = 5
+        t32 = time_plan(torch, hip, plan32, M32, Y32, ws32, None, f32_steps, 2, log, slots=False)["elapsed"]
+        t32 /= f32_steps
+        extra["f32_path"] = {"matrices_per_s": n / t32, "speedup_bf16_over_f32": value / (n / t32),
+                             "timed_steps": f32_steps, "warmup": 2}
         if not args.no_check:
             out = torch.empty(n, dtype=torch.float64, device=dev)
             ows = torch.empty(ifn.orth_error_workspace_bytes(n), dtype=torch.uint8, device=dev)

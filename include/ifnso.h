@@ -284,6 +284,39 @@ ifnso_status ifnso_ns_schedule(const void *M, int64_t rows, int64_t cols, int64_
                                int64_t ldy, int32_t steps, const double *abc, int32_t gelfand_q, int32_t compute,
                                void *workspace, size_t workspace_bytes, void *stream);
 
+/* Newton-Schulz step schedules over a batch, on the batched path: step k,
+ *   X_{k+1} = a_k X_k + b_k (X_k X_k^T) X_k + c_k (X_k X_k^T)^2 X_k   (Eq. (iteration_jordan)),
+ * is a Gram-basis plan with exponents {0, 1, 2} ({0, 1} when c_k = 0) and coefficients
+ * (a_k, b_k, c_k); the first step normalises by ||A||_F (gelfand_q = 0, Eq. (constraint)) or
+ * ||A A^T||_F^(1/2) (gelfand_q = 1, Gelfand's bound of Eq. (scale_formula_function) with q = 1),
+ * the others not at all. Steps with the same triple share one plan. The iterates between steps
+ * are stored in `dtype` (as the single-matrix schedule of ifnso_ns_schedule stores them),
+ * alternating between the workspace and Y so that the last step writes Y.
+ * abc: host array of `steps` triples (copied), 1 <= steps <= IFNSO_NS_MAX_STEPS; rows, cols:
+ * host arrays of num_problems shapes; dtype is the storage type of M, Y and the iterates
+ * (F32 with COMPUTE_F32, BF16 with COMPUTE_BF16). Errors: INVALID_ARGUMENT (NULL pointers,
+ * steps out of range, gelfand_q < 0, non-finite coefficients, bad shapes or dtype),
+ * UNSUPPORTED (gelfand_q > 1, and what ifnso_plan refuses), HIP. */
+typedef struct ifnso_schedule_plan_s *ifnso_schedule_plan_t;
+ifnso_status ifnso_schedule_plan(const double *abc, int32_t steps, int32_t gelfand_q, int32_t num_problems,
+                                 const int64_t *rows, const int64_t *cols, int32_t dtype, int32_t compute,
+                                 int32_t device, ifnso_schedule_plan_t *out_plan);
+
+/* Bytes of device workspace one call needs (256-byte aligned base): the largest step plan's
+ * workspace, then (with more than one step) one iterate buffer per problem. */
+ifnso_status ifnso_schedule_plan_workspace_bytes(ifnso_schedule_plan_t plan, size_t *bytes);
+
+/* Frees the schedule plan and its step plans; no enqueued call may still be running. NULL is
+ * accepted. */
+ifnso_status ifnso_schedule_plan_destroy(ifnso_schedule_plan_t plan);
+
+/* Runs the schedule on every problem: M, ldm, Y, ldy as for ifnso_orthogonalize_batched. Each
+ * step is one batched call of its plan (stream-ordered on `stream`; the host never blocks). M
+ * and Y must not overlap the workspace. Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, HIP. */
+ifnso_status ifnso_schedule_orthogonalize_batched(ifnso_schedule_plan_t plan, const void *const *M,
+                                                  const int64_t *ldm, void *const *Y, const int64_t *ldy,
+                                                  void *workspace, size_t workspace_bytes, void *stream);
+
 /* The input side of the FP8_E4M3 mode on its own: A (= M, or M^T when rows > cols; h x w,
  * h <= w) quantised to OCP e4m3 with the per-tensor power-of-two scale of ifnso_compute,
  * Q[i][k] = e4m3(s A[i][k]) for k < w and 0 for w <= k < round_up(w, 16): the K-major operand

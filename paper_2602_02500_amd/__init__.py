@@ -112,6 +112,16 @@ def load() -> ctypes.CDLL:
                                      vp, sz, vp]
     L.ifnso_ns_schedule.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, ctypes.POINTER(ctypes.c_double), i32, i32,
                                     vp, sz, vp]
+    L.ifnso_schedule_plan.argtypes = [ctypes.POINTER(ctypes.c_double), i32, i32, i32, P64, P64, i32, i32, i32,
+                                      ctypes.POINTER(vp)]
+    L.ifnso_schedule_plan.restype = ctypes.c_int
+    L.ifnso_schedule_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ifnso_schedule_plan_workspace_bytes.restype = ctypes.c_int
+    L.ifnso_schedule_plan_destroy.argtypes = [vp]
+    L.ifnso_schedule_plan_destroy.restype = ctypes.c_int
+    L.ifnso_schedule_orthogonalize_batched.argtypes = [vp, ctypes.POINTER(vp), P64, ctypes.POINTER(vp), P64, vp, sz,
+                                                       vp]
+    L.ifnso_schedule_orthogonalize_batched.restype = ctypes.c_int
     L.ifnso_classical_ns_workspace_bytes.argtypes = [i64, i64, i32]
     L.ifnso_classical_ns_workspace_bytes.restype = sz
     L.ifnso_orth_error.argtypes = [i32, ctypes.POINTER(vp), P64, P64, P64, i32, vp, vp, sz, vp]
@@ -367,42 +377,59 @@ class Plan:
 
 
 class SchedulePlan:
-    """Newton-Schulz step schedules over a batch, on the batched 256-tile path: step k,
-    X <- a_k X + b_k (XX^T) X + c_k (XX^T)^2 X, is a Gram-basis plan with exponents {0, 1, 2}
-    (or {0, 1} when c_k = 0) and coefficients (a_k, b_k, c_k); the first step's plan scales the
-    input by ||A||_F (gelfand_q = 0) or ||AA^T||_F^(1/2) (gelfand_q = 1), the others not at all.
-    The iterates are stored in the plans' input type between steps. Steps with the same
-    coefficients share a plan; all plans share one workspace (workspace_bytes)."""
+    """Newton-Schulz step schedules over a batch (ifnso_schedule_plan): step k,
+    X <- a_k X + b_k (XX^T) X + c_k (XX^T)^2 X, on the batched path; the first step scales the
+    input by ||A||_F (gelfand_q = 0) or ||AA^T||_F^(1/2) (gelfand_q = 1), the others not at
+    all. The iterates between steps live in the workspace (workspace_bytes)."""
 
     def __init__(self, schedule, shapes, gelfand_q: int = 0, compute="bf16", device: int = 0):
-        if gelfand_q not in (0, 1):
-            raise ValueError("batched schedules scale by ||A||_F (q = 0) or Gelfand's bound with q = 1")
+        L = load()
+        self._L = L
         self.schedule = [tuple(float(v) for v in abc) for abc in schedule]
-        if not self.schedule:
-            raise ValueError("empty schedule")
-        self._plans = {}
-        self._steps = []
-        for k, (a, b, c) in enumerate(self.schedule):
-            norm = ("frobenius" if gelfand_q == 0 else "gram_frobenius") if k == 0 else "none"
-            key = (a, b, c, norm)
-            if key not in self._plans:
-                exps, co = ((0, 1), (a, b)) if c == 0.0 else ((0, 1, 2), (a, b, c))
-                self._plans[key] = Plan(exps, co, shapes, basis="gram", norm=norm, compute=compute, device=device)
-            self._steps.append(self._plans[key])
-        self.shapes = self._steps[0].shapes
-        self.workspace_bytes = max(p.workspace_bytes for p in self._plans.values())
+        flat = [v for abc in self.schedule for v in abc]
+        if not self.schedule or len(flat) != 3 * len(self.schedule):
+            raise ValueError("schedule entries must be (a, b, c) triples")
+        self.shapes = [(int(r), int(c)) for r, c in shapes]
+        n = len(self.shapes)
+        comp = _COMPUTE[compute] if isinstance(compute, str) else int(compute)
+        self.dtype = F32 if comp == COMPUTE_F32 else BF16
+        self.device = int(device)
+        abc_c = (ctypes.c_double * len(flat))(*flat)
+        rows = (ctypes.c_int64 * n)(*[r for r, _ in self.shapes])
+        cols = (ctypes.c_int64 * n)(*[c for _, c in self.shapes])
+        h = ctypes.c_void_p()
+        _check(L.ifnso_schedule_plan(abc_c, len(self.schedule), int(gelfand_q), n, rows, cols, self.dtype, comp,
+                                     self.device, ctypes.byref(h)))
+        self._h = h
+        b = ctypes.c_size_t()
+        _check(L.ifnso_schedule_plan_workspace_bytes(h, ctypes.byref(b)))
+        self.workspace_bytes = b.value
 
-    def orthogonalize_batched(self, Ms, Ys, workspace, tmp=None, stream=None):
-        """Ys <- the schedule applied to Ms. With more than one step, `tmp` (tensors shaped like
-        Ms, distinct from Ms and Ys) holds every other iterate."""
-        n = len(self._steps)
-        if n > 1 and tmp is None:
-            raise ValueError("a schedule of several steps needs tmp buffers")
-        src = Ms
-        for k, plan in enumerate(self._steps):
-            dst = Ys if (n - 1 - k) % 2 == 0 else tmp
-            plan.orthogonalize_batched(src, dst, workspace, stream)
-            src = dst
+    def orthogonalize_batched(self, Ms, Ys, workspace, stream=None):
+        if len(Ms) != len(self.shapes) or len(Ys) != len(self.shapes):
+            raise ValueError(f"{len(Ms)} inputs and {len(Ys)} outputs for a schedule of {len(self.shapes)} problems")
+        for i, (m, y, s) in enumerate(zip(Ms, Ys, self.shapes)):
+            check_matrix(m, f"M[{i}]", s, self.dtype, self.device)
+            check_matrix(y, f"Y[{i}]", s, self.dtype, self.device)
+        nb = check_workspace(workspace, self.workspace_bytes, self.device)
+        n = len(Ms)
+        mp = (ctypes.c_void_p * n)(*[_ptr(m) for m in Ms])
+        yp = (ctypes.c_void_p * n)(*[_ptr(y) for y in Ys])
+        ldm = (ctypes.c_int64 * n)(*[int(m.stride(0)) for m in Ms])
+        ldy = (ctypes.c_int64 * n)(*[int(y.stride(0)) for y in Ys])
+        _check(self._L.ifnso_schedule_orthogonalize_batched(self._h, mp, ldm, yp, ldy, _ptr(workspace), nb,
+                                                            _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            self._L.ifnso_schedule_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def classical_ns_workspace_bytes(rows: int, cols: int, compute="bf16") -> int:

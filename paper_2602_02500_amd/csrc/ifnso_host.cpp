@@ -1493,3 +1493,139 @@ extern "C" ifnso_status ifnso_mlp_train_step(int32_t n, const float *feats, cons
 }
 
 extern "C" const char *ifnso_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------------------------
+// Newton-Schulz step schedules over a batch: one Gram-basis plan per distinct step, chained
+// ---------------------------------------------------------------------------------------------
+struct ifnso_schedule_plan_s {
+  std::vector<ifnso_plan_t> plans;  // one per distinct (a, b, c, normalisation)
+  std::vector<int> step_plan;       // plan index of each step
+  int num = 0;
+  int dtype = 0;
+  std::vector<int64_t> rows, cols, ld_iter;
+  std::vector<size_t> off_iter;     // per problem: the iterate buffer, after the plans' workspace
+  size_t ws_bytes = 0;
+};
+
+extern "C" ifnso_status ifnso_schedule_plan_destroy(ifnso_schedule_plan_t sp) {
+  if (!sp) return IFNSO_OK;
+  for (ifnso_plan_t p : sp->plans) ifnso_plan_destroy(p);
+  delete sp;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_schedule_plan(const double *abc, int32_t steps, int32_t gelfand_q, int32_t num_problems,
+                                            const int64_t *rows, const int64_t *cols, int32_t dtype, int32_t compute,
+                                            int32_t device, ifnso_schedule_plan_t *out) {
+  if (!abc || !rows || !cols || !out) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = nullptr;
+  if (steps < 1 || steps > kMaxNsSteps)
+    return fail(IFNSO_ERR_INVALID_ARGUMENT, "steps %d outside 1..%d", steps, kMaxNsSteps);
+  if (gelfand_q < 0) return fail(IFNSO_ERR_INVALID_ARGUMENT, "gelfand_q %d < 0", gelfand_q);
+  if (gelfand_q > 1)
+    return fail(IFNSO_ERR_UNSUPPORTED, "batched schedules scale by ||A||_F (q = 0) or ||AA^T||_F^(1/2) (q = 1)");
+  if (num_problems < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "num_problems %d < 1", num_problems);
+  for (int k = 0; k < 3 * steps; k++)
+    if (!std::isfinite(abc[k])) return fail(IFNSO_ERR_INVALID_ARGUMENT, "schedule entry %d is not finite", k);
+  if (dtype != IFNSO_F32 && dtype != IFNSO_BF16) return fail(IFNSO_ERR_INVALID_ARGUMENT, "bad dtype %d", dtype);
+  for (int i = 0; i < num_problems; i++)
+    if (rows[i] < 1 || cols[i] < 1) return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: dimensions must be >= 1", i);
+  ifnso_schedule_plan_s *sp = new (std::nothrow) ifnso_schedule_plan_s;
+  if (!sp) return fail(IFNSO_ERR_INTERNAL, "out of host memory");
+  sp->num = num_problems;
+  sp->dtype = dtype;
+  std::vector<double> keys;  // (a, b, c, norm) of each distinct plan
+  size_t ws_plan = 0;
+  for (int k = 0; k < steps; k++) {
+    const double a = abc[3 * k], b = abc[3 * k + 1], c = abc[3 * k + 2];
+    const int norm = k > 0 ? IFNSO_NORM_NONE : (gelfand_q == 0 ? IFNSO_NORM_FROBENIUS : IFNSO_NORM_GRAM_FROBENIUS);
+    int found = -1;
+    for (size_t q = 0; q < sp->plans.size() && found < 0; q++)
+      if (keys[4 * q] == a && keys[4 * q + 1] == b && keys[4 * q + 2] == c && keys[4 * q + 3] == norm) found = (int)q;
+    if (found < 0) {
+      // X_{k+1} = a X_k + b (X_k X_k^T) X_k + c (X_k X_k^T)^2 X_k: exponents {0, 1, 2}, or {0, 1} without c
+      const int32_t e3[3] = {0, 1, 2};
+      const double c3[3] = {a, b, c};
+      ifnso_poly_desc d;
+      std::memset(&d, 0, sizeof d);
+      d.num_terms = c == 0.0 ? 2 : 3;
+      d.exponents = e3;
+      d.coeffs = c3;
+      d.basis = IFNSO_BASIS_GRAM;
+      d.norm = norm;
+      d.compute = compute;
+      d.coeff_mode = IFNSO_COEFF_FIXED;
+      ifnso_plan_t p = nullptr;
+      const ifnso_status st = ifnso_plan(&d, num_problems, rows, cols, dtype, dtype, device, &p);
+      if (st != IFNSO_OK) {
+        ifnso_schedule_plan_destroy(sp);
+        return st;  // the message of ifnso_plan stands
+      }
+      sp->plans.push_back(p);
+      keys.insert(keys.end(), {a, b, c, (double)norm});
+      found = (int)sp->plans.size() - 1;
+      ws_plan = std::max(ws_plan, p->ws_bytes);
+    }
+    sp->step_plan.push_back(found);
+  }
+  // iterates between steps: one buffer per problem, rows 16-byte aligned for the 256-tile kernels
+  size_t o = align_up(ws_plan, kAlign);
+  const size_t es = dtype == IFNSO_F32 ? 4 : 2;
+  for (int i = 0; i < num_problems; i++) {
+    sp->rows.push_back(rows[i]);
+    sp->cols.push_back(cols[i]);
+    sp->ld_iter.push_back(round_up(cols[i], 8));
+    sp->off_iter.push_back(o);
+    o = align_up(o + (size_t)rows[i] * sp->ld_iter.back() * es, kAlign);
+  }
+  sp->ws_bytes = steps > 1 ? o : ws_plan;
+  *out = sp;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_schedule_plan_workspace_bytes(ifnso_schedule_plan_t sp, size_t *bytes) {
+  if (!sp || !bytes) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = sp->ws_bytes;
+  return IFNSO_OK;
+}
+
+extern "C" ifnso_status ifnso_schedule_orthogonalize_batched(ifnso_schedule_plan_t sp, const void *const *M,
+                                                             const int64_t *ldm, void *const *Y, const int64_t *ldy,
+                                                             void *workspace, size_t workspace_bytes, void *stream) {
+  if (!sp) return fail(IFNSO_ERR_INVALID_ARGUMENT, "schedule plan is NULL");
+  if (!M || !ldm || !Y || !ldy) return fail(IFNSO_ERR_INVALID_ARGUMENT, "NULL pointer array");
+  if (!workspace) return fail(IFNSO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < sp->ws_bytes)
+    return fail(IFNSO_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, the schedule needs %zu", workspace_bytes,
+                sp->ws_bytes);
+  const size_t es = sp->dtype == IFNSO_F32 ? 4 : 2;
+  for (int i = 0; i < sp->num; i++) {
+    ifnso_status st = check_matrix_args(sp->plans[0], i, M[i], ldm[i], Y[i], ldy[i]);
+    if (st != IFNSO_OK) return st;
+    const void *t = (const char *)workspace + sp->off_iter[i];
+    if (sp->step_plan.size() > 1 &&
+        (ranges_overlap(t, matrix_bytes(sp->rows[i], sp->ld_iter[i], sp->cols[i], es), M[i],
+                        matrix_bytes(sp->rows[i], ldm[i], sp->cols[i], es)) ||
+         ranges_overlap(t, matrix_bytes(sp->rows[i], sp->ld_iter[i], sp->cols[i], es), Y[i],
+                        matrix_bytes(sp->rows[i], ldy[i], sp->cols[i], es))))
+      return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: M or Y overlaps the workspace", i);
+  }
+  // the last step writes Y; earlier ones alternate between the iterate buffers and Y
+  const int n = (int)sp->step_plan.size();
+  std::vector<const void *> src(M, M + sp->num);
+  std::vector<int64_t> lsrc(ldm, ldm + sp->num);
+  std::vector<void *> tbuf(sp->num);
+  for (int i = 0; i < sp->num; i++) tbuf[i] = (char *)workspace + sp->off_iter[i];
+  for (int k = 0; k < n; k++) {
+    const bool to_y = (n - 1 - k) % 2 == 0;
+    std::vector<void *> dst = to_y ? std::vector<void *>(Y, Y + sp->num) : tbuf;
+    const int64_t *ld = to_y ? ldy : sp->ld_iter.data();
+    ifnso_plan_t p = sp->plans[sp->step_plan[k]];
+    const ifnso_status st =
+        ifnso_orthogonalize_batched(p, src.data(), lsrc.data(), dst.data(), ld, workspace, workspace_bytes, stream);
+    if (st != IFNSO_OK) return st;
+    for (int i = 0; i < sp->num; i++) src[i] = dst[i];
+    lsrc.assign(ld, ld + sp->num);
+  }
+  return IFNSO_OK;
+}

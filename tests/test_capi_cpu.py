@@ -270,3 +270,25 @@ def test_binding_rejects_bad_workspaces():
     with pytest.raises(ValueError) as e:
         ifn.check_workspace(torch.empty(64, dtype=torch.uint8), 64, 0)
     assert "cuda:0" in str(e.value)
+
+
+def test_schedule_plan_argument_checks(L):
+    """ifnso_schedule_plan refuses bad arguments before touching the device."""
+    def mk(abc, steps, q=0, rows=(64,), cols=(96,), dtype=1, compute=1):
+        a = (ctypes.c_double * max(len(abc), 1))(*abc)
+        n = len(rows)
+        r = (ctypes.c_int64 * n)(*rows)
+        c = (ctypes.c_int64 * n)(*cols)
+        h = ctypes.c_void_p()
+        return L.ifnso_schedule_plan(a, steps, q, n, r, c, dtype, compute, 0, ctypes.byref(h))
+    muon = [3.4445, -4.775, 2.0315]
+    assert mk(muon, 0) == 1                      # no steps
+    assert mk(muon * 17, 17) == 1                # beyond IFNSO_NS_MAX_STEPS
+    assert mk(muon, 1, q=-1) == 1
+    assert mk(muon, 1, q=2) == 2                 # Gelfand q = 2 is single-matrix only
+    assert mk([1.0, float("inf"), 0.0], 1) == 1
+    assert mk(muon, 1, dtype=7) == 1
+    assert mk(muon, 1, rows=(0,)) == 1
+    assert L.ifnso_schedule_plan(None, 1, 0, 1, None, None, 1, 1, 0, None) == 1
+    assert L.ifnso_schedule_orthogonalize_batched(None, None, None, None, None, None, 0, None) == 1
+    assert L.ifnso_schedule_plan_destroy(None) == 0

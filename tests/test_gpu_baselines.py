@@ -168,8 +168,7 @@ def test_schedule_plan_batched_matches_oracle(tdev, name, q):
     sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute="bf16")
     ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
     Ys = [torch.full_like(m, float("nan")) for m in Ms]
-    tmp = [torch.empty_like(m) for m in Ms]
-    sp.orthogonalize_batched(Ms, Ys, ws, tmp)
+    sp.orthogonalize_batched(Ms, Ys, ws)
     torch.cuda.synchronize()
     for Y, v, s in zip(Ys, vals, shapes):
         Yo = BL.ns_schedule(v, sched, q)
@@ -244,3 +243,29 @@ def test_workspace_contents_on_entry_do_not_matter(tdev):
         torch.cuda.synchronize()
         out.append(Y.float().cpu().numpy())
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_schedule_entry_equals_chained_plans(tdev):
+    """ifnso_schedule_orthogonalize_batched runs exactly the chain of Gram-basis plans that its
+    definition names (first step normalised, iterates stored in bf16 between steps): the same
+    bits as chaining the plans by hand through Y and a second buffer."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    sched, _ = configs.load_schedule("cesista_ns5")
+    shapes = [(256, 512), (512, 256), (200, 456)]
+    Ms = [_dev(torch, dev, gen.gaussian_np(*s, seed=50 + i), "bf16")[0] for i, s in enumerate(shapes)]
+    sp = ifn.SchedulePlan(sched, shapes, gelfand_q=0, compute="bf16")
+    ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.full_like(m, float("nan")) for m in Ms]
+    sp.orthogonalize_batched(Ms, Ys, ws)
+    src = Ms
+    bufs = [[torch.empty_like(m) for m in Ms], [torch.empty_like(m) for m in Ms]]
+    for k, (a, b, c) in enumerate(sched):
+        plan = ifn.Plan((0, 1, 2), (a, b, c), shapes, norm="frobenius" if k == 0 else "none", compute="bf16")
+        w = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        dst = bufs[k % 2]
+        plan.orthogonalize_batched(src, dst, w)
+        src = dst
+    torch.cuda.synchronize()
+    for y, r in zip(Ys, src):
+        assert torch.equal(y, r)

@@ -89,15 +89,14 @@ def test_d2_pair_schedule_against_closed_form(tdev):
         sp = ifn.SchedulePlan(sched, shapes, gelfand_q=q, compute=compute)
         Ms = [m.to(dt).contiguous() for m in mats]
         Ys = [torch.empty_like(m) for m in Ms]
-        tmp = [torch.empty_like(m) for m in Ms]
         ws = torch.empty(sp.workspace_bytes, dtype=torch.uint8, device=dev)
-        sp.orthogonalize_batched(Ms, Ys, ws, tmp)
+        sp.orthogonalize_batched(Ms, Ys, ws)
         torch.cuda.synchronize()
         for (rows, cols, _), Y, Yc in zip(cases, Ys, closed):
             r = _rel(Y.double().cpu().numpy(), Yc)
             print(f"  {compute} {rows}x{cols}: rel vs closed form {r:.3e}")
             assert r <= tol, (compute, rows, cols, r)
-        del ws, Ys, Ms, tmp, sp
+        del ws, Ys, Ms, sp
 
 
 # heavy-tailed batch (the e4m3 workload's matrices) through the bf16 path

@@ -129,3 +129,34 @@ def test_argument_checks(tdev):
         plan.muon_step(Ws, Gs, Bs, ws, float("nan"), 0.9)
     with pytest.raises(ifn.IfnsoError):
         plan.muon_step(Ws, Gs, Ws, ws, 0.1, 0.9)  # momentum buffer aliases the weights
+
+
+def test_learned_plan_in_the_loop(tdev):
+    """A Muon step with a learned plan: the coefficient network picks each matrix's polynomial
+    inside the step (from the traces of the Gram powers of its own U). The oracle's step with the
+    coefficients the device used (plan.stats()) gives the same update: momentum to float32
+    rounding, the weight change within the bf16 bound; the network was used for every matrix."""
+    torch, dev = tdev
+    import oracle
+    import paper_2602_02500_amd as ifn
+    exps, fixed = configs.load_coeffs("gform_v1")
+    theta = oracle.mlp_init(11).astype(np.float32)
+    shapes = [(256, 512), (512, 256), (384, 640)]
+    Ws, Gs, Bs, host = _setup(torch, dev, shapes, seed=120)
+    lr, mu, wd = 0.02, 0.95, 0.01
+    plan = ifn.Plan(exps, fixed, shapes, compute="bf16", mlp_params=theta)
+    ws = torch.empty(plan.muon_workspace_bytes, dtype=torch.uint8, device=dev)
+    plan.muon_step(Ws, Gs, Bs, ws, lr, mu, wd, True)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    for i, (W0, G, B0) in enumerate(host):
+        assert st[i][25] == 1.0
+        c_dev = np.array(st[i][9:15])
+        assert not np.allclose(c_dev, fixed)
+        W1o, B1o, _ = MU.muon_step(W0, G, B0, exps, c_dev, lr, mu, wd, True, round_input=F.bf16_round)
+        W1 = Ws[i].cpu().numpy().astype(np.float64)
+        B1 = Bs[i].cpu().numpy().astype(np.float64)
+        rb, rw = _rel(B1, B1o), _rel(W1 - W0, W1o - W0)
+        print(f"{shapes[i]} learned: momentum rel {rb:.1e}, weight change rel {rw:.2e}, c = {np.round(c_dev, 3)}")
+        assert rb <= 1e-6
+        assert rw <= 2e-2
