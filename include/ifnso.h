@@ -332,8 +332,9 @@ size_t ifnso_quantize_e4m3_workspace_bytes(int64_t rows, int64_t cols);
 /* Orthogonality error of the Experiment section, e = ||Z Z^T - I||_F with Z = Y in the
  * h <= w orientation, computed on the device in float64 for `count` matrices (host arrays
  * of device pointers, shapes and leading dimensions; one dtype for all). Writes `count`
- * doubles to the device array `out`. The device workspace must hold
- * ifnso_orth_error_workspace_bytes(count) bytes (256-byte aligned). Evaluation helper,
+ * doubles to the device array `out`. Z Z^T is formed on the float64 matrix cores
+ * (v_mfma_f64_16x16x4f64, upper 64 x 64 tiles, float64 accumulation throughout). The device
+ * workspace must hold ifnso_orth_error_workspace_bytes(count) bytes (256-byte aligned). Evaluation helper,
  * not part of the timed path: it synchronises `stream` before returning.
  * Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, HIP. */
 ifnso_status ifnso_orth_error(int32_t count, const void *const *Y, const int64_t *rows, const int64_t *cols,

@@ -1410,7 +1410,7 @@ extern "C" ifnso_status ifnso_quantize_e4m3(const void *M, int64_t rows, int64_t
 // ---------------------------------------------------------------------------------------------
 // evaluation helpers
 // ---------------------------------------------------------------------------------------------
-static constexpr int kOrthSplit = 32;
+static constexpr int kOrthSplit = 64;
 
 extern "C" size_t ifnso_orth_error_workspace_bytes(int32_t count) {
   if (count < 1) return 0;

@@ -532,18 +532,27 @@ __global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const i
 // ---------------------------------------------------------------------------------------------
 // float64 orthogonality error ||Z Z^T - I||_F (evaluation only)
 // ---------------------------------------------------------------------------------------------
+// Matrix-core form: a workgroup of 4 waves owns a 64 x 64 tile of Z Z^T (upper tiles only, the
+// off-diagonal ones counted twice); each wave a 32 x 32 quarter as 2 x 2 tiles of
+// v_mfma_f64_16x16x4_f64. Z is staged through LDS as float64, 32 K per stage. Lane layout of the
+// f64 16x16x4 instruction (measured with an in-bounds probe): A[i][k] = lane (i + 16 k), B[k][j] =
+// lane (j + 16 k), and D[i][j] in lane j + 16 (i % 4), element i / 4.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <typename TY>
 __global__ __launch_bounds__(256) void k_orth_error(const OrthArgs a) {
-  constexpr int T64 = 64, KS = 16;
-  __shared__ double Zi[KS][T64 + 1];
-  __shared__ double Zj[KS][T64 + 1];
+  constexpr int T64 = 64, KS = 32, LDZ = KS + 1;
+  __shared__ double Zi[T64][LDZ];
+  __shared__ double Zj[T64][LDZ];
   __shared__ double red[4];
   const int p = blockIdx.x / a.nsplit, split = blockIdx.x % a.nsplit;
   const OrthEntry E = a.e[p];
   const TY *Y = (const TY *)E.ptr;
   const bool trans = E.rows > E.cols;
   const int64_t h = trans ? E.cols : E.rows, w = trans ? E.rows : E.cols, ld = E.ld;
-  const int tr = threadIdx.x >> 4, tcol = threadIdx.x & 15;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, lk = lane >> 4;
   const int nt = (int)((h + T64 - 1) / T64);
   double total = 0.0;
   auto zel = [&](int64_t i, int64_t k) -> double {
@@ -552,42 +561,57 @@ __global__ __launch_bounds__(256) void k_orth_error(const OrthArgs a) {
     if constexpr (sizeof(TY) == 2) return (double)bf16_to_f32(((const uint16_t *)Y)[idx]);
     else return (double)((const float *)Y)[idx];
   };
-  for (int ti = split; ti < nt; ti += a.nsplit) {
-    for (int tj = ti; tj < nt; tj++) {
-      double acc[4][4] = {};
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int t = split; t < ntiles; t += a.nsplit) {  // upper tiles dealt round-robin
+    int ti = 0, rem = t;
+    while (rem >= nt - ti) {
+      rem -= nt - ti;
+      ti++;
+    }
+    const int tj = ti + rem;
+    {
+      f64x4 acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int v = 0; v < 2; v++) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
       for (int64_t k0 = 0; k0 < w; k0 += KS) {
+        // stage: element (r, kk) of both row blocks; consecutive threads along the contiguous
+        // index of Y (k for wide Z, the row index for tall Z)
         for (int e = threadIdx.x; e < KS * T64; e += 256) {
           const int r = trans ? (e % T64) : (e / KS), kk = trans ? (e / T64) : (e % KS);
-          Zi[kk][r] = zel((int64_t)ti * T64 + r, k0 + kk);
-          Zj[kk][r] = zel((int64_t)tj * T64 + r, k0 + kk);
+          Zi[r][kk] = zel((int64_t)ti * T64 + r, k0 + kk);
+          Zj[r][kk] = zel((int64_t)tj * T64 + r, k0 + kk);
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < KS; kk++) {
-          double av[4], bv[4];
+        for (int k = 0; k < KS; k += 4) {
+          double fa[2], fb[2];
 #pragma unroll
-          for (int u = 0; u < 4; u++) {
-            av[u] = Zi[kk][tr * 4 + u];
-            bv[u] = Zj[kk][tcol * 4 + u];
-          }
+          for (int u = 0; u < 2; u++) fa[u] = Zi[wr + 16 * u + l16][k + lk];
 #pragma unroll
-          for (int u = 0; u < 4; u++)
+          for (int v = 0; v < 2; v++) fb[v] = Zj[wc + 16 * v + l16][k + lk];
 #pragma unroll
-            for (int v = 0; v < 4; v++) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+          for (int u = 0; u < 2; u++)
+#pragma unroll
+            for (int v = 0; v < 2; v++) acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], acc[u][v], 0, 0, 0);
         }
         __syncthreads();
       }
       const double wgt = (ti == tj) ? 1.0 : 2.0;
 #pragma unroll
-      for (int u = 0; u < 4; u++)
+      for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-          const int64_t gi = (int64_t)ti * T64 + tr * 4 + u, gj = (int64_t)tj * T64 + tcol * 4 + v;
-          if (gi < h && gj < h) {
-            const double e = acc[u][v] - (gi == gj ? 1.0 : 0.0);
-            total = fma(wgt * e, e, total);
+        for (int v = 0; v < 2; v++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int64_t gi = (int64_t)ti * T64 + wr + 16 * u + lk + 4 * r;
+            const int64_t gj = (int64_t)tj * T64 + wc + 16 * v + l16;
+            if (gi < h && gj < h) {
+              const double e = acc[u][v][r] - (gi == gj ? 1.0 : 0.0);
+              total = fma(wgt * e, e, total);
+            }
           }
-        }
     }
   }
 #pragma unroll

@@ -288,6 +288,16 @@ def test_orth_error_float64(torch_dev):
     for g, m in zip(got, mats):
         ref = oracle.orth_error(m.astype(np.float32).astype(np.float64))
         assert abs(g - ref) <= 1e-10 * max(1.0, ref)
+    # bf16 storage, several 64-row tiles with ragged edges in both orientations
+    mats = [gen.haar_np(700, 260, 4, 1).T.copy(), gen.haar_np(777, 333, 5, 1), gen.gaussian_np(130, 1000, seed=6) * 0.03]
+    vals = [gen.round_to_bf16_np(m) for m in mats]
+    ts = [torch.from_numpy(v.astype(np.float32)).to(dev).to(torch.bfloat16) for v in vals]
+    out = torch.empty(len(ts), dtype=torch.float64, device=dev)
+    ws = torch.empty(ifn.orth_error_workspace_bytes(len(ts)), dtype=torch.uint8, device=dev)
+    ifn.orth_error(ts, out, ws)
+    for g, v in zip(out.cpu().numpy(), vals):
+        ref = oracle.orth_error(v)
+        assert abs(g - ref) <= 1e-10 * max(1.0, ref), (v.shape, g, ref)
 
 
 # shapes whose rows are 16-byte aligned (cols % 8 == 0): the bfloat16 plans route the Gram and
