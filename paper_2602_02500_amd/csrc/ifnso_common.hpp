@@ -91,6 +91,10 @@ struct StageArgs {
   int32_t fuse_agg;    // level layout: the last squaring forms P (no separate aggregate stage)
   int32_t p_slot;      // level layout: the level slot that holds P for the product
   int32_t split_p;     // level layout: the last squaring stores P as a split pair (hp x 2hp, two slots)
+  // With XCD queues: 8 counters (one per queue, zero at launch) from which workgroups take
+  // their next task; a workgroup whose queue is empty takes from the others. nullptr: static
+  // striding through the workgroup's queue.
+  uint32_t *qctr;
   ProbDev one;         // the problem of a single-problem launch
 };
 

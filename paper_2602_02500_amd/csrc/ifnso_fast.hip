@@ -480,6 +480,46 @@ __device__ __forceinline__ TaskRange task_range(const StageArgs &a) {
   return TaskRange{0, (int)blockIdx.x, (int)gridDim.x, a.ntasks};
 }
 
+// The tasks a workgroup runs: with per-XCD queues and task counters (a.qctr), the next entry of
+// its own XCD's queue, taken with an atomic increment of that queue's counter, and once that
+// queue is empty the entries left in the other queues (in XCD order), so that no workgroup idles
+// while another queue still holds work; otherwise static striding through its queue (or through
+// the whole list). Which workgroup runs a tile does not change any result: every reduction is
+// summed in a fixed order.
+struct TaskCursor {
+  TaskRange tr;
+  int t, tried;
+  int *slot;  // LDS word that broadcasts a taken task to the workgroup
+  __device__ TaskCursor(const StageArgs &a, int *s) : tr(task_range(a)), t(tr.start), tried(0), slot(s) {}
+  // g: index into the task list (or into the single problem's tiles); false when none is left
+  __device__ bool next(const StageArgs &a, int &g) {
+    if (!(a.qctr && a.tasks && a.xcd_sched)) {
+      if (t >= tr.end) return false;
+      g = tr.base + t;
+      t += tr.stride;
+      return true;
+    }
+    if (threadIdx.x == 0) {
+      int v = -1;
+      const int x0 = blockIdx.x & 7;
+      while (tried < 8) {
+        const int x = (x0 + tried) & 7;
+        const uint32_t i = atomicAdd(a.qctr + x, 1u);
+        if (i < (uint32_t)a.xcd_cnt[x]) {
+          v = a.xcd_off[x] + (int)i;
+          break;
+        }
+        tried++;
+      }
+      *slot = v;
+    }
+    __syncthreads();
+    g = uni(*slot);
+    __syncthreads();
+    return g >= 0;
+  }
+};
+
 __device__ __forceinline__ const ProbDev &prob(const StageArgs &a, const Task &t) {
   return a.tasks ? a.probs[t.p] : a.one;
 }
@@ -678,9 +718,11 @@ template <bool TALL, bool SPLIT>
 __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
   float *ep = (float *)smem;
-  const TaskRange tr = task_range(a);
-  for (int t = tr.start; t < tr.end; t += tr.stride) {
-    Task task = fetch(a, tr.base + t, kStageGram);
+  __shared__ int s_task;
+  TaskCursor cursor(a, &s_task);
+  int tg = 0;
+  while (cursor.next(a, tg)) {
+    Task task = fetch(a, tg, kStageGram);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -822,9 +864,11 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
   constexpr bool fuse = FUSE;
   int cur_p = -1;
   float f_out = 1.f, c_acc = 0.f, c_first = 0.f, alpha = 1.f, c_next = 0.f, dscale = 1.f;
-  const TaskRange tr = task_range(a);
-  for (int t = tr.start; t < tr.end; t += tr.stride) {
-    Task task = fetch(a, tr.base + t, kStageSquare);
+  __shared__ int s_task;
+  TaskCursor cursor(a, &s_task);
+  int tg = 0;
+  while (cursor.next(a, tg)) {
+    Task task = fetch(a, tg, kStageSquare);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -960,9 +1004,11 @@ __device__ __forceinline__ float inv_square(float s) { return 1.f / s / s; }
 
 __global__ __launch_bounds__(NT, 1) void kf_gram8(const StageArgs a) {
   __shared__ __attribute__((aligned(1024))) char smem[SMEM_BYTES];
-  const TaskRange tr = task_range(a);
-  for (int t = tr.start; t < tr.end; t += tr.stride) {
-    Task task = fetch(a, tr.base + t, kStageGram);
+  __shared__ int s_task;
+  TaskCursor cursor(a, &s_task);
+  int tg = 0;
+  while (cursor.next(a, tg)) {
+    Task task = fetch(a, tg, kStageGram);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -985,9 +1031,11 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
   const int level = a.level;
   int cur_p = -1;
   float f_out = 1.f, w_last = 0.f;
-  const TaskRange tr = task_range(a);
-  for (int t = tr.start; t < tr.end; t += tr.stride) {
-    Task task = fetch(a, tr.base + t, kStageSquare);
+  __shared__ int s_task;
+  TaskCursor cursor(a, &s_task);
+  int tg = 0;
+  while (cursor.next(a, tg)) {
+    Task task = fetch(a, tg, kStageSquare);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);
@@ -1029,9 +1077,11 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
   float *ep = (float *)smem;
   int cur_p = -1;
   float sc0 = 0.f, sps = 0.f;
-  const TaskRange tr = task_range(a);
-  for (int t = tr.start; t < tr.end; t += tr.stride) {
-    Task task = fetch(a, tr.base + t, kStageProduct);
+  __shared__ int s_task;
+  TaskCursor cursor(a, &s_task);
+  int tg = 0;
+  while (cursor.next(a, tg)) {
+    Task task = fetch(a, tg, kStageProduct);
     task.p = uni(task.p);
     task.tm = uni(task.tm);
     task.tn = uni(task.tn);

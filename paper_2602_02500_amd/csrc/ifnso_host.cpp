@@ -312,6 +312,9 @@ struct ifnso_plan_s {
   // slot's reuses it (and that slot's captured graph) without an upload.
   ProbDev *d_table[kSlotsRing] = {};
   std::vector<ProbDev> h_table[kSlotsRing];
+  // task counters of the 256-tile launches of one call, 8 per launch slot, per table slot: calls
+  // that share a table slot share its workspace too, which concurrent calls must not
+  uint32_t *d_qctr = nullptr;
   hipEvent_t ev[kSlotsRing] = {};
   bool ev_used[kSlotsRing] = {};
   int next_slot = 0;
@@ -590,6 +593,7 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e == hipSuccess) e = hipMemcpy(p->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice);
   p->n_all = all.size();
   if (e == hipSuccess) e = hipMalloc(&p->d_coef, coef.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->d_qctr, (size_t)kSlotsRing * (p->Jsq + 6) * kXcds * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemcpy(p->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_stats, (size_t)num_problems * kStatsPerProblem * sizeof(double));
   if (e == hipSuccess) e = hipMemset(p->d_stats, 0, (size_t)num_problems * kStatsPerProblem * sizeof(double));
@@ -650,6 +654,7 @@ extern "C" ifnso_status ifnso_plan_destroy(ifnso_plan_t p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_coef) (void)hipFree(p->d_coef);
+  if (p->d_qctr) (void)hipFree(p->d_qctr);
   if (p->d_stats) (void)hipFree(p->d_stats);
   if (p->d_params) (void)hipFree(p->d_params);
   if (p->d_fixed) (void)hipFree(p->d_fixed);
@@ -696,6 +701,7 @@ static bool fast_io_ok(const ifnso_plan_s *p, const ProbDev &d, const ProbLayout
 }
 
 static bool use_xcd_sched();
+static bool use_dynamic_queues();
 
 static void set_xcd(StageArgs &a, const int off[kXcds], const int cnt[kXcds], const ifnso_stage_config &c) {
   a.xcd_sched = (use_xcd_sched() && c.xcd_sched) ? 1 : 0;
@@ -723,7 +729,7 @@ static int fast_grid(const StageArgs &a, int cus) {
 
 // Enqueues every stage of a plan on `s`, reading problems from `table` (batched) or `one`.
 static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, const ProbDev *one, bool fast_io,
-                               hipStream_t s, const hipEvent_t *ev = nullptr) {
+                               hipStream_t s, const hipEvent_t *ev = nullptr, uint32_t *qctr = nullptr) {
   StageArgs a = base_args(p);
   const int outbf = p->out_dtype == IFNSO_BF16;
   const int cus = p->cus;
@@ -744,6 +750,8 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     return (((L0->trans ? L0->w : L0->h) + ts - 1) / ts) * (((L0->trans ? L0->h : L0->w) + ts - 1) / ts);
   };
   const int nprob = one ? 1 : p->num;
+  int qi = 0;  // next counter set of this call
+  if (qctr && (e = launch_zero_u32(qctr, (p->Jsq + 6) * kXcds, s)) != hipSuccess) return e;
   if ((e = mark()) != hipSuccess) return e;
   if (p->e4m3) {
     if ((e = launch_e4m3_pass(kE4m3Prepass, a, nprob, p->q_grid[0], s)) != hipSuccess) return e;
@@ -759,19 +767,23 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       if (!one) {
         a.tasks = p->d_tasks + p->offf_gram[t];
         set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1], p->cfg[kStageGram]);
+        a.qctr = (qctr && a.xcd_sched) ? qctr + kXcds * (qi++) : nullptr;
       }
       apply_cfg(a, p->cfg[kStageGram]);
       e = launch_e4m3_gemm(kStageGram, a, fast_grid(a, cus), s);
       a.xcd_sched = 0;
+      a.qctr = nullptr;
     } else if (fast && fast_io) {
       a.ntasks = one ? (t == tr0 ? ntiles_sym(kFastTS) : 0) : p->nf_gram[t];
       if (!one) {
         a.tasks = p->d_tasks + p->offf_gram[t];
         set_xcd(a, p->xq_gram[t][0], p->xq_gram[t][1], p->cfg[kStageGram]);
+        a.qctr = (qctr && a.xcd_sched) ? qctr + kXcds * (qi++) : nullptr;
       }
       apply_cfg(a, p->cfg[kStageGram]);
       e = launch_fast_stage(kStageGram, t, a, fast_grid(a, cus), outbf, s);
       a.xcd_sched = 0;
+      a.qctr = nullptr;
     } else if (t == 0) {
       a.ntasks = one ? ntiles_sym(kTS) : p->n_gram;
       if (!one) a.tasks = p->d_tasks + p->off_gram;
@@ -801,19 +813,23 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;
         set_xcd(a, p->xq_square[0], p->xq_square[1], p->cfg[kStageSquare]);
+        a.qctr = (qctr && a.xcd_sched) ? qctr + kXcds * (qi++) : nullptr;
       }
       apply_cfg(a, p->cfg[kStageSquare]);
       e = launch_e4m3_gemm(kStageSquare, a, fast_grid(a, cus), s);
       a.xcd_sched = 0;
+      a.qctr = nullptr;
     } else if (fast) {
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;
         set_xcd(a, p->xq_square[0], p->xq_square[1], p->cfg[kStageSquare]);
+        a.qctr = (qctr && a.xcd_sched) ? qctr + kXcds * (qi++) : nullptr;
       }
       apply_cfg(a, p->cfg[kStageSquare]);
       e = launch_fast_stage(kStageSquare, 0, a, fast_grid(a, cus), outbf, s);
       a.xcd_sched = 0;
+      a.qctr = nullptr;
     } else {
       a.ntasks = one ? ntiles_sym(kTS) : p->n_square;
       if (!one) a.tasks = p->d_tasks + p->off_square;
@@ -843,6 +859,7 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       if (!one) {
         a.tasks = p->d_tasks + p->offf_prod[t];
         set_xcd(a, p->xq_prod[t][0], p->xq_prod[t][1], p->cfg[kStageProduct]);
+        a.qctr = (qctr && a.xcd_sched) ? qctr + kXcds * (qi++) : nullptr;
       }
       apply_cfg(a, p->cfg[kStageProduct]);
       const int sp = a.split;
@@ -850,6 +867,7 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       e = launch_fast_stage(kStageProduct, t, a, fast_grid(a, cus), outbf, s);
       a.split = sp;
       a.xcd_sched = 0;
+      a.qctr = nullptr;
     } else if (t == 0) {
       a.ntasks = one ? ntiles_prod(kTS) : p->n_prod;
       if (!one) a.tasks = p->d_tasks + p->off_prod;
@@ -871,6 +889,11 @@ static ifnso_status check_matrix_args(const ifnso_plan_s *p, int i, const void *
   if (ranges_overlap(M, matrix_bytes(L.rows, ldm, L.cols, ies), Y, matrix_bytes(L.rows, ldy, L.cols, oes)))
     return fail(IFNSO_ERR_INVALID_ARGUMENT, "problem %d: Y overlaps M", i);
   return IFNSO_OK;
+}
+
+static bool use_dynamic_queues() {
+  const char *v = getenv("IFNSO_DYNAMIC_QUEUES");
+  return !(v && v[0] == '0');
 }
 
 static bool use_xcd_sched() {
@@ -950,12 +973,13 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
   }
   bool fast_io = p->fast;
   for (int i = 0; i < p->num && fast_io; i++) fast_io = fast_io_ok(p, ht[i], p->lay[i]);
+  uint32_t *qctr = use_dynamic_queues() ? p->d_qctr + (size_t)slot * (p->Jsq + 6) * kXcds : nullptr;
   const int gi = slot * 2 + (fast_io ? 1 : 0);
   if (use_graphs() && !evp) {
     if (!p->gexec[gi]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_plan(p, p->d_table[slot], nullptr, fast_io, p->cap_stream);
+      hipError_t e = enqueue_plan(p, p->d_table[slot], nullptr, fast_io, p->cap_stream, nullptr, qctr);
       hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -967,7 +991,7 @@ static ifnso_status run_batched(ifnso_plan_s *p, const void *const *M, const int
     }
     HIP_TRY(hipGraphLaunch(p->gexec[gi], s));
   } else {
-    HIP_TRY(enqueue_plan(p, p->d_table[slot], nullptr, fast_io, s, evp));
+    HIP_TRY(enqueue_plan(p, p->d_table[slot], nullptr, fast_io, s, evp, qctr));
   }
   HIP_TRY(hipEventRecord(p->ev[slot], s));
   p->ev_used[slot] = true;
