@@ -219,25 +219,32 @@ __device__ __forceinline__ bf16x8 tr_frag(const char *S, int mn_off, int kk) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// K-segment maps of an operand in split-bfloat16 products (a value carried as hi + lo bf16 halves
-// stored side by side: [X_hi | X_lo], seg columns each). The product runs over a logical K of
-// several segments; segment s of the logical range reads physical segment map(s) of the operand:
-//   KMAP_ID   identity (physical = logical)
-//   KMAP_MOD  every segment reads segment 0 (the operand is used as is against [Y_hi | Y_lo])
-//   KMAP_HHL  segments (0, 0, 1): [X_hi | X_hi | X_lo]
-//   KMAP_HLH  segments (0, 1, 0): [X_hi | X_lo | X_hi]
-// so that [X_hi | X_hi | X_lo] . [X_hi | X_lo | X_hi]^T = X_hi X_hi^T + X_hi X_lo^T + X_lo X_hi^T.
-enum KMapKind : int { KMAP_ID = 0, KMAP_MOD = 1, KMAP_HHL = 2, KMAP_HLH = 3 };
+// K maps of an operand in split-bfloat16 products (a value carried as hi + lo bf16 halves stored
+// side by side: [X_hi | X_lo], seg columns each). The product runs over a logical K made of
+// several segments, interleaved step by step: logical step q (64 wide) is segment q mod n of
+// physical step q / n, so the segments of one 64-wide K chunk follow each other and a chunk read
+// again by the next segment is still in L2. Segment t reads physical segment map(t):
+//   KMAP_ID   identity (no segments)
+//   KMAP_MOD  n = 2, segments (0, 0): the operand is used as is against [Y_hi | Y_lo]
+//   KMAP_SEG2 n = 2, segments (0, 1): [X_hi | X_lo]
+//   KMAP_HHL  n = 3, segments (0, 0, 1)
+//   KMAP_HLH  n = 3, segments (0, 1, 0)
+// so that HHL . HLH^T = X_hi X_hi^T + X_hi X_lo^T + X_lo X_hi^T, and MOD . SEG2^T = Y M^T form
+// Y_hi M^T + Y_lo M^T.
+enum KMapKind : int { KMAP_ID = 0, KMAP_MOD = 1, KMAP_HHL = 2, KMAP_HLH = 3, KMAP_SEG2 = 4 };
 
 template <int MAP>
 __device__ __forceinline__ int kphys(int k, int seg) {
   if constexpr (MAP == KMAP_ID) {
     return k;
   } else {
-    const int sg = k / seg, r = k - sg * seg;
-    if constexpr (MAP == KMAP_MOD) return r;
-    else if constexpr (MAP == KMAP_HHL) return r + (sg == 2 ? seg : 0);
-    else return r + (sg == 1 ? seg : 0);
+    constexpr int n = (MAP == KMAP_MOD || MAP == KMAP_SEG2) ? 2 : 3;
+    const int q = k >> 6, t = q % n;            // logical step, its segment
+    const int kk = ((q / n) << 6) + (k & 63);  // position in the segment
+    if constexpr (MAP == KMAP_MOD) return kk;
+    else if constexpr (MAP == KMAP_SEG2) return kk + (t == 1 ? seg : 0);
+    else if constexpr (MAP == KMAP_HHL) return kk + (t == 2 ? seg : 0);
+    else return kk + (t == 1 ? seg : 0);
   }
 }
 
@@ -1134,14 +1141,15 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
     } else if constexpr (TRANS) {
       // Y_out[n][i] = sum_k M[n][k] P[i][k]
       if constexpr (SPLIT)
-        mainloop<false, false, false, KMAP_MOD, KMAP_ID>(acc, smem, Mo, m0, Po, n0, uni(2 * P.hp), false, uni(P.hp), Kp);
+        mainloop<false, false, false, KMAP_MOD, KMAP_SEG2>(acc, smem, Mo, m0, Po, n0, uni(2 * P.hp), false, uni(P.hp), Kp,
+                                                           uni(2 * P.hp));
       else
         mainloop<false, false>(acc, smem, Mo, m0, Po, n0, Kp, false);
     } else {
       // Y[i][n] = sum_k P[i][k] M[k][n]
       if constexpr (SPLIT)
-        mainloop<false, true, false, KMAP_ID, KMAP_MOD>(acc, smem, Po, m0, Mo, n0, uni(2 * P.hp), false, uni(P.hp), 0,
-                                                        Kp);
+        mainloop<false, true, false, KMAP_SEG2, KMAP_MOD>(acc, smem, Po, m0, Mo, n0, uni(2 * P.hp), false, uni(P.hp),
+                                                          uni(2 * P.hp), Kp);
       else
         mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
