@@ -33,6 +33,9 @@ struct ProbDev {
   double *norm_part;   // [nt]         sum of squares of A per row block (diagonal Gram tiles)
   double *lvl_part;    // [levels][nt*nt] sum of squares of the stored level, upper tiles
   double *diag_part;   // [levels][nt]    trace partials of the stored level
+  double *lvl_sum;     // [kMaxLevels + 1] totals of the partials, written by a reduction launch
+                       //   after the stage that fills them (256-tile kernels): [0] the sum of
+                       //   norm_part, [l] the upper-tile sum of lvl_part level l
   double *coef;        // [kSlots] coefficients of this problem (slot layout)
   double *stats;       // [IFNSO_STATS_PER_PROBLEM]
   void *xbuf[2];       // classical NS: h x w iterates (wide orientation), leading dim ldx

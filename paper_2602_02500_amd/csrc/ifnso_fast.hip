@@ -421,10 +421,18 @@ struct FScalars {
   bool zero;
 };
 
-__device__ __forceinline__ FScalars scalars(const ProbDev &P, int norm) {
+// The totals P.lvl_sum[0 .. kMaxLevels], one per lane (lane l holds entry l; lanes beyond read
+// zero): one load per wave; lsum(t, l) reads entry l.
+__device__ __forceinline__ double lsum_load(const ProbDev &P) {
+  const int l = threadIdx.x & 63;
+  return l <= kMaxLevels ? P.lvl_sum[l] : 0.0;
+}
+__device__ __forceinline__ double lsum(double t, int l) { return __shfl(t, l, 64); }
+
+__device__ __forceinline__ FScalars scalars(double t, int norm) {
   FScalars s;
-  s.nA2 = wave_sum(P.norm_part, P.nt);
-  s.g2 = wave_sum_upper(P.lvl_part + (int64_t)1 * P.nt * P.nt, P.nt);
+  s.nA2 = lsum(t, 0);
+  s.g2 = lsum(t, 1);
   s.zero = !(s.nA2 > 0.0);
   if (norm == kFrob) {
     s.sg = s.zero ? 0.0 : 1.0 / s.nA2;
@@ -445,11 +453,10 @@ __device__ __forceinline__ double pow2_inv_round(double nb) {
   return exp2(-rint(log2(nb)));
 }
 
-__device__ __forceinline__ double level_scale(const ProbDev &P, double sg, int level) {
+__device__ __forceinline__ double level_scale(double t, double sg, int level) {
   double S = sg;
-  const int64_t nt2 = (int64_t)P.nt * P.nt;
   for (int l = 1; l < level; l++) {
-    const double F = pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+    const double F = pow2_inv_round(lsum(t, l));
     S = S * S / F;
   }
   return S;
@@ -882,18 +889,18 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
     const ProbDev &P = prob(a, task);
     if (task.p != cur_p) {
       cur_p = task.p;
-      const FScalars sc = scalars(P, a.norm);
-      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      const double ls = lsum_load(P);
+      const FScalars sc = scalars(ls, a.norm);
       if (a.basis == kGram) {
-        const double S = level_scale(P, sc.sg, level);
-        f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt));
+        const double S = level_scale(ls, sc.sg, level);
+        f_out = (float)pow2_inv_round(lsum(ls, level));
         c_acc = (float)(P.coef[level + 1] * S * S);
         c_first = (float)(P.coef[1] * sc.sg);
         if constexpr (fuse) {  // weights of the stored levels 1..J (the same recursion as level_scale)
           double Sl = sc.sg;
           for (int l = 1; l <= level; l++) {
             if (threadIdx.x == 0) wl[l] = (float)(P.coef[l] * Sl);
-            Sl = Sl * Sl / pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+            Sl = Sl * Sl / pow2_inv_round(lsum(ls, l));
           }
         }
       } else {
@@ -1049,16 +1056,15 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
     const ProbDev &P = prob(a, task);
     if (task.p != cur_p) {
       cur_p = task.p;
-      const int64_t nt2 = (int64_t)P.nt * P.nt;
-      f_out = (float)pow2_inv_round(wave_sum_upper(P.lvl_part + level * nt2, P.nt)) *
-              inv_square(P.q_scale[2 * level]);
+      const double ls = lsum_load(P);
+      f_out = (float)pow2_inv_round(lsum(ls, level)) * inv_square(P.q_scale[2 * level]);
       if constexpr (FUSE) {  // c_l S_l of the stored levels 1..J, and c_{J+1} S_{J+1}
-        double Sl = scalars(P, a.norm).sg;
+        double Sl = scalars(ls, a.norm).sg;
         for (int l = 1; l <= level + 1; l++) {
           const float w = (float)(P.coef[l] * Sl);
           if (l <= level) {
             if (threadIdx.x == 0) wl[l] = w;
-            Sl = Sl * Sl / pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+            Sl = Sl * Sl / pow2_inv_round(lsum(ls, l));
           } else {
             w_last = w;
           }
@@ -1095,7 +1101,7 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
     const ProbDev &P = prob(a, task);
     if (task.p != cur_p) {
       cur_p = task.p;
-      const FScalars sc = scalars(P, a.norm);
+      const FScalars sc = scalars(lsum_load(P), a.norm);
       double c0, ps, sout = sc.sout;
       if (P.h == 1) {
         // a single row or column: the polynomial of the scalar Gram, in float64
@@ -1206,13 +1212,13 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
     const ProbDev &P = a.tasks ? a.probs[task.p] : a.one;
     __syncthreads();
     if (threadIdx.x < 64) {  // one wave: level weights c_l S_l in float64, then float32
-      const FScalars sc = scalars(P, a.norm);
-      const int64_t nt2 = (int64_t)P.nt * P.nt;
+      const double ls = lsum_load(P);
+      const FScalars sc = scalars(ls, a.norm);
       double S = sc.sg;
       for (int l = 1; l <= a.J + 1; l++) {
         if (threadIdx.x == 0) wsh[l] = (float)(P.coef[l] * S);
         if (l <= a.J) {
-          const double F = pow2_inv_round(wave_sum_upper(P.lvl_part + l * nt2, P.nt));
+          const double F = pow2_inv_round(lsum(ls, l));
           S = S * S / F;
         }
       }
@@ -1263,6 +1269,53 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
 
 }  // namespace fast
 
+
+// Totals of the partial sums that a stage has just written, one workgroup per problem:
+// lvl_sum[level] = the upper-tile sum of lvl_part level `level`, and with the Gram (level 1) also
+// lvl_sum[0] = the sum of norm_part. Each thread adds a fixed strided subset in order, then the
+// lanes and the waves are combined in a fixed order, so the totals do not depend on the schedule
+// of the stage before. The tile kernels read these totals (lsum_load) instead of summing the
+// partials again in every workgroup that starts on a problem.
+__global__ __launch_bounds__(kThreads) void kf_level_sums(const StageArgs a, int batched, int level) {
+  const ProbDev &P = batched ? a.probs[blockIdx.x] : a.one;
+  __shared__ double red[kThreads / 64][2];
+  const int nt = P.nt;
+  const int n = nt * nt;
+  const double *lp = P.lvl_part + (int64_t)level * n;
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const int r = i / nt, c = i - r * nt;
+    if (c >= r) s += lp[i];
+  }
+  if (level == 1)
+    for (int i = threadIdx.x; i < nt; i += kThreads) t += P.norm_part[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    t += __shfl_xor(t, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = s;
+    red[threadIdx.x >> 6][1] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s = red[0][0];
+    t = red[0][1];
+    for (int w = 1; w < kThreads / 64; w++) {
+      s += red[w][0];
+      t += red[w][1];
+    }
+    P.lvl_sum[level] = s;
+    if (level == 1) P.lvl_sum[0] = t;
+  }
+}
+
+hipError_t launch_level_sums(const StageArgs &a, int nprob, int level, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kf_level_sums, dim3(nprob), dim3(kThreads), 0, s, a, a.probs ? 1 : 0, level);
+  return hipGetLastError();
+}
 
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;

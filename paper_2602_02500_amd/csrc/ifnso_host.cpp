@@ -56,7 +56,7 @@ constexpr int kPad = 256;
 struct ProbLayout {
   int64_t rows, cols;
   int32_t h, w, trans, hp, nt;
-  size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_xbuf[2], off_lv;
+  size_t off_opnd[2], off_accf, off_df[2], off_norm, off_lvl, off_diag, off_lsum, off_xbuf[2], off_lv;
   int64_t ldx, lv_stride;
   // the generic Gram split along K (ksplit chunks of kchunk columns) when it has few tiles
   int32_t ksplit, kchunk;
@@ -134,6 +134,7 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
   L.off_norm = take((size_t)L.nt * 8);
   L.off_lvl = take((size_t)levels * L.nt * L.nt * 8);
   L.off_diag = take((size_t)levels * L.nt * 8);
+  L.off_lsum = take((size_t)(kMaxLevels + 1) * 8);
   if (ns) {
     L.ldx = round_up(L.w, 8);
     L.off_xbuf[0] = take((size_t)L.h * L.ldx * op_size(op));
@@ -184,6 +185,7 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
   d.norm_part = (double *)(ws + L.off_norm);
   d.lvl_part = (double *)(ws + L.off_lvl);
   d.diag_part = (double *)(ws + L.off_diag);
+  d.lvl_sum = (double *)(ws + L.off_lsum);
   d.coef = coef;
   d.stats = stats;
   d.xbuf[0] = L.off_xbuf[0] ? ws + L.off_xbuf[0] : nullptr;
@@ -803,6 +805,9 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     }
     if (e != hipSuccess) return e;
   }
+  // the 256-tile kernels read per-problem totals of the partials (ProbDev::lvl_sum)
+  const bool sums = fast || p->e4m3;
+  if (sums && (e = launch_level_sums(a, nprob, 1, s)) != hipSuccess) return e;
   for (int lvl = 1; lvl <= p->Jsq; lvl++) {
     if ((e = mark()) != hipSuccess) return e;
     a.level = lvl;
@@ -836,6 +841,8 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
       e = launch_stage(p->op, kTS, kStageSquare, a, grid_for(p->op, kStageSquare, a.ntasks, cus), outbf, s);
     }
     if (e != hipSuccess) return e;
+    // level lvl + 1 is read by the next squaring and by the aggregate stage, never after the last
+    if (sums && lvl < p->Jsq && (e = launch_level_sums(a, nprob, lvl + 1, s)) != hipSuccess) return e;
   }
   a.level = 0;
   a.last = 0;

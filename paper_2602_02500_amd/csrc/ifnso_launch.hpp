@@ -31,6 +31,9 @@ hipError_t launch_fast_stage(int stage, int trans, const StageArgs &a, int grid,
 hipError_t fast_occupancy(int stage, int *blocks_per_cu);
 // P = sum_l c_l S_l B_l over the stored levels (level layout); tasks are (problem, chunk)
 hipError_t launch_aggregate(const StageArgs &a, int grid, hipStream_t s);
+// 256-tile kernels: per-problem totals of the partials of level `level` (and of the norm with
+// the Gram, level 1) into ProbDev::lvl_sum, one workgroup per problem.
+hipError_t launch_level_sums(const StageArgs &a, int nprob, int level, hipStream_t s);
 constexpr int kAggChunk = 1 << 17;  // elements per aggregate task
 
 // e4m3 compute (ifnso_fp8.hip): memory-bound passes, one grid row per problem
