@@ -103,6 +103,49 @@ __device__ __forceinline__ double lds_sumsq(const char *At) {
   return s;
 }
 
+// Global-memory views of generic pointers. An access through a generic (flat) pointer counts in
+// both the vector-memory and the LDS wait counters, so each wait for an LDS read would also wait
+// for every global load and store still in flight; through these views the accesses are global
+// ones, which only the vector-memory counter tracks.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T *p) {
+  return (gptr<T>)p;
+}
+// 8- and 16-byte accesses through a global view q (any gptr): HIP's vector classes have no
+// members for address-space-qualified objects, so these go through clang's vector types.
+typedef uint32_t gu2 __attribute__((ext_vector_type(2)));
+typedef uint32_t gu4 __attribute__((ext_vector_type(4)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+template <typename Q>
+__device__ __forceinline__ void gst(Q q, uint2 v) {
+  *(gptr<gu2>)q = gu2{v.x, v.y};
+}
+template <typename Q>
+__device__ __forceinline__ void gst(Q q, uint4 v) {
+  *(gptr<gu4>)q = gu4{v.x, v.y, v.z, v.w};
+}
+template <typename Q>
+__device__ __forceinline__ void gst(Q q, float4 v) {
+  *(gptr<gf4>)q = gf4{v.x, v.y, v.z, v.w};
+}
+template <typename Q>
+__device__ __forceinline__ uint2 gld_u2(Q q) {
+  const gu2 v = *(gptr<const gu2>)q;
+  return make_uint2(v.x, v.y);
+}
+template <typename Q>
+__device__ __forceinline__ uint4 gld_u4(Q q) {
+  const gu4 v = *(gptr<const gu4>)q;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <typename Q>
+__device__ __forceinline__ float4 gld_f4(Q q) {
+  const gf4 v = *(gptr<const gf4>)q;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // vmcnt-only wait (expcnt and lgkmcnt left at their maxima)
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -542,15 +585,16 @@ __device__ __forceinline__ const ProbDev &prob(const StageArgs &a, const Task &t
 // the other covered upper slots get 0, so consumers sum the same grid as for 128 tiles.
 __device__ __forceinline__ void write_level_partials(const ProbDev &P, int level, const Task &t, double lv, double dg) {
   const int nt = P.nt;
-  double *lp = P.lvl_part + (int64_t)level * nt * nt;
+  gptr<double> lp = gbl(P.lvl_part + (int64_t)level * nt * nt);
   const int r0 = 2 * t.tm, c0 = 2 * t.tn;
   lp[r0 * nt + c0] = lv;
   lp[r0 * nt + c0 + 1] = 0.0;
   lp[(r0 + 1) * nt + c0 + 1] = 0.0;
   if (t.tm != t.tn) lp[(r0 + 1) * nt + c0] = 0.0;
   if (t.tm == t.tn) {
-    P.diag_part[level * nt + r0] = dg;
-    P.diag_part[level * nt + r0 + 1] = 0.0;
+    gptr<double> dp = gbl(P.diag_part + level * nt);
+    dp[r0] = dg;
+    dp[r0 + 1] = 0.0;
   }
 }
 
@@ -566,13 +610,13 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
     constexpr int RS = NT / 64;  // rows per iteration
     const int row0 = threadIdx.x >> 6, c4 = (threadIdx.x & 63) * 4;
     const float *src = ep + row0 * EP_LD + c4;
-    uint16_t *d = dst + (int64_t)(m0 + half * 128 + row0) * hp + n0 + c4;
+    gptr<uint16_t> d = gbl(dst + (int64_t)(m0 + half * 128 + row0) * hp + n0 + c4);
 #pragma unroll 4
     for (int it = 0; it < 128 / RS; it++) {
       const float4 v = *(const float4 *)(src + it * RS * EP_LD);
       const int row = row0 + it * RS;
-      *(uint2 *)(d + (int64_t)uni(it * RS) * hp) = make_uint2(pack_bf16x2(f(v.x, row, c4), f(v.y, row, c4 + 1)),
-                                                              pack_bf16x2(f(v.z, row, c4 + 2), f(v.w, row, c4 + 3)));
+      gst(d + (int64_t)uni(it * RS) * hp, make_uint2(pack_bf16x2(f(v.x, row, c4), f(v.y, row, c4 + 1)),
+                                                     pack_bf16x2(f(v.z, row, c4 + 2), f(v.w, row, c4 + 3))));
     }
   }
   if (diag) return;
@@ -584,7 +628,7 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
     constexpr int CPI = NT / 4, NC = 256 / CPI;  // columns per iteration, iterations per 32 rows
     const int c0 = threadIdx.x >> 2, r0 = (threadIdx.x & 3) * 8;
     const float *src = ep + r0 * EP_LD + c0;
-    uint16_t *d = dst + (int64_t)(n0 + c0) * hp + m0 + half * 128 + r0;
+    gptr<uint16_t> d = gbl(dst + (int64_t)(n0 + c0) * hp + m0 + half * 128 + r0);
 #pragma unroll 8
     for (int it = 0; it < 4 * NC; it++) {
       const int dc = CPI * (it % NC), dr = 32 * (it / NC);
@@ -596,7 +640,7 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
       o.y = pack_bf16x2(v[2], v[3]);
       o.z = pack_bf16x2(v[4], v[5]);
       o.w = pack_bf16x2(v[6], v[7]);
-      *(uint4 *)(d + (int64_t)uni(dc) * hp + dr) = o;
+      gst(d + (int64_t)uni(dc) * hp + dr, o);
     }
   }
 }
@@ -713,7 +757,7 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
     write_level_partials(P, out, task, lv, dg);
     if constexpr (AMAX) {
       const int nt = P.nt, r0 = 2 * task.tm, c0 = 2 * task.tn;
-      float *ap = P.amax_part + (int64_t)out * nt * nt;
+      gptr<float> ap = gbl(P.amax_part + (int64_t)out * nt * nt);
       ap[r0 * nt + c0] = mx;
       ap[r0 * nt + c0 + 1] = 0.f;
       ap[(r0 + 1) * nt + c0 + 1] = 0.f;
@@ -768,7 +812,7 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
       for (int q = threadIdx.x; q < 128 * 64; q += NT) {
         const int row = q >> 6, c4 = (q & 63) * 4;
         const float4 v = *(const float4 *)(ep + row * EP_LD + c4);
-        if (keep_f32) *(float4 *)(P.accf + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4) = v;
+        if (keep_f32) gst(gbl(P.accf + (int64_t)(m0 + half * 128 + row) * hp + n0 + c4), v);
         const double w = diag ? 1.0 : 2.0;
         lv += w * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w);
         if (diag) {
@@ -783,8 +827,9 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
     if (threadIdx.x == 0) {
       write_level_partials(P, 1, task, lv, dg);
       if (diag) {
-        P.norm_part[2 * task.tm] = nrm;
-        P.norm_part[2 * task.tm + 1] = 0.0;
+        gptr<double> np = gbl(P.norm_part);
+        np[2 * task.tm] = nrm;
+        np[2 * task.tm + 1] = 0.0;
       }
     }
     __syncthreads();
@@ -813,7 +858,7 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
     stage_half(acc, ep, half);
     __syncthreads();
     float *src = ep + row0 * EP_LD + c4;
-    const char *lb = (const char *)P.lv + ((int64_t)(m0 + half * 128 + row0) * hp + n0 + c4) * 2;
+    gptr<const char> lb = gbl((const char *)P.lv + ((int64_t)(m0 + half * 128 + row0) * hp + n0 + c4) * 2);
     // two row groups per pass, levels four at a time: up to eight 8-byte loads in flight
     constexpr int UR = 2, UL = 4;
     for (int it = 0; it < 128 / RS; it += UR) {
@@ -833,8 +878,7 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
         for (int u = 0; u < UR; u++)
 #pragma unroll
           for (int k = 0; k < UL; k++)
-            q[u][k] = l0 + k <= J ? *(const uint2 *)(lb + (int64_t)uni((it + u) * RS) * hp * 2 +
-                                                     (int64_t)(l0 + k - 1) * P.lv_stride)
+            q[u][k] = l0 + k <= J ? gld_u2(lb + (int64_t)uni((it + u) * RS) * hp * 2 + (int64_t)(l0 + k - 1) * P.lv_stride)
                                   : make_uint2(0, 0);
 #pragma unroll
         for (int k = 0; k < UL; k++) {
@@ -946,18 +990,18 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
           const int q = threadIdx.x + NT * (b0 + u);
           const int row = q >> 6, c4 = (q & 63) * 4;
           const int64_t gi = (int64_t)(m0 + half * 128 + row) * hp + n0 + c4;
-          pin[u] = *(const float4 *)(P.accf + gi);
+          pin[u] = gld_f4(gbl(P.accf + gi));
           if constexpr (SPLIT) {
             // D_level from its split operand (hi + lo) instead of a float32 copy
             if (level > 1) {
-              const uint16_t *so = (const uint16_t *)P.opnd[(level - 1) & 1] + (int64_t)(m0 + half * 128 + row) * (2 * hp) +
+              gptr<const uint16_t> so = gbl((const uint16_t *)P.opnd[(level - 1) & 1]) + (int64_t)(m0 + half * 128 + row) * (2 * hp) +
                                    n0 + c4;
-              const uint2 h2 = *(const uint2 *)so, l2 = *(const uint2 *)(so + hp);
+              const uint2 h2 = gld_u2(so), l2 = gld_u2(so + hp);
               dpv[u] = make_float4(bf16_pair_lo(h2.x) + bf16_pair_lo(l2.x), bf16_pair_hi(h2.x) + bf16_pair_hi(l2.x),
                                    bf16_pair_lo(h2.y) + bf16_pair_lo(l2.y), bf16_pair_hi(h2.y) + bf16_pair_hi(l2.y));
             }
           } else if (a.basis != kGram && level > 1) {
-            dpv[u] = *(const float4 *)(P.df[level & 1] + gi);
+            dpv[u] = gld_f4(gbl(P.df[level & 1] + gi));
           }
         }
 #pragma unroll
@@ -984,9 +1028,9 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
                                          : pin[u];
             pv = make_float4(p0.x + c_next * outv.x, p0.y + c_next * outv.y, p0.z + c_next * outv.z,
                              p0.w + c_next * outv.w);
-            if (!SPLIT && !last) *(float4 *)(P.df[(level + 1) & 1] + gi) = outv;
+            if (!SPLIT && !last) gst(gbl(P.df[(level + 1) & 1] + gi), outv);
           }
-          if (!last) *(float4 *)(P.accf + gi) = pv;
+          if (!last) gst(gbl(P.accf + gi), pv);
           const double w = diag ? 1.0 : 2.0;
           lv += w * ((double)outv.x * outv.x + (double)outv.y * outv.y + (double)outv.z * outv.z +
                      (double)outv.w * outv.w);
@@ -1168,12 +1212,12 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
       stage_half(acc, ep, half);
       __syncthreads();
       const int r0 = m0 + half * 128 + row0;
-      const uint16_t *mp = (const uint16_t *)P.M + (int64_t)r0 * P.ldm + c;
+      gptr<const uint16_t> mp = gbl((const uint16_t *)P.M) + (int64_t)r0 * P.ldm + c;
       const float *src = ep + row0 * EP_LD + c8;
       uint4 xm[PER];
 #pragma unroll
       for (int u = 0; u < PER; u++)
-        xm[u] = (cin && r0 + u * RS < rows_out) ? *(const uint4 *)(mp + (int64_t)uni(u * RS) * P.ldm)
+        xm[u] = (cin && r0 + u * RS < rows_out) ? gld_u4(mp + (int64_t)uni(u * RS) * P.ldm)
                                                  : make_uint4(0, 0, 0, 0);
 #pragma unroll
       for (int u = 0; u < PER; u++) {
@@ -1188,12 +1232,12 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
         }
         const int64_t yo = (int64_t)(r0 + u * RS) * P.ldy + c;
         if (out_bf16) {
-          *(uint4 *)((uint16_t *)P.Y + yo) = make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]),
-                                                        pack_bf16x2(y[4], y[5]), pack_bf16x2(y[6], y[7]));
+          gst(gbl((uint16_t *)P.Y + yo), make_uint4(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]),
+                                                   pack_bf16x2(y[4], y[5]), pack_bf16x2(y[6], y[7])));
         } else {
-          float *yp = (float *)P.Y + yo;
-          *(float4 *)yp = make_float4(y[0], y[1], y[2], y[3]);
-          *(float4 *)(yp + 4) = make_float4(y[4], y[5], y[6], y[7]);
+          gptr<float> yp = gbl((float *)P.Y + yo);
+          gst(yp, make_float4(y[0], y[1], y[2], y[3]));
+          gst(yp + 4, make_float4(y[4], y[5], y[6], y[7]));
         }
       }
       __syncthreads();
@@ -1228,7 +1272,7 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
     const int64_t e0 = (int64_t)task.tm * kAggChunk;
     const int64_t e1 = e0 + kAggChunk < n ? e0 + kAggChunk : n;
     const int L = a.J + 1;
-    char *base = (char *)P.lv;
+    gptr<char> base = gbl((char *)P.lv);
     constexpr int U = 4;  // chunks of 8 elements per thread in flight
     for (int64_t e = e0 + (int64_t)threadIdx.x * 8; e < e1; e += (int64_t)kThreads * 8 * U) {
       float acc[U][8];
@@ -1238,12 +1282,12 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
         for (int i = 0; i < 8; i++) acc[u][i] = 0.f;
       for (int l = 1; l <= L; l++) {
         const float wl = wsh[l];
-        const uint16_t *src = (const uint16_t *)(base + (int64_t)(l - 1) * P.lv_stride);
+        gptr<const uint16_t> src = (gptr<const uint16_t>)(base + (int64_t)(l - 1) * P.lv_stride);
         uint4 v[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
           const int64_t ee = e + (int64_t)u * kThreads * 8;
-          v[u] = ee < e1 ? *(const uint4 *)(src + ee) : make_uint4(0, 0, 0, 0);
+          v[u] = ee < e1 ? gld_u4(src + ee) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -1255,13 +1299,13 @@ __global__ __launch_bounds__(kThreads) void kf_aggregate(const StageArgs a) {
           }
         }
       }
-      uint16_t *dst = (uint16_t *)base;
+      gptr<uint16_t> dst = (gptr<uint16_t>)base;
 #pragma unroll
       for (int u = 0; u < U; u++) {
         const int64_t ee = e + (int64_t)u * kThreads * 8;
         if (ee < e1)
-          *(uint4 *)(dst + ee) = make_uint4(pack_bf16x2(acc[u][0], acc[u][1]), pack_bf16x2(acc[u][2], acc[u][3]),
-                                            pack_bf16x2(acc[u][4], acc[u][5]), pack_bf16x2(acc[u][6], acc[u][7]));
+          gst(dst + ee, make_uint4(pack_bf16x2(acc[u][0], acc[u][1]), pack_bf16x2(acc[u][2], acc[u][3]),
+                                   pack_bf16x2(acc[u][4], acc[u][5]), pack_bf16x2(acc[u][6], acc[u][7])));
       }
     }
   }
