@@ -452,8 +452,12 @@ __device__ __forceinline__ void stage_half(const f32x16 (&acc)[FM][FN], float *e
   }
 }
 
+// Two float32 values rounded to bfloat16 (to nearest, ties to even) and packed, a in the low
+// half: one v_cvt_pk_bf16_f32.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  return (uint32_t)f32_to_bf16(a) | ((uint32_t)f32_to_bf16(b) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -646,7 +650,7 @@ __device__ __forceinline__ void emit_sym_bf16(const float *ep, uint16_t *dst, in
 }
 
 // bfloat16 value of v (round to nearest even), as a float
-__device__ __forceinline__ float bf16_value(float v) { return __uint_as_float((uint32_t)f32_to_bf16(v) << 16); }
+__device__ __forceinline__ float bf16_value(float v) { return __uint_as_float(pack_bf16x2(v, 0.f) << 16); }
 // The two bfloat16 values packed in a 32-bit word (the lower address in the low half).
 __device__ __forceinline__ float bf16_pair_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_pair_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
@@ -707,10 +711,13 @@ __device__ __forceinline__ float block_max(float v, float *scratch) {
 
 // Sum of squares and (AMAX) max |value| of scale * tile straight from the accumulators (each
 // lane's 32 x 32 blocks summed in float32, accumulated in float64); off-diagonal tiles count
-// twice (mirror).
+// twice (mirror). The scale is a power of two, so the sums of the raw accumulators times scale^2
+// (and |scale| times their maximum) are the same numbers, one multiply per value cheaper.
 template <bool AMAX>
 __device__ __forceinline__ void reg_partials(const f32x16 (&acc)[FM][FN], float scale, bool diag, double &lv,
                                              float &mx) {
+  double sum = 0.0;
+  float amax = 0.f;
 #pragma unroll
   for (int i = 0; i < FM; i++)
 #pragma unroll
@@ -718,13 +725,13 @@ __device__ __forceinline__ void reg_partials(const f32x16 (&acc)[FM][FN], float 
       float s2 = 0.f;
 #pragma unroll
       for (int r = 0; r < 16; r++) {
-        const float x = scale * acc[i][j][r];
-        s2 = fmaf(x, x, s2);
-        if constexpr (AMAX) mx = fmaxf(mx, fabsf(x));
+        s2 = fmaf(acc[i][j][r], acc[i][j][r], s2);
+        if constexpr (AMAX) amax = fmaxf(amax, fabsf(acc[i][j][r]));
       }
-      lv += (double)s2;
+      sum += (double)s2;
     }
-  if (!diag) lv *= 2.0;
+  lv += sum * ((double)scale * (double)scale) * (diag ? 1.0 : 2.0);
+  if constexpr (AMAX) mx = fmaxf(mx, fabsf(scale) * amax);
 }
 
 // Level-layout epilogue: level `out` = scale * acc is stored as bfloat16 (tile and mirror) at
@@ -736,7 +743,6 @@ __device__ __forceinline__ void reg_partials(const f32x16 (&acc)[FM][FN], float 
 template <bool AMAX>
 __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *smem, const ProbDev &P, int out,
                                             const Task &task, float scale) {
-  float *ep = (float *)smem;
   const int m0 = task.tm * BM, n0 = task.tn * BN;
   const bool diag = task.tm == task.tn;
   const int64_t hp = P.hp;
@@ -744,6 +750,7 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
   double lv = 0.0, dg = 0.0, unused = 0.0;
   float mx = 0.f;
   reg_partials<AMAX>(acc, scale, diag, lv, mx);
+  float *ep = (float *)smem;
   for (int half = 0; half < 2; half++) {
     stage_half(acc, ep, half);
     __syncthreads();
