@@ -53,12 +53,14 @@ typedef enum { IFNSO_F32 = 0, IFNSO_BF16 = 1 } ifnso_dtype;
 /* operand type of the matrix products (accumulation is always float32):
  *  F32   float32 operands on the FP32 matrix cores (the plain path; M must be F32)
  *  BF16  bfloat16 operands (M must be BF16)
- *  FP8_E4M3  OCP e4m3 operands (round to nearest even) for the Gram and the squarings, each
- *        operand with its own power-of-two scale s = 2^floor(log2(448 / amax)) from the
- *        absolute maximum of the tensor it quantises (A, then each stored power; exponent
- *        clamped to [-63, 63]); ||A||_F comes from a float64 pre-pass over M; the stored powers,
- *        their weighted sum and the final product use bfloat16. Gram basis only; M must be
- *        BF16; problems need h * round_up(w, 16) < 2^31 and h <= 32512. */
+ *  FP8_E4M3  OCP e4m3 operands (round to nearest even) for the Gram and the squarings, with
+ *        power-of-two scales s = 2^floor(log2(448 / amax)) (exponent clamped to [-63, 63]):
+ *        A takes one scale from its absolute maximum; each stored power is quantised where it
+ *        is produced, every 256 x 256 tile with the scale of its own maximum, and the squaring
+ *        that reads it applies the tiles' scales in the matrix instruction. ||A||_F comes from
+ *        a float64 pre-pass over M; the stored powers, their weighted sum and the final
+ *        product use bfloat16. Gram basis only; M must be BF16; problems need
+ *        h * round_up(w, 16) < 2^31 and h <= 32512. */
 typedef enum { IFNSO_COMPUTE_F32 = 0, IFNSO_COMPUTE_BF16 = 1, IFNSO_COMPUTE_FP8_E4M3 = 2 } ifnso_compute;
 
 typedef enum { IFNSO_BASIS_GRAM = 0, IFNSO_BASIS_COMPLEMENT = 1 } ifnso_basis;
@@ -177,8 +179,8 @@ ifnso_status ifnso_orthogonalize_batched(ifnso_plan_t plan, const void *const *M
 /* Launch slots of one call of this plan, in order: preparation (in FP8_E4M3 plans the pre-pass
  * (||A||_F and amax) with the e4m3 quantisation of A; empty in other plans), Gram for the
  * problems with rows <= cols, Gram for the
- * transposed (rows > cols) problems, one squaring per level (in FP8_E4M3 plans with the
- * quantisation of the power it squares), the aggregation of the weighted powers, then the
+ * transposed (rows > cols) problems, one squaring per level, the aggregation of the weighted
+ * powers, then the
  * product for the two groups in the same order: J + 6 slots where 2^J is the largest exponent.
  * A slot with no work in a call launches nothing. The aggregation slot runs only in learned
  * plans and in FP8_E4M3 plans without squarings; the other bfloat16 and FP8_E4M3 Gram-basis

@@ -8,8 +8,13 @@ operands for the Gram and the squarings). This module states that variant exactl
   infinities; 0x7F / 0xFF are NaN; largest finite value 448 = 1.75 * 2^8; smallest normal
   2^-6; subnormals k * 2^-9. Rounding is to nearest, ties to even; magnitudes beyond 448
   saturate to 448.
-* Per-tensor scale of an operand T: s = 2^e, e = floor(log2(448 / max|T|)) clamped to
-  [-63, 63] (s = 1 for an all-zero or non-finite maximum); the operand is e4m3(s T) / s.
+* Scale of an operand block T: s = 2^e, e = floor(log2(448 / max|T|)) clamped to
+  [-63, 63] (s = 1 for an all-zero or non-finite maximum); the block is e4m3(s T) / s.
+  The Gram's operand A takes one scale for the whole tensor. A stored level is quantised
+  where it is produced, tile by tile, before the whole level's maximum exists: each
+  256 x 256 tile (counted from the origin; edge tiles are partial) takes the scale of its
+  own maximum, and the squaring that reads it applies the tiles' scales exactly (powers of
+  two). A level of at most 256 rows is one tile, so there the two rules agree.
 * Stored powers, their weighted sum P and the operands of the final product are bfloat16
   (8 significant bits, ties to even). Rounding is applied scale-free (on the significand),
   which is what the GPU's power-of-two rescaled levels see.
@@ -26,11 +31,12 @@ import numpy as np
 from .ifnso import _check_terms, orient
 
 __all__ = [
-    "E4M3_MAX", "e4m3_round", "e4m3_encode", "e4m3_decode", "e4m3_scale", "e4m3_quantize",
-    "bf16_round", "ifnso_e4m3",
+    "E4M3_MAX", "E4M3_TILE", "e4m3_round", "e4m3_encode", "e4m3_decode", "e4m3_scale", "e4m3_quantize",
+    "e4m3_quantize_tiles", "bf16_round", "ifnso_e4m3",
 ]
 
 E4M3_MAX = 448.0
+E4M3_TILE = 256  # side of the square tiles that carry their own scale in a stored level
 
 
 def e4m3_decode(codes) -> np.ndarray:
@@ -92,6 +98,17 @@ def e4m3_quantize(T):
     return e4m3_round(T * s) / s, s
 
 
+def e4m3_quantize_tiles(T, tile: int = E4M3_TILE) -> np.ndarray:
+    """e4m3(s_t T_t) / s_t for every tile x tile block T_t of T (from the origin; edge blocks
+    are partial), each with the scale of its own maximum (e4m3_scale)."""
+    T = np.asarray(T, dtype=np.float64)
+    out = np.empty_like(T)
+    for r0 in range(0, T.shape[0], tile):
+        for c0 in range(0, T.shape[1], tile):
+            out[r0:r0 + tile, c0:c0 + tile] = e4m3_quantize(T[r0:r0 + tile, c0:c0 + tile])[0]
+    return out
+
+
 def bf16_round(x) -> np.ndarray:
     """Nearest value with 8 significant bits (ties to even), on the significand."""
     x = np.asarray(x, dtype=np.float64)
@@ -104,21 +121,22 @@ def _identity(x):
 
 
 def ifnso_e4m3(M, exponents: Sequence[int], coeffs: Sequence[float], norm: str = "frobenius",
-               quantize=None, store=None) -> np.ndarray:
+               quantize=None, store=None, quantize_level=None) -> np.ndarray:
     """Gram-basis IFNSO with e4m3 operands for the Gram and the squarings.
 
     In the order of the method (Sec. 1 transposition, Sec. 2.4 squaring, Algorithm 1):
       A  = M or M^T (h <= w);  s_A = ||A||_F from the unquantised A (float64)
       L1 = store(Q(A) Q(A)^T)                    the Gram, unnormalised
-      L_{l+1} = store(Q(L_l) Q(L_l))             repeated squaring (L_l symmetric)
+      L_{l+1} = store(QL(L_l) QL(L_l))           repeated squaring (L_l symmetric)
       B^(2^(l-1)) = L_l / n^(2^l)                n = s_A (Frobenius), ||L1||_F^(1/2)
                                                  (Gram-Frobenius) or 1 (none)
       P  = store(sum_{e_k >= 1} c_k B^(e_k));  Y = (c_0 A + P A) / n
-    Q is the per-tensor e4m3 quantiser, `store` the bfloat16 rounding of stored matrices.
-    Both can be replaced (identity: the plain float64 polynomial). Returns Y in M's
-    orientation."""
+    Q is the per-tensor e4m3 quantiser, QL the per-tile one (e4m3_quantize_tiles), `store` the
+    bfloat16 rounding of stored matrices. Any can be replaced (identity: the plain float64
+    polynomial); `quantize` alone replaces both quantisers. Returns Y in M's orientation."""
     e, c = _check_terms(exponents, coeffs)
     Q = quantize if quantize is not None else (lambda T: e4m3_quantize(T)[0])
+    QL = quantize_level if quantize_level is not None else (quantize if quantize is not None else e4m3_quantize_tiles)
     store = store if store is not None else bf16_round
     A, trans = orient(M)
     h = A.shape[0]
@@ -127,7 +145,7 @@ def ifnso_e4m3(M, exponents: Sequence[int], coeffs: Sequence[float], norm: str =
     while (1 << J) < e[-1]:
         J += 1
     for l in range(1, J + 1):
-        Ql = Q(levels[l])
+        Ql = QL(levels[l])
         levels[l + 1] = store(Ql @ Ql)
     if norm == "frobenius":
         n = math.sqrt(float(np.sum(A * A)))

@@ -46,14 +46,17 @@ struct ProbDev {
   void *lv;            // level layout: level l (l = 1..J+1) stored at lv + (l-1) * lv_stride bytes,
   int64_t lv_stride;   //   as a full symmetric h x h operand; level 1 later holds P
   // e4m3 compute: per-tensor scaled OCP e4m3 copy of A (h rows, leading dimension ldq, K
-  // contiguous, zero beyond w) for the Gram, later of the current level (hp x hp) for a squaring
+  // contiguous, zero beyond w) for the Gram
   uint8_t *q8;
   int64_t ldq;
+  // e4m3 copies of the stored levels, written by the epilogue that produces each level: level
+  // l in ql[l & 1] (hp x hp, full symmetric), each 256 x 256 tile t scaled by its own power of
+  // two 2^e_t, with e_t in qexp[l & 1][tm * (hp / 256) + tn] (tile and mirror alike)
+  uint8_t *ql[2];
+  int32_t *qexp[2];
   double *q_part;      // [nq] pre-pass sums of squares of M, chunks of rq storage rows
   float *q_amax;       // [nq] pre-pass max |M| per chunk
-  float *amax_part;    // [levels][nt*nt] max |stored level| per tile (upper tiles)
-  float *q_scale;      // [2 (kMaxLevels + 1)]: [2l] scale (a power of two), [2l + 1] max |value|;
-                       //   l = 0 the input, l >= 1 level l
+  float *q_scale;      // [2]: the input's scale (a power of two) and max |value|
   int32_t nq, rq;
 };
 

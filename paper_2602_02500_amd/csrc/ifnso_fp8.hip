@@ -1,7 +1,7 @@
 // Memory-bound passes of the e4m3 compute mode: per-tensor amax and sum of squares of the
-// input, quantisation of A (transposed for tall inputs) and of each stored level to OCP e4m3
-// with a power-of-two scale. The e4m3 Gram and squaring GEMMs live with the other 256 x 256
-// kernels; they consume what these passes write.
+// input, and quantisation of A (transposed for tall inputs) to OCP e4m3 with a power-of-two
+// scale. The e4m3 Gram and squaring GEMMs live with the other 256 x 256 kernels; they consume
+// what these passes write, and their epilogues quantise each stored level tile by tile.
 //
 // Scale rule: s = 2^e with e = floor(log2(448 / amax)) (448 is e4m3's largest finite value),
 // so the scaled maximum lies in (224, 448] and the scaling itself is exact; e is clamped to
@@ -22,14 +22,7 @@ namespace e4m3 {
 
 __device__ __forceinline__ const ProbDev &problem(const StageArgs &a) { return a.probs ? a.probs[blockIdx.y] : a.one; }
 
-__device__ __forceinline__ float scale_from_amax(float amax) {
-  if (!(amax > 0.f) || !isfinite(amax)) return 1.f;
-  int x;
-  const float f = frexpf(amax, &x);  // amax = f 2^x, f in [0.5, 1)
-  int e = (2.f * f <= 1.75f ? 9 : 8) - x;
-  e = e < -63 ? -63 : (e > 63 ? 63 : e);
-  return ldexpf(1.f, e);
-}
+__device__ __forceinline__ float scale_from_amax(float amax) { return ldexpf(1.f, e4m3_scale_exp(amax)); }
 
 // four floats -> four e4m3 bytes, first value in the lowest byte
 __device__ __forceinline__ uint32_t pack4(float a, float b, float c, float d) {
@@ -62,16 +55,6 @@ __device__ __forceinline__ float block_max(float v, float *scratch) {
   v = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
   __syncthreads();
   return v;
-}
-
-// max over the upper tiles (c >= r) of an nt x nt grid of tile maxima
-__device__ __forceinline__ float max_upper(const float *p, int nt, float *scratch) {
-  float m = 0.f;
-  for (int i = threadIdx.x; i < nt * nt; i += blockDim.x) {
-    const int r = i / nt, c = i - r * nt;
-    if (c >= r) m = fmaxf(m, p[i]);
-  }
-  return block_max(m, scratch);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -208,29 +191,6 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// quantise level `a.level` (bfloat16, hp x hp, full symmetric) into q8 with its own scale
-// ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_quant_level(const StageArgs a) {
-  __shared__ float fscr[4];
-  const ProbDev &P = problem(a);
-  const int level = a.level;
-  const float mx = max_upper(P.amax_part + (int64_t)level * P.nt * P.nt, P.nt, fscr);
-  const float s = scale_from_amax(mx);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    P.q_scale[2 * level] = s;
-    P.q_scale[2 * level + 1] = mx;
-  }
-  const uint16_t *src = (const uint16_t *)((const char *)P.lv + (int64_t)(level - 1) * P.lv_stride);
-  const int64_t ng = (int64_t)P.hp * P.hp / 16;
-  for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < ng; g += (int64_t)gridDim.x * kThreads) {
-    float x[16];
-    unpack8(*(const uint4 *)(src + g * 16), x);
-    unpack8(*(const uint4 *)(src + g * 16 + 8), x + 8);
-    *(uint4 *)(P.q8 + g * 16) = pack16(x, s);
-  }
-}
-
 __global__ void k_export(const ProbDev P, double *out) {
   if (threadIdx.x == 0) {
     out[0] = P.norm_part[0];
@@ -246,8 +206,7 @@ hipError_t launch_e4m3_pass(int which, const StageArgs &a, int nprob, int per_pr
   if (nprob <= 0) return hipSuccess;
   const dim3 grid(per_problem, nprob);
   if (which == kE4m3Prepass) hipLaunchKernelGGL(e4m3::k_prepass, grid, dim3(kThreads), 0, s, a);
-  else if (which == kE4m3QuantInput) hipLaunchKernelGGL(e4m3::k_quant_input, grid, dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(e4m3::k_quant_level, grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(e4m3::k_quant_input, grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

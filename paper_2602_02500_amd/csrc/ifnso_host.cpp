@@ -62,7 +62,7 @@ struct ProbLayout {
   int32_t ksplit, kchunk;
   size_t off_gpart, off_gnrm, off_gcnt;
   // e4m3 compute
-  size_t off_q8, off_qpart, off_qamax, off_amaxp, off_qscale;
+  size_t off_q8, off_ql[2], off_qexp[2], off_qpart, off_qamax, off_qscale;
   int64_t ldq;
   int32_t nq, rq;
   size_t bytes;
@@ -70,7 +70,7 @@ struct ProbLayout {
 
 // e4m3 pre-pass chunks: about kQElems elements (whole storage rows) each
 constexpr int64_t kQElems = 1 << 16;
-constexpr int kQScaleFloats = 2 * (kMaxLevels + 1);
+constexpr int kQScaleFloats = 2;
 
 void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
   rq = (int32_t)std::max<int64_t>(1, kQElems / cols);
@@ -150,13 +150,18 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     }
   }
   if (e4m3) {
-    // one e4m3 buffer: A (h x ldq) for the Gram, then each level (hp x hp) for its squaring
+    // A (h x ldq) for the Gram; two level buffers (hp x hp) with their tile exponents, level l
+    // in slot l & 1 (a squaring reads one slot and writes the other)
     L.ldq = round_up(L.w, 16);
     e4m3_chunks(rows, cols, L.rq, L.nq);
-    L.off_q8 = take(std::max((size_t)L.h * L.ldq, hh));
+    L.off_q8 = take((size_t)L.h * L.ldq);
+    const size_t nt2 = (size_t)(L.hp / 256) * (L.hp / 256);
+    for (int i = 0; i < 2; i++) {
+      L.off_ql[i] = take(hh);
+      L.off_qexp[i] = take(nt2 * 4);
+    }
     L.off_qpart = take((size_t)L.nq * 8);
     L.off_qamax = take((size_t)L.nq * 4);
-    L.off_amaxp = take((size_t)levels * L.nt * L.nt * 4);
     L.off_qscale = take(kQScaleFloats * 4);
   }
   L.bytes = o;
@@ -201,7 +206,10 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
     d.ldq = L.ldq;
     d.q_part = (double *)(ws + L.off_qpart);
     d.q_amax = (float *)(ws + L.off_qamax);
-    d.amax_part = (float *)(ws + L.off_amaxp);
+    for (int i = 0; i < 2; i++) {
+      d.ql[i] = (uint8_t *)(ws + L.off_ql[i]);
+      d.qexp[i] = (int32_t *)(ws + L.off_qexp[i]);
+    }
     d.q_scale = (float *)(ws + L.off_qscale);
     d.nq = L.nq;
     d.rq = L.rq;
@@ -292,7 +300,7 @@ struct ifnso_plan_s {
   bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
   bool split_p = false;  // Gram basis: P carried into the product as a split bf16 pair
   bool fuse_agg = false;  // level layout with fixed coefficients: the last squaring forms P
-  int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, level)
+  int q_grid[2] = {1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
   double *d_fixed = nullptr;       // learned mode: fixed coefficient slots (fallback)
@@ -615,16 +623,15 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e4m3) {
     // workgroups per problem for the memory-bound passes: enough work for each, about 8 per
     // CU over the whole batch
-    int need[3] = {1, 1, 1};
+    int need[2] = {1, 1};
     for (const ProbLayout &L : p->lay) {
       need[0] = std::max(need[0], L.nq);
       const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64)
                                        : ((int64_t)L.h * L.ldq / 16 + kThreads - 1) / kThreads;
       need[1] = (int)std::max<int64_t>(need[1], units_in);
-      need[2] = (int)std::max<int64_t>(need[2], ((int64_t)L.hp * L.hp / 16 + kThreads - 1) / kThreads);
     }
     const int cap = std::max(1, (8 * p->cus + num_problems - 1) / num_problems);
-    for (int k = 0; k < 3; k++) p->q_grid[k] = std::max(1, std::min(need[k], cap));
+    for (int k = 0; k < 2; k++) p->q_grid[k] = std::max(1, std::min(need[k], cap));
   }
   p->grid[kStageGram] = grid_for(op, kStageGram, p->n_gram, p->cus);
   p->grid[kStageSquare] = grid_for(op, kStageSquare, p->n_square, p->cus);
@@ -813,7 +820,6 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     a.level = lvl;
     a.last = lvl == p->Jsq;
     if (p->e4m3) {
-      if ((e = launch_e4m3_pass(kE4m3QuantLevel, a, nprob, p->q_grid[2], s)) != hipSuccess) return e;
       a.ntasks = one ? ntiles_sym(kFastTS) : p->nf_square;
       if (!one) {
         a.tasks = p->d_tasks + p->offf_square;

@@ -26,6 +26,18 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+// e4m3 scale exponent of a block with maximum |value| amax: e = floor(log2(448 / amax)) (448 is
+// e4m3's largest finite value), so the scaled maximum lies in (224, 448] and the scaling by 2^e
+// is exact; clamped to [-63, 63] so that 2^(-2e) stays a normal float; 0 for an all-zero or
+// non-finite maximum.
+__device__ __forceinline__ int e4m3_scale_exp(float amax) {
+  if (!(amax > 0.f) || !isfinite(amax)) return 0;
+  int x;
+  const float f = frexpf(amax, &x);  // amax = f 2^x, f in [0.5, 1)
+  const int e = (2.f * f <= 1.75f ? 9 : 8) - x;
+  return e < -63 ? -63 : (e > 63 ? 63 : e);
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN

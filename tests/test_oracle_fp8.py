@@ -118,3 +118,45 @@ def test_model_error_is_e4m3_sized():
     eb = np.linalg.norm(F.ifnso_e4m3(M, exps, coeffs, quantize=lambda T: T) - want) / np.linalg.norm(want)
     assert eb < 1e-2
     assert 1e-3 < e8 < 0.15 and e8 > 2 * eb
+
+
+# ---------------------------------------------------------------------------------------------
+# per-tile quantisation of the stored levels
+# ---------------------------------------------------------------------------------------------
+def test_tiles_worked_example():
+    """Two 2 x 2 tiles (tile = 2) worked by hand. Left tile: maximum 1 -> scale 2^8; 76.8 and
+    25.6 and 12.8 round to the nearest e4m3 values 80, 26, 13 (four significant bits).
+    Right tile: maximum 100 -> scale 2^2 (448 / 100 = 4.48); 400 lies halfway between 384 and
+    416 and goes to the even significand 1.5 (384); 12, 8, 4 are exact."""
+    T = np.array([[1.0, 0.3, 100.0, 3.0], [0.1, 0.05, 2.0, 1.0]])
+    want = np.array([[1.0, 80 / 256, 96.0, 3.0], [26 / 256, 13 / 256, 2.0, 1.0]])
+    assert np.array_equal(F.e4m3_quantize_tiles(T, tile=2), want)
+
+
+def test_tiles_are_independent():
+    """Each tile is the per-tensor quantisation of that tile alone, edge tiles included, and
+    scaling one tile by a power of two scales only its own output, exactly."""
+    T = gen.normal_np(17, 0, 10 * 13).reshape(10, 13) * np.repeat(np.repeat(
+        np.array([[1.0, 50.0, 1e-3], [7.0, 0.2, 3e4], [1.0, 1.0, 1.0]]), 4, axis=0), 5, axis=1)[:10, :13]
+    Q = F.e4m3_quantize_tiles(T, tile=4)
+    for r0 in range(0, 10, 4):
+        for c0 in range(0, 13, 4):
+            assert np.array_equal(Q[r0:r0 + 4, c0:c0 + 4], F.e4m3_quantize(T[r0:r0 + 4, c0:c0 + 4])[0])
+    T2 = T.copy()
+    T2[4:8, 8:12] *= 2.0 ** 5
+    Q2 = F.e4m3_quantize_tiles(T2, tile=4)
+    mask = np.zeros(T.shape, bool)
+    mask[4:8, 8:12] = True
+    assert np.array_equal(Q2[mask], Q[mask] * 2.0 ** 5)
+    assert np.array_equal(Q2[~mask], Q[~mask])
+
+
+def test_one_tile_levels_match_the_per_tensor_rule():
+    """Levels of at most 256 rows are a single tile: the default model (per-tile levels) and the
+    per-tensor rule give the same result; beyond 256 rows they differ."""
+    exps, coeffs = configs.D2_EXPONENTS, configs.load_coeffs("gform_v1")[1]
+    per_tensor = lambda T: F.e4m3_quantize(T)[0]  # noqa: E731
+    M = gen.normal_np(18, 0, 200 * 300).reshape(200, 300)
+    assert np.array_equal(F.ifnso_e4m3(M, exps, coeffs), F.ifnso_e4m3(M, exps, coeffs, quantize_level=per_tensor))
+    M = gen.normal_np(19, 0, 300 * 320).reshape(300, 320) * np.linspace(0.2, 3.0, 300)[:, None]
+    assert not np.array_equal(F.ifnso_e4m3(M, exps, coeffs), F.ifnso_e4m3(M, exps, coeffs, quantize_level=per_tensor))
