@@ -53,14 +53,15 @@ typedef enum { IFNSO_F32 = 0, IFNSO_BF16 = 1 } ifnso_dtype;
 /* operand type of the matrix products (accumulation is always float32):
  *  F32   float32 operands on the FP32 matrix cores (the plain path; M must be F32)
  *  BF16  bfloat16 operands (M must be BF16)
- *  FP8_E4M3  OCP e4m3 operands (round to nearest even) for the Gram and the squarings, with
- *        power-of-two scales s = 2^floor(log2(448 / amax)) (exponent clamped to [-63, 63]):
- *        A takes one scale from its absolute maximum; each stored power is quantised where it
- *        is produced, every 256 x 256 tile with the scale of its own maximum, and the squaring
- *        that reads it applies the tiles' scales in the matrix instruction. ||A||_F comes from
- *        a float64 pre-pass over M; the stored powers, their weighted sum and the final
- *        product use bfloat16. Gram basis only; M must be BF16; problems need
- *        h * round_up(w, 16) < 2^31 and h <= 32512. */
+ *  FP8_E4M3  OCP e4m3 operands (round to nearest even) for the Gram and the squarings, each
+ *        with one power-of-two scale per tensor, s = 2^floor(log2(448 / amax)) (exponent
+ *        clamped to [-63, 63]): for A its absolute maximum; a stored power X X^T is quantised
+ *        where it is produced, with amax its largest magnitude before the bfloat16 rounding,
+ *        the largest row sum of squares of the quantised X (the product is positive
+ *        semi-definite), which a pass over X's e4m3 copy finds first. ||A||_F comes from a
+ *        float64 pre-pass over M; the stored powers, their weighted sum and the final product
+ *        use bfloat16. Gram basis only; M must be BF16; problems need h * round_up(w, 16) < 2^31
+ *        and h <= 32512. */
 typedef enum { IFNSO_COMPUTE_F32 = 0, IFNSO_COMPUTE_BF16 = 1, IFNSO_COMPUTE_FP8_E4M3 = 2 } ifnso_compute;
 
 typedef enum { IFNSO_BASIS_GRAM = 0, IFNSO_BASIS_COMPLEMENT = 1 } ifnso_basis;

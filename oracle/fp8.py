@@ -8,13 +8,14 @@ operands for the Gram and the squarings). This module states that variant exactl
   infinities; 0x7F / 0xFF are NaN; largest finite value 448 = 1.75 * 2^8; smallest normal
   2^-6; subnormals k * 2^-9. Rounding is to nearest, ties to even; magnitudes beyond 448
   saturate to 448.
-* Scale of an operand block T: s = 2^e, e = floor(log2(448 / max|T|)) clamped to
-  [-63, 63] (s = 1 for an all-zero or non-finite maximum); the block is e4m3(s T) / s.
-  The Gram's operand A takes one scale for the whole tensor. A stored level is quantised
-  where it is produced, tile by tile, before the whole level's maximum exists: each
-  256 x 256 tile (counted from the origin; edge tiles are partial) takes the scale of its
-  own maximum, and the squaring that reads it applies the tiles' scales exactly (powers of
-  two). A level of at most 256 rows is one tile, so there the two rules agree.
+* Per-tensor scale of an operand T from a maximum m: s = 2^e, e = floor(log2(448 / m))
+  clamped to [-63, 63] (s = 1 for m = 0 or non-finite); the operand is e4m3(s T) / s. For A,
+  m = max|A|. A stored power L = store(X X^T) (X = Q(A) for the Gram, X = Q(L_prev) for a
+  squaring; L_prev is symmetric) is positive semi-definite before its bfloat16 rounding, so
+  the largest magnitude of X X^T is its largest diagonal entry, the largest squared row norm
+  of X; m is that value, known from X alone, so the power is quantised where it is formed.
+  The rounding to bfloat16 can lift a stored value above m by at most 2^-8 relative, which
+  the scaled maximum (at most 448 (1 + 2^-8)) absorbs: it still rounds to 448.
 * Stored powers, their weighted sum P and the operands of the final product are bfloat16
   (8 significant bits, ties to even). Rounding is applied scale-free (on the significand),
   which is what the GPU's power-of-two rescaled levels see.
@@ -31,12 +32,11 @@ import numpy as np
 from .ifnso import _check_terms, orient
 
 __all__ = [
-    "E4M3_MAX", "E4M3_TILE", "e4m3_round", "e4m3_encode", "e4m3_decode", "e4m3_scale", "e4m3_quantize",
-    "e4m3_quantize_tiles", "bf16_round", "ifnso_e4m3",
+    "E4M3_MAX", "e4m3_round", "e4m3_encode", "e4m3_decode", "e4m3_scale", "e4m3_quantize",
+    "e4m3_quantize_with", "gram_row_max", "bf16_round", "ifnso_e4m3",
 ]
 
 E4M3_MAX = 448.0
-E4M3_TILE = 256  # side of the square tiles that carry their own scale in a stored level
 
 
 def e4m3_decode(codes) -> np.ndarray:
@@ -98,15 +98,18 @@ def e4m3_quantize(T):
     return e4m3_round(T * s) / s, s
 
 
-def e4m3_quantize_tiles(T, tile: int = E4M3_TILE) -> np.ndarray:
-    """e4m3(s_t T_t) / s_t for every tile x tile block T_t of T (from the origin; edge blocks
-    are partial), each with the scale of its own maximum (e4m3_scale)."""
+def e4m3_quantize_with(T, m: float):
+    """(e4m3(s T) / s, s) with the scale of the maximum m (e4m3_scale(m))."""
     T = np.asarray(T, dtype=np.float64)
-    out = np.empty_like(T)
-    for r0 in range(0, T.shape[0], tile):
-        for c0 in range(0, T.shape[1], tile):
-            out[r0:r0 + tile, c0:c0 + tile] = e4m3_quantize(T[r0:r0 + tile, c0:c0 + tile])[0]
-    return out
+    s = e4m3_scale(m)
+    return e4m3_round(T * s) / s, s
+
+
+def gram_row_max(X) -> float:
+    """max_i sum_k X[i][k]^2: the largest diagonal entry of X X^T, which for this positive
+    semi-definite product is also its largest magnitude."""
+    X = np.asarray(X, dtype=np.float64)
+    return float(np.max(np.sum(X * X, axis=1))) if X.size else 0.0
 
 
 def bf16_round(x) -> np.ndarray:
@@ -121,32 +124,34 @@ def _identity(x):
 
 
 def ifnso_e4m3(M, exponents: Sequence[int], coeffs: Sequence[float], norm: str = "frobenius",
-               quantize=None, store=None, quantize_level=None) -> np.ndarray:
+               quantize=None, store=None) -> np.ndarray:
     """Gram-basis IFNSO with e4m3 operands for the Gram and the squarings.
 
     In the order of the method (Sec. 1 transposition, Sec. 2.4 squaring, Algorithm 1):
       A  = M or M^T (h <= w);  s_A = ||A||_F from the unquantised A (float64)
-      L1 = store(Q(A) Q(A)^T)                    the Gram, unnormalised
-      L_{l+1} = store(QL(L_l) QL(L_l))           repeated squaring (L_l symmetric)
+      X_1 = Q(A, max|A|);            L1 = store(X_1 X_1^T)        the Gram, unnormalised
+      X_{l+1} = Q(L_l, rowmax(X_l)); L_{l+1} = store(X_{l+1} X_{l+1})   repeated squaring
       B^(2^(l-1)) = L_l / n^(2^l)                n = s_A (Frobenius), ||L1||_F^(1/2)
                                                  (Gram-Frobenius) or 1 (none)
       P  = store(sum_{e_k >= 1} c_k B^(e_k));  Y = (c_0 A + P A) / n
-    Q is the per-tensor e4m3 quantiser, QL the per-tile one (e4m3_quantize_tiles), `store` the
-    bfloat16 rounding of stored matrices. Any can be replaced (identity: the plain float64
-    polynomial); `quantize` alone replaces both quantisers. Returns Y in M's orientation."""
+    Q(T, m) is the per-tensor e4m3 quantiser with the scale of the maximum m (e4m3_quantize_with),
+    rowmax(X) = gram_row_max(X) the largest magnitude of X X^T (L_l = store(X_l X_l^T) with X_l
+    symmetric for l >= 2), `store` the bfloat16 rounding of stored matrices. Both can be replaced
+    (identity: the plain float64 polynomial); a replacement quantiser takes (T, m). Returns Y in
+    M's orientation."""
     e, c = _check_terms(exponents, coeffs)
-    Q = quantize if quantize is not None else (lambda T: e4m3_quantize(T)[0])
-    QL = quantize_level if quantize_level is not None else (quantize if quantize is not None else e4m3_quantize_tiles)
+    Q = quantize if quantize is not None else (lambda T, m: e4m3_quantize_with(T, m)[0])
     store = store if store is not None else bf16_round
     A, trans = orient(M)
     h = A.shape[0]
-    levels = {1: store(Q(A) @ Q(A).T)}
+    X = Q(A, float(np.max(np.abs(A))) if A.size else 0.0)
+    levels = {1: store(X @ X.T)}
     J = 0
     while (1 << J) < e[-1]:
         J += 1
     for l in range(1, J + 1):
-        Ql = QL(levels[l])
-        levels[l + 1] = store(Ql @ Ql)
+        X = Q(levels[l], gram_row_max(X))
+        levels[l + 1] = store(X @ X)
     if norm == "frobenius":
         n = math.sqrt(float(np.sum(A * A)))
     elif norm == "gram_frobenius":

@@ -50,13 +50,20 @@ struct ProbDev {
   uint8_t *q8;
   int64_t ldq;
   // e4m3 copies of the stored levels, written by the epilogue that produces each level: level
-  // l in ql[l & 1] (hp x hp, full symmetric), each 256 x 256 tile t scaled by its own power of
-  // two 2^e_t, with e_t in qexp[l & 1][tm * (hp / 256) + tn] (tile and mirror alike)
+  // l in ql[l & 1] (hp x hp, full symmetric), scaled by q_scale[2l]
   uint8_t *ql[2];
-  int32_t *qexp[2];
+  // [kMaxLevels + 1]: the largest sum of squares over a row of the e4m3 values (codes, in
+  // their scaled units) of the quantised A ([0]) and of level l ([l]); as float64 bit patterns,
+  // raised by atomic maxima (every value is >= 0), zeroed when A is quantised
+  uint64_t *qrmax;
+  // sums of squares of the codes of A's e4m3 copy per row and chunk, [i * qnch + c], written
+  // by the input quantisation (chunks: 4096 columns for wide inputs, 64 for tall ones)
+  double *qrow_in;
+  int32_t qnch;
   double *q_part;      // [nq] pre-pass sums of squares of M, chunks of rq storage rows
   float *q_amax;       // [nq] pre-pass max |M| per chunk
-  float *q_scale;      // [2]: the input's scale (a power of two) and max |value|
+  float *q_scale;      // [2 (kMaxLevels + 1)]: [2l] scale (a power of two) of the e4m3 copy of
+                       //   A (l = 0) or of level l, [2l + 1] the maximum it was chosen for
   int32_t nq, rq;
 };
 

@@ -140,7 +140,6 @@ __device__ __forceinline__ uint4 gld_u4(Q q) {
   const gu4 v = *(gptr<const gu4>)q;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ int gld_i32(const int32_t *p) { return *gbl(p); }
 template <typename Q>
 __device__ __forceinline__ float4 gld_f4(Q q) {
   const gf4 v = *(gptr<const gf4>)q;
@@ -299,17 +298,11 @@ __device__ __forceinline__ int kphys(int k, int seg) {
 // double-buffered: slice kk+1's are read from LDS while slice kk's MFMAs run.
 // PA / PB: K-segment maps (segments of `seg`, a multiple of the stage depth); K is then the
 // logical depth, and kvA / kvB bound the physical K of each operand (beyond it reads as zero).
-// QS (e4m3 levels): each 256 x 256 tile of the operands carries its own power-of-two scale;
-// qa / qb hold the exponents e of the tiles along the operand rows am0 / bn0 (K tile t at
-// [t]), and each MFMA multiplies its products by 2^-(e_a + e_b) (the instruction's E8M0 scale
-// operands, 127 meaning 1), so acc holds the unscaled product.
-template <bool F8, bool AMN = false, bool BMN = false, int PA = KMAP_ID, int PB = KMAP_ID, bool QS = false>
+template <bool F8, bool AMN = false, bool BMN = false, int PA = KMAP_ID, int PB = KMAP_ID>
 __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                               const Operand &B, int bn0, int K, bool want_norm, int seg = 0,
-                                              int kvA = 0, int kvB = 0, const int32_t *qa = nullptr,
-                                              const int32_t *qb = nullptr) {
+                                              int kvA = 0, int kvB = 0) {
   static_assert(!F8 || (!AMN && !BMN), "e4m3 operands are K-major");
-  static_assert(!QS || F8, "tile scales are an e4m3 option");
   const int KA = PA == KMAP_ID ? K : kvA, KB = PB == KMAP_ID ? K : kvB;
   constexpr int ES = F8 ? 1 : 2;
   constexpr int KST = 128 / ES;           // elements per stage
@@ -339,18 +332,8 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
     issue_krows<BM, ES, 0, RPT, AMN>(RA, lbase, A.w, ka, KA, ka + KST <= KA, A.ld_bytes, wave);
     issue_krows<BN, ES, 0, RPT, BMN>(RB, lbase + BM * 128, B.w, kb, KB, kb + KST <= KB, B.ld_bytes, wave);
   }
-  // QS: exponents of 64 K tiles at a time, one per lane (K tile t in lane t % 64)
-  int qea = 0, qeb = 0;
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
-    if constexpr (QS) {
-      constexpr int SPT = BM / KST;  // K steps per 256-wide tile
-      if (kt % (64 * SPT) == 0) {
-        const int t = kt / SPT + lane, nkt = (K + BM - 1) / BM;
-        qea = t < nkt ? gld_i32(qa + t) : 0;
-        qeb = t < nkt ? gld_i32(qb + t) : 0;
-      }
-    }
     wait_vmcnt<0>();
     __syncthreads();
     const char *As = smem + cur * STAGE_BYTES, *Bs = As + BM * 128;
@@ -390,24 +373,11 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
           const uint4 hi = *(const uint4 *)(Bs + lds_off(row, 4 * kk + 2 * lg + 1));
           fb[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
         }
-        if constexpr (QS) {
-          // E8M0 scale bytes 127 - e (all four bytes alike; the instruction takes the low one)
-          constexpr int SPT = BM / KST;
-          const int t = (kt / SPT) % 64;
-          const int sa = (127 - __builtin_amdgcn_readlane(qea, t)) * 0x01010101;
-          const int sb = (127 - __builtin_amdgcn_readlane(qeb, t)) * 0x01010101;
 #pragma unroll
-          for (int i = 0; i < FM; i++)
+        for (int i = 0; i < FM; i++)
 #pragma unroll
-            for (int j = 0; j < FN; j++)
-              acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, sa, 0, sb);
-        } else {
-#pragma unroll
-          for (int i = 0; i < FM; i++)
-#pragma unroll
-            for (int j = 0; j < FN; j++)
-              acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 0, 0, 0);
-        }
+          for (int j = 0; j < FN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 0, 0, 0);
       };
       slice(std::integral_constant<int, 0>{});
       slice(std::integral_constant<int, 1>{});
@@ -456,12 +426,11 @@ __device__ __forceinline__ double mainloop_kk(f32x16 (&acc)[FM][FN], char *smem,
 // array whose rows run along K) or, with AMN / BMN, MN-major (the array's rows run along K and
 // its columns am0.. are the tile's rows: Aop = X^T). F8: OCP e4m3 operands (1 byte, 128 per LDS
 // row and stage, K-major), MFMA 32x32x64.
-template <bool AMN, bool BMN, bool F8 = false, int PA = KMAP_ID, int PB = KMAP_ID, bool QS = false>
+template <bool AMN, bool BMN, bool F8 = false, int PA = KMAP_ID, int PB = KMAP_ID>
 __device__ __forceinline__ double mainloop(f32x16 (&acc)[FM][FN], char *smem, const Operand &A, int am0,
                                            const Operand &B, int bn0, int K, bool want_norm, int seg = 0,
-                                           int kvA = 0, int kvB = 0, const int32_t *qa = nullptr,
-                                           const int32_t *qb = nullptr) {
-  return mainloop_kk<F8, AMN, BMN, PA, PB, QS>(acc, smem, A, am0, B, bn0, K, want_norm, seg, kvA, kvB, qa, qb);
+                                           int kvA = 0, int kvB = 0) {
+  return mainloop_kk<F8, AMN, BMN, PA, PB>(acc, smem, A, am0, B, bn0, K, want_norm, seg, kvA, kvB);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -639,10 +608,13 @@ __device__ __forceinline__ uint32_t pack4_e4m3(float a, float b, float c, float 
   v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
   return (uint32_t)v;
 }
-// e4m3 bytes of qs times the four bfloat16 values packed in two words
+// e4m3 bytes of qs times the four bfloat16 values packed in two words, saturating at +-448 (the
+// scale keeps every value within 448 (1 + 2^-8), which rounds to 448 anyway; the clamp keeps a
+// value beyond it finite)
+__device__ __forceinline__ float sat448(float v) { return __builtin_amdgcn_fmed3f(v, -448.f, 448.f); }
 __device__ __forceinline__ uint32_t e4m3_of_bf16(uint32_t w0, uint32_t w1, float qs) {
-  return pack4_e4m3(qs * __uint_as_float(w0 << 16), qs * __uint_as_float(w0 & 0xffff0000u),
-                    qs * __uint_as_float(w1 << 16), qs * __uint_as_float(w1 & 0xffff0000u));
+  return pack4_e4m3(sat448(qs * __uint_as_float(w0 << 16)), sat448(qs * __uint_as_float(w0 & 0xffff0000u)),
+                    sat448(qs * __uint_as_float(w1 << 16)), sat448(qs * __uint_as_float(w1 & 0xffff0000u)));
 }
 
 // Writes the staged half tile (rows half*128..) as bfloat16 into dst (ld hp) at the tile and,
@@ -786,14 +758,16 @@ __device__ __forceinline__ void reg_partials(const f32x16 (&acc)[FM][FN], float 
 
 // Level-layout epilogue: level `out` = scale * acc is stored as bfloat16 (tile and mirror) at
 // lv + (out - 1) * lv_stride with the partials of its sum of squares (reg_partials) and trace
-// (diagonal tiles: from the staged tile). With AMAX (e4m3 plans) the tile is also stored as
-// e4m3 in ql[out & 1], scaled by the power of two of its own maximum (exponent in qexp[out & 1]
-// for the tile and its mirror); the maximum is taken before the bfloat16 rounding, which is
-// monotone, so its rounding is the maximum of the stored values.
+// (diagonal tiles: from the staged tile). With AMAX (e4m3 plans) the level is also stored as
+// e4m3 in ql[out & 1], with the power-of-two scale of `amax`, the largest magnitude of scale *
+// acc before rounding: acc is X X^T of a quantised operand X, positive semi-definite, so that
+// is scale times its largest diagonal entry, scale times the largest row sum of squares of X,
+// which the pass before the stage found. Rounding to bfloat16 can lift a stored value above
+// amax by 2^-8 relative at most; scaled it stays below 464 and rounds to e4m3's 448.
 
 template <bool AMAX>
 __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *smem, const ProbDev &P, int out,
-                                            const Task &task, float scale) {
+                                            const Task &task, float scale, float amax = 0.f) {
   const int m0 = task.tm * BM, n0 = task.tn * BN;
   const bool diag = task.tm == task.tn;
   const int64_t hp = P.hp;
@@ -801,11 +775,9 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
   double lv = 0.0, dg = 0.0, unused = 0.0;
   float mx = 0.f;
   reg_partials<AMAX>(acc, scale, diag, lv, mx);
-  // AMAX: the tile's own e4m3 scale 2^qe from the largest stored (bfloat16) value
-  int qe = 0;
-  if constexpr (AMAX) qe = e4m3_scale_exp(bf16_value(block_max(mx, (float *)smem)));
+  // AMAX: the level's e4m3 scale, from the largest magnitude of the level before its rounding
+  const float qs = AMAX ? ldexpf(1.f, e4m3_scale_exp(amax)) : 1.f;
   uint8_t *dst8 = AMAX ? P.ql[out & 1] : nullptr;
-  const float qs = AMAX ? __builtin_ldexpf(1.f, qe) : 1.f;
   float *ep = (float *)smem;
   for (int half = 0; half < 2; half++) {
     stage_half(acc, ep, half);
@@ -817,11 +789,10 @@ __device__ __forceinline__ void store_level(const f32x16 (&acc)[FM][FN], char *s
   block_sum3w(lv, dg, unused, (double *)smem);
   if (threadIdx.x == 0) {
     write_level_partials(P, out, task, lv, dg);
-    if constexpr (AMAX) {
-      const int nt2 = P.hp / BM;
-      gptr<int32_t> qx = gbl(P.qexp[out & 1]);
-      qx[task.tm * nt2 + task.tn] = qe;
-      qx[task.tn * nt2 + task.tm] = qe;
+    if (AMAX && task.tm == 0 && task.tn == 0) {  // every tile has the same scale; one records it
+      gptr<float> qsc = gbl(P.q_scale);
+      qsc[2 * out] = qs;
+      qsc[2 * out + 1] = amax;
     }
   }
   __syncthreads();
@@ -1113,12 +1084,13 @@ __global__ __launch_bounds__(NT, 1) void kf_square(const StageArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// e4m3 Gram and squaring. The Gram's operands are the e4m3 copy of A (q8, K contiguous, one
-// scale s): the float32 accumulator holds s^2 times the product, removed by the exact
-// power-of-two factor 1/s^2 in the epilogue. A squaring reads the e4m3 copy of its level that
-// the previous epilogue wrote tile by tile (ql, each tile with its own scale, undone by the
-// scaled MFMA). Every epilogue stores its level as in the bfloat16 level layout and, through
-// store_level<true>, the e4m3 copy of it for the next squaring.
+// e4m3 Gram and squaring: both operands are one e4m3 buffer with one scale s (the Gram: A's
+// copy q8, K contiguous; a squaring: its level's copy ql[level & 1], written by the epilogue
+// that produced the level); the float32 accumulator holds s^2 times the product, removed by the
+// exact power-of-two factor 1/s^2 in the epilogue. Every epilogue stores its level as in the
+// bfloat16 level layout and, through store_level<true>, its e4m3 copy for the next squaring,
+// with the scale of the largest row sum of squares of the operand codes (qrmax) times the
+// epilogue's factor.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ float inv_square(float s) { return 1.f / s / s; }
 
@@ -1134,11 +1106,12 @@ __global__ __launch_bounds__(NT, 1) void kf_gram8(const StageArgs a) {
     task.tn = uni(task.tn);
     const ProbDev &P = prob(a, task);
     const float dscale = inv_square(P.q_scale[0]);
+    const float amax = (float)(dscale * __longlong_as_double((long long)P.qrmax[0]));
     const int ldq = uni((int)P.ldq);
     const Operand op = make_operand(P.q8, (uint32_t)((int64_t)P.h * ldq), (uint32_t)ldq, P.h);
     f32x16 acc[FM][FN];
     mainloop<false, false, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, ldq, false);
-    store_level<true>(acc, smem, P, 1, task, dscale);
+    store_level<true>(acc, smem, P, 1, task, dscale, amax);
   }
 }
 
@@ -1150,7 +1123,7 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
   __shared__ float wl[kMaxLevels];
   const int level = a.level;
   int cur_p = -1;
-  float f_out = 1.f, w_last = 0.f;
+  float f_out = 1.f, w_last = 0.f, amax_next = 0.f;
   __shared__ int s_task;
   TaskCursor cursor(a, &s_task);
   int tg = 0;
@@ -1163,7 +1136,8 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
     if (task.p != cur_p) {
       cur_p = task.p;
       const double ls = lsum_load(P);
-      f_out = (float)pow2_inv_round(lsum(ls, level));
+      f_out = (float)pow2_inv_round(lsum(ls, level)) * inv_square(P.q_scale[2 * level]);
+      amax_next = (float)(f_out * __longlong_as_double((long long)P.qrmax[level]));
       if constexpr (FUSE) {  // c_l S_l of the stored levels 1..J, and c_{J+1} S_{J+1}
         double Sl = scalars(ls, a.norm).sg;
         for (int l = 1; l <= level + 1; l++) {
@@ -1179,13 +1153,10 @@ __global__ __launch_bounds__(NT, 1) void kf_square8(const StageArgs a) {
     }
     const int64_t hp = P.hp;
     const Operand op = make_operand(P.ql[level & 1], (uint32_t)(hp * hp), (uint32_t)hp, P.hp);
-    const int32_t *qx = P.qexp[level & 1];
-    const int nt2 = uni(P.hp / BM);
     f32x16 acc[FM][FN];
-    mainloop<false, false, true, KMAP_ID, KMAP_ID, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, uni(P.h),
-                                                         false, 0, 0, 0, qx + task.tm * nt2, qx + task.tn * nt2);
+    mainloop<false, false, true>(acc, smem, op, task.tm * BM, op, task.tn * BN, uni(P.h), false);
     if constexpr (FUSE) store_p_fused<true>(acc, smem, wl, P, level, task, w_last, f_out);
-    else store_level<true>(acc, smem, P, level + 1, task, f_out);
+    else store_level<true>(acc, smem, P, level + 1, task, f_out, amax_next);
   }
 }
 

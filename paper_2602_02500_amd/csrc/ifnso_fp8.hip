@@ -1,7 +1,8 @@
 // Memory-bound passes of the e4m3 compute mode: per-tensor amax and sum of squares of the
-// input, and quantisation of A (transposed for tall inputs) to OCP e4m3 with a power-of-two
-// scale. The e4m3 Gram and squaring GEMMs live with the other 256 x 256 kernels; they consume
-// what these passes write, and their epilogues quantise each stored level tile by tile.
+// input, quantisation of A (transposed for tall inputs) to OCP e4m3 with a power-of-two scale,
+// and the largest row sum of squares of a quantised operand, from which the scale of the next
+// power follows. The e4m3 Gram and squaring GEMMs live with the other 256 x 256 kernels; their
+// epilogues quantise each power as they store it.
 //
 // Scale rule: s = 2^e with e = floor(log2(448 / amax)) (448 is e4m3's largest finite value),
 // so the scaled maximum lies in (224, 448] and the scaling itself is exact; e is clamped to
@@ -35,6 +36,13 @@ __device__ __forceinline__ uint4 pack16(const float (&x)[16], float s) {
   return make_uint4(pack4(s * x[0], s * x[1], s * x[2], s * x[3]), pack4(s * x[4], s * x[5], s * x[6], s * x[7]),
                     pack4(s * x[8], s * x[9], s * x[10], s * x[11]),
                     pack4(s * x[12], s * x[13], s * x[14], s * x[15]));
+}
+
+// sum of squares of the four e4m3 values in a word (exact: each square has 8 significant bits)
+__device__ __forceinline__ double sumsq_e4m3(uint32_t w) {
+  const double x0 = __builtin_amdgcn_cvt_f32_fp8((int)w, 0), x1 = __builtin_amdgcn_cvt_f32_fp8((int)w, 1);
+  const double x2 = __builtin_amdgcn_cvt_f32_fp8((int)w, 2), x3 = __builtin_amdgcn_cvt_f32_fp8((int)w, 3);
+  return fma(x3, x3, fma(x2, x2, fma(x1, x1, x0 * x0)));
 }
 
 __device__ __forceinline__ void unpack8(const uint4 &v, float *x) {
@@ -114,6 +122,7 @@ constexpr int kTile = 64;
 
 __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
   __shared__ float fscr[4];
+  __shared__ double dscr[12];
   __shared__ uint16_t tile[kTile][kTile + 2];
   const ProbDev &P = problem(a);
   float mx = 0.f;
@@ -130,28 +139,43 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
       }
     }
     for (int i = 1 + threadIdx.x; i < P.nt; i += kThreads) P.norm_part[i] = 0.0;
+    if (P.qrmax)  // the row maxima of this call start from zero
+      for (int i = threadIdx.x; i <= kMaxLevels; i += kThreads) P.qrmax[i] = 0ull;
   }
   const uint16_t *M = (const uint16_t *)P.M;
   const int h = P.h, w = P.w;
   const int64_t ldq = P.ldq;
   const int gpr = (int)(ldq / 16);  // 16-element groups per row of q8
   if (!P.trans) {
+    // one workgroup per chunk of kThreads 16-element groups of a row (the chunk's sum of
+    // squares of the codes goes to qrow_in when the plan keeps it)
     const bool vec = P.vecM && (w % 8) == 0;
-    const int64_t ng = (int64_t)h * gpr;
-    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < ng; g += (int64_t)gridDim.x * kThreads) {
-      const int i = (int)(g / gpr), k = (int)(g % gpr) * 16;
-      const uint16_t *src = M + (int64_t)i * P.ldm + k;
-      float x[16];
-      if (vec) {
-        if (k < w) unpack8(*(const uint4 *)src, x);
-        else for (int j = 0; j < 8; j++) x[j] = 0.f;
-        if (k + 8 < w) unpack8(*(const uint4 *)(src + 8), x + 8);
-        else for (int j = 8; j < 16; j++) x[j] = 0.f;
-      } else {
+    const int nch = (gpr + kThreads - 1) / kThreads;
+    for (int64_t u = blockIdx.x; u < (int64_t)h * nch; u += gridDim.x) {
+      const int i = (int)(u / nch), c = (int)(u % nch);
+      const int g = c * kThreads + threadIdx.x, k = g * 16;
+      double ss = 0.0;
+      if (g < gpr) {
+        const uint16_t *src = M + (int64_t)i * P.ldm + k;
+        float x[16];
+        if (vec) {
+          if (k < w) unpack8(*(const uint4 *)src, x);
+          else for (int j = 0; j < 8; j++) x[j] = 0.f;
+          if (k + 8 < w) unpack8(*(const uint4 *)(src + 8), x + 8);
+          else for (int j = 8; j < 16; j++) x[j] = 0.f;
+        } else {
 #pragma unroll
-        for (int j = 0; j < 16; j++) x[j] = k + j < w ? bf16_to_f32(src[j]) : 0.f;
+          for (int j = 0; j < 16; j++) x[j] = k + j < w ? bf16_to_f32(src[j]) : 0.f;
+        }
+        const uint4 q = pack16(x, s);
+        *(uint4 *)(P.q8 + (int64_t)i * ldq + k) = q;
+        ss = sumsq_e4m3(q.x) + sumsq_e4m3(q.y) + sumsq_e4m3(q.z) + sumsq_e4m3(q.w);
       }
-      *(uint4 *)(P.q8 + (int64_t)i * ldq + k) = pack16(x, s);
+      if (P.qrow_in) {
+        double u0 = 0.0, u1 = 0.0;
+        block_sum3(ss, u0, u1, dscr);
+        if (threadIdx.x == 0) P.qrow_in[(int64_t)i * P.qnch + c] = ss;
+      }
     }
     return;
   }
@@ -179,15 +203,71 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
     }
     __syncthreads();
     {
+      // row i0 + ii, 16 of the tile's 64 columns per thread; the four threads of a row (a lane
+      // quad) add their sums of squares of the codes for qrow_in
       const int ii = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 16;
+      double ss = 0.0;
       if (i0 + ii < h && k0 + kq < ldq) {
         float x[16];
 #pragma unroll
         for (int j = 0; j < 16; j++) x[j] = bf16_to_f32(tile[kq + j][ii]);
-        *(uint4 *)(P.q8 + (int64_t)(i0 + ii) * ldq + k0 + kq) = pack16(x, s);
+        const uint4 q = pack16(x, s);
+        *(uint4 *)(P.q8 + (int64_t)(i0 + ii) * ldq + k0 + kq) = q;
+        ss = sumsq_e4m3(q.x) + sumsq_e4m3(q.y) + sumsq_e4m3(q.z) + sumsq_e4m3(q.w);
       }
+      ss += __shfl_xor(ss, 1, 64);
+      ss += __shfl_xor(ss, 2, 64);
+      if (P.qrow_in && (threadIdx.x & 3) == 0 && i0 + ii < h) P.qrow_in[(int64_t)(i0 + ii) * P.qnch + k0 / kTile] = ss;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// largest row sum of squares of an e4m3 operand (its codes): of level a.level's copy (hp x hp;
+// a wave takes one row at a time, 16 bytes per lane, with float64 partials summed over the wave
+// in a fixed order) or, for level 0, of A (from the chunk sums the quantisation wrote); the
+// workgroup's maximum goes into qrmax[a.level] as an atomic maximum of the float64 bit pattern
+// (every value is >= 0, so the patterns order as the values and the result does not depend on
+// the order of the updates).
+// ---------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_row_max(const StageArgs a) {
+  __shared__ double wmax[kThreads / 64];
+  const ProbDev &P = problem(a);
+  const int l = a.level;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mx = 0.0;
+  if (l == 0) {  // A: the rows' chunk sums from the input quantisation, added in chunk order
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.h; i += gridDim.x * kThreads) {
+      double s = 0.0;
+      for (int c = 0; c < P.qnch; c++) s += P.qrow_in[(int64_t)i * P.qnch + c];
+      mx = fmax(mx, s);
+    }
+  }
+  const uint8_t *q = P.ql[l & 1];
+  const int rows = l == 0 ? 0 : P.hp;
+  const int64_t ld = P.hp;  // a multiple of 16 bytes
+  for (int r0 = blockIdx.x * kQRowsPerBlock; r0 < rows; r0 += gridDim.x * kQRowsPerBlock) {
+    const int r1 = min(rows, r0 + kQRowsPerBlock);
+    for (int r = r0 + wave; r < r1; r += kThreads / 64) {
+      double s = 0.0;
+      for (int64_t k = (int64_t)lane * 16; k < ld; k += 64 * 16) {
+        const uint4 v = *(const uint4 *)(q + (int64_t)r * ld + k);
+        s += sumsq_e4m3(v.x) + sumsq_e4m3(v.y) + sumsq_e4m3(v.z) + sumsq_e4m3(v.w);
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      mx = fmax(mx, s);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));  // level 0: per-thread rows
+  if (lane == 0) wmax[wave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; w++) mx = fmax(mx, wmax[w]);
+    atomicMax((unsigned long long *)(P.qrmax + l), (unsigned long long)__double_as_longlong(mx));
   }
 }
 
@@ -206,7 +286,8 @@ hipError_t launch_e4m3_pass(int which, const StageArgs &a, int nprob, int per_pr
   if (nprob <= 0) return hipSuccess;
   const dim3 grid(per_problem, nprob);
   if (which == kE4m3Prepass) hipLaunchKernelGGL(e4m3::k_prepass, grid, dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(e4m3::k_quant_input, grid, dim3(kThreads), 0, s, a);
+  else if (which == kE4m3QuantInput) hipLaunchKernelGGL(e4m3::k_quant_input, grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(e4m3::k_row_max, grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -62,7 +62,8 @@ struct ProbLayout {
   int32_t ksplit, kchunk;
   size_t off_gpart, off_gnrm, off_gcnt;
   // e4m3 compute
-  size_t off_q8, off_ql[2], off_qexp[2], off_qpart, off_qamax, off_qscale;
+  size_t off_q8, off_ql[2], off_qrmax, off_qrow_in, off_qpart, off_qamax, off_qscale;
+  int32_t qnch;
   int64_t ldq;
   int32_t nq, rq;
   size_t bytes;
@@ -70,7 +71,7 @@ struct ProbLayout {
 
 // e4m3 pre-pass chunks: about kQElems elements (whole storage rows) each
 constexpr int64_t kQElems = 1 << 16;
-constexpr int kQScaleFloats = 2;
+constexpr int kQScaleFloats = 2 * (kMaxLevels + 1);
 
 void e4m3_chunks(int64_t rows, int64_t cols, int32_t &rq, int32_t &nq) {
   rq = (int32_t)std::max<int64_t>(1, kQElems / cols);
@@ -150,16 +151,15 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     }
   }
   if (e4m3) {
-    // A (h x ldq) for the Gram; two level buffers (hp x hp) with their tile exponents, level l
-    // in slot l & 1 (a squaring reads one slot and writes the other)
+    // A (h x ldq) for the Gram; two level buffers (hp x hp), level l in slot l & 1 (a squaring
+    // reads one slot and writes the other)
     L.ldq = round_up(L.w, 16);
     e4m3_chunks(rows, cols, L.rq, L.nq);
     L.off_q8 = take((size_t)L.h * L.ldq);
-    const size_t nt2 = (size_t)(L.hp / 256) * (L.hp / 256);
-    for (int i = 0; i < 2; i++) {
-      L.off_ql[i] = take(hh);
-      L.off_qexp[i] = take(nt2 * 4);
-    }
+    for (int i = 0; i < 2; i++) L.off_ql[i] = take(hh);
+    L.off_qrmax = take((size_t)(kMaxLevels + 1) * 8);
+    L.qnch = (int32_t)(L.trans ? (L.ldq + 63) / 64 : (L.ldq / 16 + kThreads - 1) / kThreads);
+    L.off_qrow_in = take((size_t)L.h * L.qnch * 8);
     L.off_qpart = take((size_t)L.nq * 8);
     L.off_qamax = take((size_t)L.nq * 4);
     L.off_qscale = take(kQScaleFloats * 4);
@@ -206,10 +206,10 @@ void fill_dev(ProbDev &d, const ProbLayout &L, char *ws, const void *M, int64_t 
     d.ldq = L.ldq;
     d.q_part = (double *)(ws + L.off_qpart);
     d.q_amax = (float *)(ws + L.off_qamax);
-    for (int i = 0; i < 2; i++) {
-      d.ql[i] = (uint8_t *)(ws + L.off_ql[i]);
-      d.qexp[i] = (int32_t *)(ws + L.off_qexp[i]);
-    }
+    for (int i = 0; i < 2; i++) d.ql[i] = (uint8_t *)(ws + L.off_ql[i]);
+    d.qrmax = (uint64_t *)(ws + L.off_qrmax);
+    d.qrow_in = (double *)(ws + L.off_qrow_in);
+    d.qnch = L.qnch;
     d.q_scale = (float *)(ws + L.off_qscale);
     d.nq = L.nq;
     d.rq = L.rq;
@@ -300,7 +300,7 @@ struct ifnso_plan_s {
   bool split = false;  // complement basis: squaring and product operands as split bf16 pairs
   bool split_p = false;  // Gram basis: P carried into the product as a split bf16 pair
   bool fuse_agg = false;  // level layout with fixed coefficients: the last squaring forms P
-  int q_grid[2] = {1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input)
+  int q_grid[3] = {1, 1, 1};  // e4m3 passes: workgroups per problem (pre-pass, input, row maxima)
   int Jsq = 0;        // squaring launches: J, or J + 2 in learned mode (levels for m_6, m_7)
   float *d_params = nullptr;       // learned mode: network parameters
   double *d_fixed = nullptr;       // learned mode: fixed coefficient slots (fallback)
@@ -623,15 +623,15 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
   if (e4m3) {
     // workgroups per problem for the memory-bound passes: enough work for each, about 8 per
     // CU over the whole batch
-    int need[2] = {1, 1};
+    int need[3] = {1, 1, 1};
     for (const ProbLayout &L : p->lay) {
       need[0] = std::max(need[0], L.nq);
-      const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64)
-                                       : ((int64_t)L.h * L.ldq / 16 + kThreads - 1) / kThreads;
+      const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64) : (int64_t)L.h * L.qnch;
       need[1] = (int)std::max<int64_t>(need[1], units_in);
+      need[2] = std::max(need[2], (L.hp + kQRowsPerBlock - 1) / kQRowsPerBlock);  // row-maxima blocks
     }
     const int cap = std::max(1, (8 * p->cus + num_problems - 1) / num_problems);
-    for (int k = 0; k < 2; k++) p->q_grid[k] = std::max(1, std::min(need[k], cap));
+    for (int k = 0; k < 3; k++) p->q_grid[k] = std::max(1, std::min(need[k], cap));
   }
   p->grid[kStageGram] = grid_for(op, kStageGram, p->n_gram, p->cus);
   p->grid[kStageSquare] = grid_for(op, kStageSquare, p->n_square, p->cus);
@@ -765,6 +765,8 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   if (p->e4m3) {
     if ((e = launch_e4m3_pass(kE4m3Prepass, a, nprob, p->q_grid[0], s)) != hipSuccess) return e;
     if ((e = launch_e4m3_pass(kE4m3QuantInput, a, nprob, p->q_grid[1], s)) != hipSuccess) return e;
+    a.level = 0;  // the largest row sum of Q(A): the scale of the Gram's stored power
+    if ((e = launch_e4m3_pass(kE4m3RowMax, a, nprob, p->q_grid[2], s)) != hipSuccess) return e;
   }
   // Gram
   for (int t = 0; t < 2; t++) {
@@ -815,6 +817,16 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
   // the 256-tile kernels read per-problem totals of the partials (ProbDev::lvl_sum)
   const bool sums = fast || p->e4m3;
   if (sums && (e = launch_level_sums(a, nprob, 1, s)) != hipSuccess) return e;
+  // e4m3: the largest row sum of a stored power's e4m3 copy gives the scale of the next one
+  auto row_max = [&](int level) -> hipError_t {
+    if (!p->e4m3 || level > p->Jsq) return hipSuccess;
+    const int l0 = a.level;
+    a.level = level;
+    const hipError_t r = launch_e4m3_pass(kE4m3RowMax, a, nprob, p->q_grid[2], s);
+    a.level = l0;
+    return r;
+  };
+  if ((e = row_max(1)) != hipSuccess) return e;
   for (int lvl = 1; lvl <= p->Jsq; lvl++) {
     if ((e = mark()) != hipSuccess) return e;
     a.level = lvl;
@@ -849,6 +861,7 @@ static hipError_t enqueue_plan(const ifnso_plan_s *p, const ProbDev *table, cons
     if (e != hipSuccess) return e;
     // level lvl + 1 is read by the next squaring and by the aggregate stage, never after the last
     if (sums && lvl < p->Jsq && (e = launch_level_sums(a, nprob, lvl + 1, s)) != hipSuccess) return e;
+    if (lvl < p->Jsq && (e = row_max(lvl + 1)) != hipSuccess) return e;
   }
   a.level = 0;
   a.last = 0;

@@ -37,7 +37,9 @@ hipError_t launch_level_sums(const StageArgs &a, int nprob, int level, hipStream
 constexpr int kAggChunk = 1 << 17;  // elements per aggregate task
 
 // e4m3 compute (ifnso_fp8.hip): memory-bound passes, one grid row per problem
-enum E4m3Pass : int { kE4m3Prepass = 0, kE4m3QuantInput = 1 };
+enum E4m3Pass : int { kE4m3Prepass = 0, kE4m3QuantInput = 1, kE4m3RowMax = 2 };
+// rows of an e4m3 operand that one workgroup of the row-maxima pass covers
+constexpr int kQRowsPerBlock = 64;
 hipError_t launch_e4m3_pass(int which, const StageArgs &a, int nprob, int per_problem, hipStream_t s);
 // device out[3] = {||A||_F^2, max |A|, scale} of a single-problem pass
 hipError_t launch_e4m3_export(const ProbDev &P, double *out, hipStream_t s);

@@ -93,7 +93,7 @@ def test_model_reduces_to_float64_polynomial(shape, norm):
     """With identity quantiser and storage the e4m3 model is the plain polynomial."""
     M = gen.normal_np(14, 0, shape[0] * shape[1]).reshape(shape) * 0.3
     exps, coeffs = configs.D2_EXPONENTS, configs.load_coeffs("gform_v1")[1]
-    ident = lambda T: np.asarray(T, dtype=np.float64)
+    ident = lambda T, m=None: np.asarray(T, dtype=np.float64)  # noqa: E731
     got = F.ifnso_e4m3(M, exps, coeffs, norm=norm, quantize=ident, store=ident)
     want = O.ifnso(M, exps, coeffs, basis="gram", norm=norm)
     assert np.linalg.norm(got - want) <= 1e-11 * max(1.0, np.linalg.norm(want))
@@ -115,48 +115,46 @@ def test_model_error_is_e4m3_sized():
     exps, coeffs = configs.D2_EXPONENTS, configs.load_coeffs("gform_v1")[1]
     want = O.ifnso(M, exps, coeffs)
     e8 = np.linalg.norm(F.ifnso_e4m3(M, exps, coeffs) - want) / np.linalg.norm(want)
-    eb = np.linalg.norm(F.ifnso_e4m3(M, exps, coeffs, quantize=lambda T: T) - want) / np.linalg.norm(want)
+    eb = np.linalg.norm(F.ifnso_e4m3(M, exps, coeffs, quantize=lambda T, m: T) - want) / np.linalg.norm(want)
     assert eb < 1e-2
     assert 1e-3 < e8 < 0.15 and e8 > 2 * eb
 
 
 # ---------------------------------------------------------------------------------------------
-# per-tile quantisation of the stored levels
+# the scale of a stored power: the largest magnitude of the product before its rounding
 # ---------------------------------------------------------------------------------------------
-def test_tiles_worked_example():
-    """Two 2 x 2 tiles (tile = 2) worked by hand. Left tile: maximum 1 -> scale 2^8; 76.8 and
-    25.6 and 12.8 round to the nearest e4m3 values 80, 26, 13 (four significant bits).
-    Right tile: maximum 100 -> scale 2^2 (448 / 100 = 4.48); 400 lies halfway between 384 and
-    416 and goes to the even significand 1.5 (384); 12, 8, 4 are exact."""
-    T = np.array([[1.0, 0.3, 100.0, 3.0], [0.1, 0.05, 2.0, 1.0]])
-    want = np.array([[1.0, 80 / 256, 96.0, 3.0], [26 / 256, 13 / 256, 2.0, 1.0]])
-    assert np.array_equal(F.e4m3_quantize_tiles(T, tile=2), want)
+def test_gram_row_max_is_the_largest_magnitude():
+    """For X X^T (any X) and X X (symmetric X) the largest magnitude is the largest squared row
+    norm of X (brute force over all entries)."""
+    X = gen.normal_np(20, 0, 37 * 53).reshape(37, 53)
+    assert np.isclose(F.gram_row_max(X), np.max(np.abs(X @ X.T)), rtol=1e-14, atol=0)
+    S = X[:, :37] + X[:, :37].T
+    assert np.isclose(F.gram_row_max(S), np.max(np.abs(S @ S)), rtol=1e-14, atol=0)
+    assert F.gram_row_max(np.zeros((3, 4))) == 0.0
 
 
-def test_tiles_are_independent():
-    """Each tile is the per-tensor quantisation of that tile alone, edge tiles included, and
-    scaling one tile by a power of two scales only its own output, exactly."""
-    T = gen.normal_np(17, 0, 10 * 13).reshape(10, 13) * np.repeat(np.repeat(
-        np.array([[1.0, 50.0, 1e-3], [7.0, 0.2, 3e4], [1.0, 1.0, 1.0]]), 4, axis=0), 5, axis=1)[:10, :13]
-    Q = F.e4m3_quantize_tiles(T, tile=4)
-    for r0 in range(0, 10, 4):
-        for c0 in range(0, 13, 4):
-            assert np.array_equal(Q[r0:r0 + 4, c0:c0 + 4], F.e4m3_quantize(T[r0:r0 + 4, c0:c0 + 4])[0])
-    T2 = T.copy()
-    T2[4:8, 8:12] *= 2.0 ** 5
-    Q2 = F.e4m3_quantize_tiles(T2, tile=4)
-    mask = np.zeros(T.shape, bool)
-    mask[4:8, 8:12] = True
-    assert np.array_equal(Q2[mask], Q[mask] * 2.0 ** 5)
-    assert np.array_equal(Q2[~mask], Q[~mask])
+def test_power_scale_worked_example():
+    """X = [1, 1/2, 1/2, 1/2, 2^-5]: X X^T = 1.75 + 2^-10 exactly. Its bfloat16 value is 1.75
+    (8 significant bits), whose scale would be 448 / 1.75 = 2^8; the product before rounding
+    gives 448 / 1.7509765625 < 2^8, so 2^7. The model takes the latter: the quantiser of the
+    first squaring is called with that maximum."""
+    X = np.array([[1.0, 0.5, 0.5, 0.5, 2.0 ** -5]])
+    assert F.gram_row_max(X) == 1.75 + 2.0 ** -10
+    assert F.bf16_round(X @ X.T)[0, 0] == 1.75
+    assert F.e4m3_scale(F.gram_row_max(X)) == 2.0 ** 7
+    assert F.e4m3_scale(1.75) == 2.0 ** 8
+    seen = []
+
+    def q(T, m):
+        seen.append(m)
+        return F.e4m3_quantize_with(T, m)[0]
+
+    F.ifnso_e4m3(X, (0, 1, 2), (0.5, 0.3, 0.2), norm="none", quantize=q)
+    assert seen == [1.0, 1.75 + 2.0 ** -10]  # max|A|, then the Gram's largest row norm
 
 
-def test_one_tile_levels_match_the_per_tensor_rule():
-    """Levels of at most 256 rows are a single tile: the default model (per-tile levels) and the
-    per-tensor rule give the same result; beyond 256 rows they differ."""
-    exps, coeffs = configs.D2_EXPONENTS, configs.load_coeffs("gform_v1")[1]
-    per_tensor = lambda T: F.e4m3_quantize(T)[0]  # noqa: E731
-    M = gen.normal_np(18, 0, 200 * 300).reshape(200, 300)
-    assert np.array_equal(F.ifnso_e4m3(M, exps, coeffs), F.ifnso_e4m3(M, exps, coeffs, quantize_level=per_tensor))
-    M = gen.normal_np(19, 0, 300 * 320).reshape(300, 320) * np.linspace(0.2, 3.0, 300)[:, None]
-    assert not np.array_equal(F.ifnso_e4m3(M, exps, coeffs), F.ifnso_e4m3(M, exps, coeffs, quantize_level=per_tensor))
+def test_quantize_with_matches_per_tensor_rule():
+    T = gen.normal_np(21, 0, 30 * 40).reshape(30, 40)
+    a, s = F.e4m3_quantize(T)
+    b, t = F.e4m3_quantize_with(T, float(np.max(np.abs(T))))
+    assert s == t and np.array_equal(a, b)
