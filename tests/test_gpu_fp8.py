@@ -220,3 +220,25 @@ def test_error_against_bf16_mode(tdev):
     assert res["fp8"][0] < 0.25
     assert abs(res["fp8"][1] - res["bf16"][1]) < 0.1
     assert ifn  # the binding is loaded
+
+
+def test_power_scale_from_exact_maximum(tdev):
+    """The scale of a stored power comes from its largest magnitude before the bf16 rounding.
+    Worked in exact arithmetic (every product, sum and rounding below is exact on both sides):
+    A = [Z | I] (2 x 8), Z rows [1, 1, 1/2, 1/2, 2^-5, 2^-5] and [13 2^-16, 0, ...]. Then
+    L1 = A A^T has L1[0][0] = 3.5 + 2^-9 (stored as 3.5) and L1[0][1] = 13 2^-16. The scale
+    of L1 is 2^6 (448 / (3.5 + 2^-9) < 2^7); the one of its stored maximum would be 2^7. Under
+    2^6, 13 2^-16 scales to 6.5 e4m3 quanta (2^-9) and rounds to 6; under 2^7 it stays exact. So
+    the power read off Y's identity block, L2[0][1], is 13.5 2^-14 (it would be 14.625 2^-14)."""
+    torch, dev = tdev
+    Z = np.zeros((2, 6))
+    Z[0] = [1.0, 1.0, 0.5, 0.5, 2.0 ** -5, 2.0 ** -5]
+    Z[1, 0] = 13 * 2.0 ** -16
+    A = np.concatenate([Z, np.eye(2)], axis=1)
+    Mt, vals = _bf16_dev(torch, dev, A)
+    assert np.array_equal(vals, A)
+    exps, c = (0, 2), (0.0, 1.0)
+    (Y,), _ = _run(torch, dev, [vals], [Mt], exps, c, norm="none")
+    Ym = F.ifnso_e4m3(vals, exps, c, norm="none")
+    assert Ym[0, 7] == 13.5 * 2.0 ** -14 and Ym[0, 6] == 12.25 and Ym[1, 7] == 1.0
+    assert np.array_equal(Y[:, 6:], Ym[:, 6:]), (Y[:, 6:], Ym[:, 6:])

@@ -158,3 +158,19 @@ def test_quantize_with_matches_per_tensor_rule():
     a, s = F.e4m3_quantize(T)
     b, t = F.e4m3_quantize_with(T, float(np.max(np.abs(T))))
     assert s == t and np.array_equal(a, b)
+
+
+def test_power_scale_worked_example_through_the_model():
+    """The same rule end to end (the GPU test of it uses this input): A = [Z | I] with Z rows
+    [1, 1, 1/2, 1/2, 2^-5, 2^-5] and [13 2^-16, 0, ...]; L1[0][0] = 3.5 + 2^-9 gives the scale
+    2^6, under which L1[0][1] = 13 2^-16 is 6.5 e4m3 quanta and rounds to 6, so with the single
+    power B^2 the identity block of Y holds L2[0][1] = (3.5 + 1) 3 2^-14 = 13.5 2^-14; the scale
+    of the stored maximum 3.5 (2^7) would keep 13 2^-16 and give 4.5 13 2^-16 = 14.625 2^-14."""
+    Z = np.zeros((2, 6))
+    Z[0] = [1.0, 1.0, 0.5, 0.5, 2.0 ** -5, 2.0 ** -5]
+    Z[1, 0] = 13 * 2.0 ** -16
+    A = np.concatenate([Z, np.eye(2)], axis=1)
+    Y = F.ifnso_e4m3(A, (0, 2), (0.0, 1.0), norm="none")
+    assert Y[0, 7] == 13.5 * 2.0 ** -14 and Y[0, 6] == 12.25 and Y[1, 7] == 1.0
+    stored_max_rule = F.ifnso_e4m3(A, (0, 2), (0.0, 1.0), norm="none", quantize=lambda T, m: F.e4m3_quantize(T)[0])
+    assert stored_max_rule[0, 7] == 14.625 * 2.0 ** -14
