@@ -133,8 +133,12 @@ __device__ __forceinline__ void store4<uint16_t>(uint16_t *p, float4 v) {
 // ---------------------------------------------------------------------------------------------
 // Gram
 // ---------------------------------------------------------------------------------------------
+// float32 (the Gram, squaring and product kernels): two workgroups per CU. The float32 matrix
+// instruction is slow enough that one workgroup's loads and epilogue hide behind the other's
+// MFMAs; the register cap makes the compiler spill (the Gram also inside its K loops), which
+// costs less than the overlap gains.
 template <typename T, int TS>
-__global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 2 : 1) void k_gram(const StageArgs a) {
   using TL = Tile<T, TS, TS>;
   __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
   __shared__ int s_last;
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const StageArgs a) {
 // squaring: level -> level + 1
 // ---------------------------------------------------------------------------------------------
 template <typename T, int TS>
-__global__ __launch_bounds__(kThreads) void k_square(const StageArgs a) {
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 2 : 1) void k_square(const StageArgs a) {
   using TL = Tile<T, TS, TS>;
   __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
   const int level = a.level;
@@ -396,7 +400,7 @@ __device__ __forceinline__ float load_el(const void *p, int64_t idx) {
 }
 
 template <typename T, int TS>
-__global__ __launch_bounds__(kThreads) void k_product(const StageArgs a, const int out_bf16) {
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 2 : 1) void k_product(const StageArgs a, const int out_bf16) {
   using TL = Tile<T, TS, TS>;
   __shared__ __attribute__((aligned(16))) char smem[TL::LDS_BYTES];
   int cur_p = -1;
