@@ -867,6 +867,55 @@ __global__ __launch_bounds__(NT, 1) void kf_gram(const StageArgs a) {
   }
 }
 
+// One staged half tile (128 rows of float32 at src, row pitch EP_LD, 8 columns per lane, RS rows
+// apart per lane group) gets c_last x (itself, rounded as a stored level when ROUND) plus
+// w_l x level l of the same tile for l = 1..J, read from global memory (lb: this lane's first
+// element of level 1; levels lv_stride bytes apart, rows 2 hp bytes apart). UR row groups per
+// pass and levels four at a time: UR x 4 16-byte loads in flight per lane.
+template <int UR, bool ROUND>
+__device__ __forceinline__ void fold_levels(float *src, gptr<const char> lb, const float *wl, int J, int64_t hp,
+                                            int64_t lv_stride, float c_last, float f_store) {
+  constexpr int RS = NT / 32, UL = 4;
+  for (int it = 0; it < 128 / RS; it += UR) {
+    float v[UR][8];
+#pragma unroll
+    for (int u = 0; u < UR; u++) {
+      const float4 a = *(const float4 *)(src + (it + u) * RS * EP_LD);
+      const float4 b = *(const float4 *)(src + (it + u) * RS * EP_LD + 4);
+      const float x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int e = 0; e < 8; e++) v[u][e] = ROUND ? c_last * bf16_value(f_store * x[e]) : c_last * x[e];
+    }
+    for (int l0 = 1; l0 <= J; l0 += UL) {
+      uint4 q[UR][UL];
+#pragma unroll
+      for (int u = 0; u < UR; u++)
+#pragma unroll
+        for (int k = 0; k < UL; k++)
+          q[u][k] = l0 + k <= J ? gld_u4(lb + (int64_t)uni((it + u) * RS) * hp * 2 + (int64_t)(l0 + k - 1) * lv_stride)
+                                : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int k = 0; k < UL; k++) {
+        const float w = l0 + k <= J ? wl[l0 + k] : 0.f;
+#pragma unroll
+        for (int u = 0; u < UR; u++) {
+          const uint32_t qw[4] = {q[u][k].x, q[u][k].y, q[u][k].z, q[u][k].w};
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            v[u][2 * e] += w * __uint_as_float(qw[e] << 16);
+            v[u][2 * e + 1] += w * __uint_as_float(qw[e] & 0xffff0000u);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UR; u++) {
+      *(float4 *)(src + (it + u) * RS * EP_LD) = make_float4(v[u][0], v[u][1], v[u][2], v[u][3]);
+      *(float4 *)(src + (it + u) * RS * EP_LD + 4) = make_float4(v[u][4], v[u][5], v[u][6], v[u][7]);
+    }
+  }
+}
+
 // Last squaring with the aggregation folded in (level layout): instead of storing level J + 1,
 // the tile of P = c_{J+1} S_{J+1} L_{J+1} + sum_{l <= J} c_l S_l L_l is formed from the float32
 // accumulators (c_last = c_{J+1} S_J^2 times acc is the first term; the stored level would be
@@ -883,49 +932,18 @@ __device__ __forceinline__ void store_p_fused(const f32x16 (&acc)[FM][FN], char 
   const bool diag = task.tm == task.tn;
   const int64_t hp = P.hp;
   uint16_t *dst = (uint16_t *)((char *)P.lv + (int64_t)J * P.lv_stride);
-  constexpr int RS = NT / 64;  // rows per iteration; a wave reads one staged row
-  const int row0 = threadIdx.x >> 6, c4 = (threadIdx.x & 63) * 4;
+  const int row0 = threadIdx.x >> 5, c8 = (threadIdx.x & 31) * 8;  // 32 lanes per staged row
+  // unrolled, so that the accumulators are dead while the second half is folded
+#pragma unroll
   for (int half = 0; half < 2; half++) {
     stage_half(acc, ep, half);
     __syncthreads();
-    float *src = ep + row0 * EP_LD + c4;
-    gptr<const char> lb = gbl((const char *)P.lv + ((int64_t)(m0 + half * 128 + row0) * hp + n0 + c4) * 2);
-    // two row groups per pass, levels four at a time: up to eight 8-byte loads in flight
-    constexpr int UR = 2, UL = 4;
-    for (int it = 0; it < 128 / RS; it += UR) {
-      float4 v[UR];
-#pragma unroll
-      for (int u = 0; u < UR; u++) {
-        v[u] = *(const float4 *)(src + (it + u) * RS * EP_LD);
-        if constexpr (ROUND)
-          v[u] = make_float4(c_last * bf16_value(f_store * v[u].x), c_last * bf16_value(f_store * v[u].y),
-                             c_last * bf16_value(f_store * v[u].z), c_last * bf16_value(f_store * v[u].w));
-        else
-          v[u] = make_float4(c_last * v[u].x, c_last * v[u].y, c_last * v[u].z, c_last * v[u].w);
-      }
-      for (int l0 = 1; l0 <= J; l0 += UL) {
-        uint2 q[UR][UL];
-#pragma unroll
-        for (int u = 0; u < UR; u++)
-#pragma unroll
-          for (int k = 0; k < UL; k++)
-            q[u][k] = l0 + k <= J ? gld_u2(lb + (int64_t)uni((it + u) * RS) * hp * 2 + (int64_t)(l0 + k - 1) * P.lv_stride)
-                                  : make_uint2(0, 0);
-#pragma unroll
-        for (int k = 0; k < UL; k++) {
-          const float w = l0 + k <= J ? wl[l0 + k] : 0.f;
-#pragma unroll
-          for (int u = 0; u < UR; u++) {
-            v[u].x += w * __uint_as_float(q[u][k].x << 16);
-            v[u].y += w * __uint_as_float(q[u][k].x & 0xffff0000u);
-            v[u].z += w * __uint_as_float(q[u][k].y << 16);
-            v[u].w += w * __uint_as_float(q[u][k].y & 0xffff0000u);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UR; u++) *(float4 *)(src + (it + u) * RS * EP_LD) = v[u];
-    }
+    float *src = ep + row0 * EP_LD + c8;
+    gptr<const char> lb = gbl((const char *)P.lv + ((int64_t)(m0 + half * 128 + row0) * hp + n0 + c8) * 2);
+    // two row groups per pass; in the e4m3 squaring (more registers live) one while the second
+    // half's accumulators are still held (measured faster there)
+    if (ROUND && half == 0) fold_levels<1, ROUND>(src, lb, wl, J, hp, P.lv_stride, c_last, f_store);
+    else fold_levels<2, ROUND>(src, lb, wl, J, hp, P.lv_stride, c_last, f_store);
     __syncthreads();
     if (split_p) emit_operand<true>(ep, dst, hp, m0, n0, half, diag);  // [P_hi | P_lo], slots J and J + 1
     else emit_sym_bf16(ep, dst, hp, m0, n0, half, diag, [](float v, int, int) { return v; });
