@@ -161,6 +161,46 @@ def test_single_power_batched_multitile(tdev, j):
         assert np.array_equal(Y0, Y1)
 
 
+# weighted fold: every power 2^0 .. 2^J of the multi-tile inputs with a weight of its own, so
+# that the last squaring's fold reads each stored level (J >= 5 takes a second pass of its
+# four-level loop). Bound: three to four times what the bf16 storage-point model gives on the
+# same inputs (3.8e-3 .. 4.2e-3 for J = 4, 5, 6; tests/test_oracle_bounds.py recomputes it).
+# Dropping one level's term or swapping two neighbouring weights moves P by 0.32 or more.
+TOL_BF16_FOLD = 1.5e-2
+FOLD_J = [4, 5, 6]
+
+
+def fold_terms(J):
+    """Exponents 0, 1, 2, 4, .., 2^J and weights 0 (no identity term, so the right block of Y is
+    alpha P), then (-1)^k (1 + k / 4) for 2^k."""
+    exps = (0,) + tuple(1 << k for k in range(J + 1))
+    return exps, (0.0,) + tuple((-1) ** k * (1.0 + 0.25 * k) for k in range(J + 1))
+
+
+@pytest.mark.parametrize("J", FOLD_J)
+def test_weighted_fold_batched_multitile(tdev, J):
+    """The bf16 Gram-basis plan over MULTI_TILE with every power weighted: the sum P that the
+    last squaring forms from its own product and the J stored levels, against the oracle's."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    exps, coeffs = fold_terms(J)
+    ins = [multi_tile_input(h, tall) for h, tall in MULTI_TILE]
+    shapes = [v.shape for v, _ in ins]
+    print(f"case weighted fold J={J} shapes {shapes}", flush=True)
+    Ms = [torch.from_numpy(v.astype(np.float32)).to(dev).to(torch.bfloat16) for v, _ in ins]
+    plan = ifn.Plan(exps, coeffs, shapes, norm="none", compute="bf16", out_dtype=ifn.F32)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.full(s, float("nan"), dtype=torch.float32, device=dev) for s in shapes]
+    plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    for (h, tall), (v, alpha), Y in zip(MULTI_TILE, ins, Ys):
+        Y = Y.cpu().numpy().astype(np.float64)
+        P = oracle.ifnso_parts(v, exps, coeffs, "gram", "none")["P"]
+        r = _rel((Y.T if tall else Y)[:, h:] / alpha, P)
+        print(f"  h={h} tall={tall} J={J}: rel {r:.2e}")
+        assert r <= TOL_BF16_FOLD
+
+
 @pytest.mark.parametrize("h", [256, 192])
 @pytest.mark.parametrize("j", [0, 1, 2, 3, 4])
 def test_single_power_e4m3(tdev, h, j):

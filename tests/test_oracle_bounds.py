@@ -157,6 +157,37 @@ def test_stage_bounds():
     _within(TG.TOL_BF16_POWER, worst["power"])
 
 
+def test_fold_bound():
+    """The weighted-fold bound of tests/test_gpu_stages.py (every power up to 2^J weighted, the
+    multi-tile inputs), and that it separates a fold that misreads a level: dropping any stored
+    level's term, or swapping two neighbouring weights, moves P by far more than the bound."""
+    worst = 0.0
+    for J in TG.FOLD_J:
+        exps, c = TG.fold_terms(J)
+        for h, tall in TG.MULTI_TILE:
+            v, alpha = TG.multi_tile_input(h, tall)
+            P = oracle.ifnso_parts(v, exps, c, "gram", "none")["P"]
+            Y = BM.gram_levels(v, exps, c, "none", out_bf16=False)
+            worst = max(worst, _rel((Y.T if tall else Y)[:, h:] / alpha, P))
+    _within(TG.TOL_BF16_FOLD, worst)
+    h, tall = TG.MULTI_TILE[0]
+    v, _ = TG.multi_tile_input(h, tall)
+    for J in TG.FOLD_J:
+        exps, c = TG.fold_terms(J)
+        P = oracle.ifnso_parts(v, exps, c, "gram", "none")["P"]
+        wrong = []
+        for k in range(1, J + 1):
+            cc = list(c)
+            cc[k] = 0.0
+            wrong.append(cc)
+        for k in range(1, J):
+            cc = list(c)
+            cc[k], cc[k + 1] = cc[k + 1], cc[k]
+            wrong.append(cc)
+        for cc in wrong:
+            assert _rel(oracle.ifnso_parts(v, exps, cc, "gram", "none")["P"], P) > 10 * TG.TOL_BF16_FOLD
+
+
 def _golden(golden_dir):
     with open(os.path.join(golden_dir, "bf16_bounds.json")) as f:
         return json.load(f)
