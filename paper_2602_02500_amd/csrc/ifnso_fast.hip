@@ -1257,22 +1257,24 @@ __global__ __launch_bounds__(NT, 1) void kf_product(const StageArgs a, const int
       else
         mainloop<false, true>(acc, smem, Po, m0, Mo, n0, Kp, false);
     }
-    // each thread owns one 8-column chunk of RS rows apart; row offsets are uniform additions
+    // each thread owns one 8-column chunk of RS rows apart; row offsets are uniform additions.
+    // The half tile's M reads are issued before its staging, so they land during it.
     constexpr int RS = NT / 32, PER = 128 / RS;
     const int row0 = threadIdx.x >> 5, c8 = (threadIdx.x & 31) * 8;
     const int c = n0 + c8;
     const bool cin = c < cols_out;
+#pragma unroll
     for (int half = 0; half < 2; half++) {
-      stage_half(acc, ep, half);
-      __syncthreads();
       const int r0 = m0 + half * 128 + row0;
       gptr<const uint16_t> mp = gbl((const uint16_t *)P.M) + (int64_t)r0 * P.ldm + c;
-      const float *src = ep + row0 * EP_LD + c8;
       uint4 xm[PER];
 #pragma unroll
       for (int u = 0; u < PER; u++)
         xm[u] = (cin && r0 + u * RS < rows_out) ? gld_u4(mp + (int64_t)uni(u * RS) * P.ldm)
                                                  : make_uint4(0, 0, 0, 0);
+      stage_half(acc, ep, half);
+      __syncthreads();
+      const float *src = ep + row0 * EP_LD + c8;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
         if (!cin || r0 + u * RS >= rows_out) continue;
