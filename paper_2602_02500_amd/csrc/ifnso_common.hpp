@@ -57,7 +57,8 @@ struct ProbDev {
   // raised by atomic maxima (every value is >= 0), zeroed when A is quantised
   uint64_t *qrmax;
   // sums of squares of the codes of A's e4m3 copy per row and chunk, [i * qnch + c], written
-  // by the input quantisation (chunks: 4096 columns for wide inputs, 64 for tall ones)
+  // by the input quantisation (chunks: 1024 columns for wide inputs, one per wave; 64 for tall
+  // ones)
   double *qrow_in;
   int32_t qnch;
   double *q_part;      // [nq] pre-pass sums of squares of M, chunks of rq storage rows

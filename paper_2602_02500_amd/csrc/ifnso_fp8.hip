@@ -80,19 +80,48 @@ __global__ __launch_bounds__(kThreads) void k_prepass(const StageArgs a) {
     double ss = 0.0;
     float mx = 0.f;
     if (vec) {
+      // 8-element groups, kThreads apart in row-major order; each thread keeps the (row, group)
+      // of its kU slots and advances them without a division, and issues the kU 16-byte loads
+      // of an iteration before using them
+      constexpr int kU = 4;
       const int gpr = cols / 8;  // 8-element groups per row
-      const int64_t ng = (int64_t)(r1 - r0) * gpr;
-      for (int64_t g = threadIdx.x; g < ng; g += kThreads) {
-        const int r = r0 + (int)(g / gpr), k = (int)(g % gpr) * 8;
-        float x[8];
-        unpack8(*(const uint4 *)(M + (int64_t)r * P.ldm + k), x);
-        float s8 = 0.f;  // squares of bfloat16 values are exact in float32
+      const int ng = (r1 - r0) * gpr;  // below kQElems / 8 + cols / 8
+      const int dr = kU * kThreads / gpr, dk = kU * kThreads % gpr;
+      int rr[kU], kk[kU];
+      rr[0] = r0 + (int)threadIdx.x / gpr;
+      kk[0] = (int)threadIdx.x % gpr;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-          s8 = fmaf(x[i], x[i], s8);
-          mx = fmaxf(mx, fabsf(x[i]));
+      for (int u = 1; u < kU; u++) {
+        rr[u] = rr[u - 1] + kThreads / gpr;
+        kk[u] = kk[u - 1] + kThreads % gpr;
+        if (kk[u] >= gpr) {
+          kk[u] -= gpr;
+          rr[u]++;
         }
-        ss += (double)s8;
+      }
+      for (int g = threadIdx.x; g < ng; g += kU * kThreads) {
+        uint4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+          v[u] = g + u * kThreads < ng ? *(const uint4 *)(M + (int64_t)rr[u] * P.ldm + kk[u] * 8) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+          float x[8];
+          unpack8(v[u], x);
+          float s8 = 0.f;  // squares of bfloat16 values are exact in float32
+#pragma unroll
+          for (int i = 0; i < 8; i++) {
+            s8 = fmaf(x[i], x[i], s8);
+            mx = fmaxf(mx, fabsf(x[i]));
+          }
+          ss += (double)s8;
+          rr[u] += dr;
+          kk[u] += dk;
+          if (kk[u] >= gpr) {
+            kk[u] -= gpr;
+            rr[u]++;
+          }
+        }
       }
     } else {
       const int64_t n = (int64_t)(r1 - r0) * cols;
@@ -147,22 +176,25 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
   const int64_t ldq = P.ldq;
   const int gpr = (int)(ldq / 16);  // 16-element groups per row of q8
   if (!P.trans) {
-    // one workgroup per chunk of kThreads 16-element groups of a row (the chunk's sum of
-    // squares of the codes goes to qrow_in when the plan keeps it)
+    // one wave per chunk of 64 16-element groups (1024 columns of q8) of a row; the chunk's sum
+    // of squares of the codes (exact in float64, summed over the wave in a fixed order) goes to
+    // qrow_in when the plan keeps it. No barrier: each wave moves on by itself.
     const bool vec = P.vecM && (w % 8) == 0;
-    const int nch = (gpr + kThreads - 1) / kThreads;
-    for (int64_t u = blockIdx.x; u < (int64_t)h * nch; u += gridDim.x) {
-      const int i = (int)(u / nch), c = (int)(u % nch);
-      const int g = c * kThreads + threadIdx.x, k = g * 16;
+    const int nch = (gpr + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int64_t units = (int64_t)h * nch, wstep = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t u = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); u < units; u += wstep) {
+      const int i = (int)(u / nch), c = (int)(u - (int64_t)i * nch);
+      const int g = c * 64 + lane, k = g * 16;
       double ss = 0.0;
       if (g < gpr) {
         const uint16_t *src = M + (int64_t)i * P.ldm + k;
         float x[16];
         if (vec) {
-          if (k < w) unpack8(*(const uint4 *)src, x);
-          else for (int j = 0; j < 8; j++) x[j] = 0.f;
-          if (k + 8 < w) unpack8(*(const uint4 *)(src + 8), x + 8);
-          else for (int j = 8; j < 16; j++) x[j] = 0.f;
+          const uint4 v0 = k < w ? *(const uint4 *)src : make_uint4(0, 0, 0, 0);
+          const uint4 v1 = k + 8 < w ? *(const uint4 *)(src + 8) : make_uint4(0, 0, 0, 0);
+          unpack8(v0, x);
+          unpack8(v1, x + 8);
         } else {
 #pragma unroll
           for (int j = 0; j < 16; j++) x[j] = k + j < w ? bf16_to_f32(src[j]) : 0.f;
@@ -172,9 +204,9 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
         ss = sumsq_e4m3(q.x) + sumsq_e4m3(q.y) + sumsq_e4m3(q.z) + sumsq_e4m3(q.w);
       }
       if (P.qrow_in) {
-        double u0 = 0.0, u1 = 0.0;
-        block_sum3(ss, u0, u1, dscr);
-        if (threadIdx.x == 0) P.qrow_in[(int64_t)i * P.qnch + c] = ss;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+        if (lane == 0) P.qrow_in[(int64_t)i * P.qnch + c] = ss;
       }
     }
     return;

@@ -158,7 +158,7 @@ ProbLayout layout_problem(int64_t rows, int64_t cols, int op, int J, bool comple
     L.off_q8 = take((size_t)L.h * L.ldq);
     for (int i = 0; i < 2; i++) L.off_ql[i] = take(hh);
     L.off_qrmax = take((size_t)(kMaxLevels + 1) * 8);
-    L.qnch = (int32_t)(L.trans ? (L.ldq + 63) / 64 : (L.ldq / 16 + kThreads - 1) / kThreads);
+    L.qnch = (int32_t)(L.trans ? (L.ldq + 63) / 64 : (L.ldq / 16 + 63) / 64);  // see ProbDev::qrow_in
     L.off_qrow_in = take((size_t)L.h * L.qnch * 8);
     L.off_qpart = take((size_t)L.nq * 8);
     L.off_qamax = take((size_t)L.nq * 4);
@@ -626,7 +626,9 @@ extern "C" ifnso_status ifnso_plan(const ifnso_poly_desc *desc, int32_t num_prob
     int need[3] = {1, 1, 1};
     for (const ProbLayout &L : p->lay) {
       need[0] = std::max(need[0], L.nq);
-      const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64) : (int64_t)L.h * L.qnch;
+      // tall: 64 x 64 tiles; wide: row chunks, one per wave (kThreads / 64 per workgroup)
+      const int64_t units_in = L.trans ? (int64_t)((L.h + 63) / 64) * ((L.ldq + 63) / 64)
+                                       : ((int64_t)L.h * L.qnch + kThreads / 64 - 1) / (kThreads / 64);
       need[1] = (int)std::max<int64_t>(need[1], units_in);
       need[2] = std::max(need[2], (L.hp + kQRowsPerBlock - 1) / kQRowsPerBlock);  // row-maxima blocks
     }
@@ -1449,7 +1451,8 @@ extern "C" ifnso_status ifnso_quantize_e4m3(const void *M, int64_t rows, int64_t
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   const int cus = dev_cus(dev);
-  const int64_t units_in = d.trans ? ((h + 63) / 64) * ((ldq + 63) / 64) : (h * ldq / 16 + kThreads - 1) / kThreads;
+  const int64_t units_in = d.trans ? ((h + 63) / 64) * ((ldq + 63) / 64)
+                                   : (h * ((ldq / 16 + 63) / 64) + kThreads / 64 - 1) / (kThreads / 64);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_e4m3_pass(kE4m3Prepass, a, 1, std::max(1, std::min(ql.nq, 8 * cus)), s));
   HIP_TRY(launch_e4m3_pass(kE4m3QuantInput, a, 1, (int)std::max<int64_t>(1, std::min<int64_t>(units_in, 8 * cus)), s));

@@ -68,8 +68,10 @@ def _run(torch, dev, vals_list, Ms, exps, c, norm="frobenius", out="f32", comput
 # ---------------------------------------------------------------------------------------------
 # input quantiser
 # ---------------------------------------------------------------------------------------------
+# the wide rows of the last two cross the 1024-column chunks of the quantiser (one per wave),
+# the last chunk ragged; the pre-pass takes several rows per chunk
 QSHAPES = [(256, 512, 0, 0), (640, 384, 0, 0), (100, 203, 0, 0), (300, 97, 0, 0), (64, 96, 5, 32),
-           (130, 72, 8, 16), (1, 40, 0, 0), (45, 1, 0, 0)]
+           (130, 72, 8, 16), (1, 40, 0, 0), (45, 1, 0, 0), (96, 2504, 8, 16), (70, 3000, 0, 0)]
 
 
 @pytest.mark.parametrize("rows,cols,ld_pad,q_pad", QSHAPES)
@@ -116,7 +118,7 @@ def test_quantize_zero_matrix(tdev):
 # ---------------------------------------------------------------------------------------------
 # whole plans
 # ---------------------------------------------------------------------------------------------
-PSHAPES = [(256, 512), (512, 256), (384, 640), (200, 456), (520, 264)]
+PSHAPES = [(256, 512), (512, 256), (384, 640), (200, 456), (520, 264), (160, 2312)]
 
 
 @pytest.mark.parametrize("shape", PSHAPES)
