@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_quant_input(const StageArgs a) {
 
 // ---------------------------------------------------------------------------------------------
 // largest row sum of squares of an e4m3 operand (its codes): of level a.level's copy (hp x hp;
-// a wave takes one row at a time, 16 bytes per lane, with float64 partials summed over the wave
+// a wave takes four rows at a time, 16 bytes per lane, with float64 partials summed over the wave
 // in a fixed order) or, for level 0, of A (from the chunk sums the quantisation wrote); the
 // workgroup's maximum goes into qrmax[a.level] as an atomic maximum of the float64 bit pattern
 // (every value is >= 0, so the patterns order as the values and the result does not depend on
@@ -282,15 +282,27 @@ __global__ __launch_bounds__(kThreads) void k_row_max(const StageArgs a) {
   const int64_t ld = P.hp;  // a multiple of 16 bytes
   for (int r0 = blockIdx.x * kQRowsPerBlock; r0 < rows; r0 += gridDim.x * kQRowsPerBlock) {
     const int r1 = min(rows, r0 + kQRowsPerBlock);
-    for (int r = r0 + wave; r < r1; r += kThreads / 64) {
-      double s = 0.0;
+    // kR rows per wave pass: their loads are issued together and their wave sums interleave
+    constexpr int kR = 4;
+    for (int r = r0 + wave * kR; r < r1; r += (kThreads / 64) * kR) {
+      double s[kR];
+#pragma unroll
+      for (int j = 0; j < kR; j++) s[j] = 0.0;
       for (int64_t k = (int64_t)lane * 16; k < ld; k += 64 * 16) {
-        const uint4 v = *(const uint4 *)(q + (int64_t)r * ld + k);
-        s += sumsq_e4m3(v.x) + sumsq_e4m3(v.y) + sumsq_e4m3(v.z) + sumsq_e4m3(v.w);
+        uint4 v[kR];
+#pragma unroll
+        for (int j = 0; j < kR; j++)
+          v[j] = r + j < r1 ? *(const uint4 *)(q + (int64_t)(r + j) * ld + k) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < kR; j++)
+          s[j] += sumsq_e4m3(v[j].x) + sumsq_e4m3(v[j].y) + sumsq_e4m3(v[j].z) + sumsq_e4m3(v[j].w);
       }
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      mx = fmax(mx, s);
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < kR; j++) s[j] += __shfl_xor(s[j], off, 64);
+#pragma unroll
+      for (int j = 0; j < kR; j++) mx = fmax(mx, s[j]);  // rows past r1 add zero sums
     }
   }
 #pragma unroll
