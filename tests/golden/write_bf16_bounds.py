@@ -23,6 +23,9 @@ from workloads import configs, gen  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bf16_bounds.json")
 D4_SAMPLED = [0, 21, 42, 63]
+# (layer, index) of the gradient-set matrices the full-size test samples: Wq and Wk of layer 0,
+# gate (tall) and down (wide) of layer 31
+D3_SAMPLED = [(0, 0), (0, 1), (31, 4), (31, 6)]
 
 
 def _rel(a, b):
@@ -50,8 +53,18 @@ def d4_case(i):
     return _rel(Ym, oracle.closed_form(U, sigma, V, exps, c)), _rel(Ym, oracle.ifnso(Mb, exps, c))
 
 
+def d3_case(layer, index):
+    """One matrix of the gradient set (numpy twin of the device generator, rounded to bf16)
+    through the bf16 Gram-basis plan (gform_v1), against the polynomial of the same input."""
+    exps, c = configs.load_coeffs("gform_v1")
+    _, rows, cols = configs.LAYER_SHAPES[index]
+    Mb = gen.round_to_bf16_np(gen.lowrank_plus_noise_np(rows, cols, configs.d3_seed(layer, index)))
+    return _rel(BM.gram_levels(Mb, exps, c), oracle.ifnso(Mb, exps, c))
+
+
 def main():
-    out = {"d2_schedule_muon_ns5": {}, "d4_gform_v1_closed": {}, "d4_gform_v1_oracle": {}}
+    out = {"d2_schedule_muon_ns5": {}, "d4_gform_v1_closed": {}, "d4_gform_v1_oracle": {},
+           "d3_gform_v1_oracle": {}}
     for rows, cols, seed in [(4096, 4096, 1), (14336, 4096, 2)]:
         out["d2_schedule_muon_ns5"][f"{rows}x{cols}"] = d2_schedule_case(rows, cols, seed)
         print(rows, cols, out["d2_schedule_muon_ns5"][f"{rows}x{cols}"], flush=True)
@@ -60,6 +73,9 @@ def main():
         out["d4_gform_v1_closed"][str(i)] = rc
         out["d4_gform_v1_oracle"][str(i)] = ro
         print(i, rc, ro, flush=True)
+    for layer, index in D3_SAMPLED:
+        out["d3_gform_v1_oracle"][f"{layer}/{index}"] = d3_case(layer, index)
+        print(layer, index, out["d3_gform_v1_oracle"][f"{layer}/{index}"], flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
         f.write("\n")

@@ -200,6 +200,8 @@ def test_fullsize_bounds_from_golden(golden_dir):
     _within(TF.TOL_D4_ORACLE, g["d4_gform_v1_oracle"]["0"])
     # the closed-form bound is the path's 2e-2; the model stays under a third of it
     assert 3.0 * max(g["d4_gform_v1_closed"].values()) <= TF.TOL_D4_CLOSED
+    assert set(g["d3_gform_v1_oracle"]) == {f"{l}/{i}" for l, i in TF.D3_SAMPLED}
+    _within(TF.TOL_D3_ORACLE, max(g["d3_gform_v1_oracle"].values()))
 
 
 @pytest.mark.slow
