@@ -8,9 +8,9 @@ this size.
 Bounds: float32 path 1e-4. bfloat16 path 2e-2; it includes the bfloat16 rounding of the input
 (about 1e-3 relative in the output, since the polynomial is close to linear at these sigma~).
 
-Also at full size: the heavy-tailed batch of the e4m3 workload through the bf16 path, and the
-benchmark's gradient set (224 matrices) in the benchmark's launch configuration, each with
-sampled matrices against the oracle."""
+Also at full size: the heavy-tailed batch of the e4m3 workload through the bf16 and the e4m3
+path, and the benchmark's gradient set (224 matrices) in the benchmark's launch configuration,
+each with sampled matrices against the oracle."""
 import numpy as np
 import pytest
 
@@ -147,6 +147,41 @@ def test_heavy_tailed_batch_bf16(tdev):
     r = _rel(Ys[0].double().cpu().numpy(), oracle.ifnso(vals, exps, c))
     print(f"  matrix 0: rel vs the polynomial of its rounded input {r:.3e}")
     assert r <= TOL_D4_ORACLE
+
+
+# the same batch through the e4m3 plan, as the e4m3 benchmark runs it; bound: the e4m3 plans'
+# 1e-2 against the oracle's e4m3 model with bf16 output (tests/test_gpu_fp8.py)
+D4_E4M3_SAMPLED = [0, 63]
+TOL_D4_E4M3_MODEL = 1e-2
+
+
+def test_heavy_tailed_batch_e4m3(tdev):
+    """The 64 matrices 2048x8192 of the e4m3 workload through one e4m3 plan (e4m3 Gram and
+    squarings with per-tensor scales, bf16 product and output) in one batched call; sampled
+    matrices against the oracle's e4m3 model of the same input (the same quantisation points,
+    float64 elsewhere)."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    from oracle import fp8 as F
+    exps, c = configs.load_coeffs("gform_v1")
+    rows, cols = configs.D4_SHAPE
+    sigma = configs.d4_sigma(min(rows, cols))
+    Ms = []
+    for i in range(configs.D4_BATCH):
+        M, U, V = gen.spectral_torch(rows, cols, sigma, configs.d4_seed(i), device=dev)
+        Ms.append(gen.round_to_bf16_torch(M))
+        del M, U, V
+    print(f"case e4m3 batch {len(Ms)} x {rows}x{cols}", flush=True)
+    plan = ifn.Plan(exps, c, [(rows, cols)] * len(Ms), compute="fp8")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    for i in D4_E4M3_SAMPLED:
+        vals = Ms[i].double().cpu().numpy()
+        r = _rel(Ys[i].double().cpu().numpy(), F.ifnso_e4m3(vals, exps, c))
+        print(f"  matrix {i}: rel vs the e4m3 model {r:.3e}")
+        assert r <= TOL_D4_E4M3_MODEL, (i, r)
 
 
 # the gradient set, as the benchmark runs it
