@@ -10,7 +10,7 @@ Bounds: float32 path 1e-4. bfloat16 path 2e-2; it includes the bfloat16 rounding
 
 Also at full size: the heavy-tailed batch of the e4m3 workload through the bf16 and the e4m3
 path, and the benchmark's gradient set (224 matrices) in the benchmark's launch configuration,
-each with sampled matrices against the oracle."""
+in the Gram basis and in the paper's form, each with sampled matrices against the oracle."""
 import numpy as np
 import pytest
 
@@ -225,3 +225,40 @@ def test_gradient_set_full_size(tdev):
         r = _rel(Ys[k].double().cpu().numpy(), oracle.ifnso(vals, exps, c))
         print(f"  layer {layer} {configs.LAYER_SHAPES[idx][0]} {vals.shape}: rel vs the polynomial {r:.3e}")
         assert r <= TOL_D3_ORACLE, (layer, idx, r)
+
+
+# the paper's form (complement basis, depth 14, split bf16) on the gradient set, as its benchmark
+# runs it (bf16 output). Bound: the split path's 3e-3 with float32 output (tests/test_gpu_split.py)
+# plus 2^-9, the largest relative change that rounding the output to bf16 can add.
+TFORM_SAMPLED = [(0, 0), (0, 1)]  # Wq, Wk of layer 0
+TOL_TFORM_BF16_OUT = 3e-3 + 2.0 ** -9
+
+
+def test_gradient_set_paper_form_full_size(tdev):
+    """The 224 matrices of the gradient set through one complement-basis plan at depth 14 with
+    split bf16 operands and bf16 output, in one batched call; layer 0's Wq and Wk against the
+    float64 oracle of the same form."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    exps, c = configs.load_coeffs("paper_L14")
+    Ms = []
+    for layer in range(32):
+        for idx, (_, r, cc) in enumerate(configs.LAYER_SHAPES):
+            m = gen.lowrank_plus_noise_torch(r, cc, configs.d3_seed(layer, idx), device=dev)
+            Ms.append(gen.round_to_bf16_torch(m))
+            del m
+    shapes = [tuple(m.shape) for m in Ms]
+    print(f"case gradient set, paper form: {len(Ms)} matrices", flush=True)
+    plan = ifn.Plan(exps, c, shapes, basis="complement", norm="gram_frobenius", compute="bf16",
+                    flags=ifn.FLAG_SPLIT_BF16)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    Ys = [torch.empty_like(m) for m in Ms]
+    plan.orthogonalize_batched(Ms, Ys, ws)
+    torch.cuda.synchronize()
+    for layer, idx in TFORM_SAMPLED:
+        k = layer * len(configs.LAYER_SHAPES) + idx
+        vals = Ms[k].double().cpu().numpy()
+        Yo = oracle.ifnso(vals, exps, c, "complement", "gram_frobenius")
+        r = _rel(Ys[k].double().cpu().numpy(), Yo)
+        print(f"  layer {layer} {configs.LAYER_SHAPES[idx][0]} {vals.shape}: rel vs the oracle {r:.3e}")
+        assert r <= TOL_TFORM_BF16_OUT, (layer, idx, r)
