@@ -160,3 +160,42 @@ def test_learned_plan_in_the_loop(tdev):
         print(f"{shapes[i]} learned: momentum rel {rb:.1e}, weight change rel {rw:.2e}, c = {np.round(c_dev, 3)}")
         assert rb <= 1e-6
         assert rw <= 2e-2
+
+
+MUON_SAMPLED = [(0, 0), (0, 1), (31, 4)]  # Wq, Wk of layer 0; gate of layer 31
+
+
+def test_step_on_gradient_set_full_size(tdev):
+    """One Nesterov Muon step over the 224 matrices of the gradient set (the Muon benchmark's
+    shapes, gradients and hyperparameters; the momentum starts from a seeded nonzero state), in
+    one call; sampled matrices against the oracle's step with the bounds above."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    exps, c = configs.load_coeffs("gform_v1")
+    lr, mu, wd = 0.02, 0.95, 0.01
+    Ws, Gs, Bs, shapes = [], [], [], []
+    for layer in range(32):
+        for idx, (_, r, cc) in enumerate(configs.LAYER_SHAPES):
+            i = len(Ws)
+            Ws.append(gen.gaussian_torch(r, cc, 5000 + i, 0, 0.02, device=dev).float())
+            m = gen.lowrank_plus_noise_torch(r, cc, configs.d3_seed(layer, idx), device=dev)
+            Gs.append(gen.round_to_bf16_torch(m))
+            del m
+            Bs.append(gen.gaussian_torch(r, cc, 6000 + i, 0, 0.01, device=dev).float())
+            shapes.append((r, cc))
+    per_layer = len(configs.LAYER_SHAPES)
+    host = {k: (Ws[k].double().cpu().numpy(), Gs[k].double().cpu().numpy(), Bs[k].double().cpu().numpy())
+            for k in (layer * per_layer + idx for layer, idx in MUON_SAMPLED)}
+    print(f"case Muon step, gradient set: {len(Ws)} matrices", flush=True)
+    plan = ifn.Plan(exps, c, shapes, compute="bf16")
+    ws = torch.empty(plan.muon_workspace_bytes, dtype=torch.uint8, device=dev)
+    plan.muon_step(Ws, Gs, Bs, ws, lr, mu, wd, True)
+    torch.cuda.synchronize()
+    for k, (W0, G, B0) in host.items():
+        W1o, B1o, _ = MU.muon_step(W0, G, B0, exps, c, lr, mu, wd, True, round_input=F.bf16_round)
+        W1 = Ws[k].cpu().numpy().astype(np.float64)
+        B1 = Bs[k].cpu().numpy().astype(np.float64)
+        rb, rw = _rel(B1, B1o), _rel(W1 - W0, W1o - W0)
+        print(f"  matrix {k} {shapes[k]}: momentum rel {rb:.1e}, weight change rel {rw:.2e}")
+        assert rb <= 1e-6
+        assert rw <= 2e-2
