@@ -405,6 +405,7 @@ def run_e4m3(args, torch, dev, hip, log):
             relm.append(float(np.linalg.norm(y8 - Ym) / np.linalg.norm(Ym)))
         extra["rel_err_vs_fp64_oracle"] = {"e4m3": rel8, "bf16": relb, "e4m3_vs_e4m3_model": relm}
         cpu = {"value": len(idx) / dt, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
+               "cpu_model": _cpu_model(),
                "sample": f"{len(idx)} matrices of the batch (2048x8192), float64 numpy, {dt:.1f} s"}
     line = {
         "metric": "matrices/s on the e4m3 workload; ||Y - Y_fp64|| vs FP64 oracle",
@@ -883,6 +884,7 @@ def cpu_baseline_table1(methods, inputs):
     dt = time.perf_counter() - t0
     calls = len(methods) * len(inputs)
     cpu = {"value": calls / dt, "unit": "matrices/s", "cores": _oracle_threads(), "kind": "oracle",
+           "cpu_model": _cpu_model(),
            "sample": f"all {calls} method x size cases of the table, float64 numpy, {dt:.2f} s"}
     return cpu, errs
 
