@@ -517,7 +517,8 @@ def run_tform(args, torch, dev, hip, log):
     X = A / ||AA^T||_F^(1/2), depth L = 14 (exponents 0, 1, 2, ..., 2^13: 13 squarings of the
     shifted power D = T - I), coefficients "paper_L14", bfloat16 compute with split (hi + lo)
     operands; `--unsplit` uses single bfloat16 operands instead. Reports throughput, the
-    orthogonality error on all matrices beside the Gram-basis form's, and the parity of layer
+    orthogonality error on all matrices beside the Gram-basis form's and beside the same form
+    through the float32 path (speed and error; `--no-f32` skips it), and the parity of layer
     0's two 1024x4096 matrices against the float64 oracle."""
     import numpy as np
 
@@ -571,6 +572,23 @@ def run_tform(args, torch, dev, hip, log):
     plan_g.orthogonalize_batched(Ms, Yg, ws)
     torch.cuda.synchronize()
     err_g = orth(Yg)
+    del Yg, ws, plan_g
+    # the same form through the plain float32 path (generic kernels, float32 operands): speed and
+    # orthogonality beside the bf16 path's, where the form does orthogonalise
+    f32 = None
+    if not args.no_f32:
+        M32 = [m.float() for m in Ms]
+        Y32 = [torch.empty_like(m) for m in M32]
+        plan32 = ifn.Plan(exps, coeffs, shapes, basis="complement", norm="gram_frobenius", compute="f32")
+        ws32 = torch.empty(plan32.workspace_bytes, dtype=torch.uint8, device=dev)
+        f32_steps = 2
+        t32 = time_plan(torch, hip, plan32, M32, Y32, ws32, None, f32_steps, 1, log, slots=False)["elapsed"]
+        t32 /= f32_steps
+        err32 = orth(Y32)
+        f32 = {"matrices_per_s": round(n / t32, 3), "speedup_bf16_over_f32": round(ms_per_step ** -1 * 1e3 * t32, 3),
+               "timed_steps": f32_steps, "warmup": 1, "orth_err_over_sqrt_h": err32,
+               "orth_err_mean_bf16_over_f32": round(err_t["mean"] / err32["mean"], 4)}
+        del M32, Y32, ws32, plan32
     line = {
         "metric": "paper form (complement basis, L = 14) on the 32-layer gradient set: matrices/s and "
                   "||YY^T - I||_F / sqrt(h)",
@@ -591,6 +609,7 @@ def run_tform(args, torch, dev, hip, log):
         "gram_basis_gform_v1_orth_err_over_sqrt_h": err_g,
         "parity_layer0_1024x4096_rel_vs_oracle": rel,
         "oracle_orth_err_over_sqrt_h_layer0_1024x4096": orth_o,
+        "f32_path": f32,
     }
     if args.layers == 32 and split:
         _attach_traffic(line, dom, "traffic_tform_gradset_224_bf16.json", TFORM_PROFILE_KERNEL)
