@@ -262,3 +262,39 @@ def test_gradient_set_paper_form_full_size(tdev):
         r = _rel(Ys[k].double().cpu().numpy(), Yo)
         print(f"  layer {layer} {configs.LAYER_SHAPES[idx][0]} {vals.shape}: rel vs the oracle {r:.3e}")
         assert r <= TOL_TFORM_BF16_OUT, (layer, idx, r)
+
+
+def test_paper_form_bf16_keeps_float32_orthogonality(tdev):
+    """One layer of the gradient set (seven matrices, all three shape classes) through the
+    paper's form in split bf16 and in float32: the bf16 path's ||YY^T - I||_F / sqrt(h) stays
+    within 10 % of the float32 path's on every matrix (the stated precision target; on the whole
+    set the two agree to 0.2 %). Unlike the Gram basis with the fixed coefficients, this form
+    does orthogonalise (errors 0.006 .. 0.14), so the comparison carries information."""
+    torch, dev = tdev
+    import paper_2602_02500_amd as ifn
+    exps, c = configs.load_coeffs("paper_L14")
+    Ms = []
+    for idx, (_, r, cc) in enumerate(configs.LAYER_SHAPES):
+        m = gen.lowrank_plus_noise_torch(r, cc, configs.d3_seed(0, idx), device=dev)
+        Ms.append(gen.round_to_bf16_torch(m))
+        del m
+    shapes = [tuple(m.shape) for m in Ms]
+    print(f"case paper form bf16 vs float32: {len(Ms)} matrices", flush=True)
+
+    def orth(plan, Xs):
+        Ys = [torch.empty_like(x) for x in Xs]
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        plan.orthogonalize_batched(Xs, Ys, ws)
+        out = torch.empty(len(Ys), dtype=torch.float64, device=dev)
+        ows = torch.empty(ifn.orth_error_workspace_bytes(len(Ys)), dtype=torch.uint8, device=dev)
+        ifn.orth_error(Ys, out, ows)
+        torch.cuda.synchronize()
+        return out.cpu().numpy() / np.sqrt([min(s) for s in shapes])
+
+    e16 = orth(ifn.Plan(exps, c, shapes, basis="complement", norm="gram_frobenius", compute="bf16",
+                        flags=ifn.FLAG_SPLIT_BF16), Ms)
+    e32 = orth(ifn.Plan(exps, c, shapes, basis="complement", norm="gram_frobenius", compute="f32"),
+               [m.float() for m in Ms])
+    for (name, _, _), a, b in zip(configs.LAYER_SHAPES, e16, e32):
+        print(f"  {name}: bf16 {a:.5f}, float32 {b:.5f}, ratio {a / b:.4f}")
+        assert abs(a / b - 1.0) <= 0.1, (name, a, b)
